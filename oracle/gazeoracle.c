@@ -1,0 +1,688 @@
+/*
+ * gazeoracle.c -- plain, slow CPU oracle for the gaze-line stereo graph cut
+ * (Oguri & Shibata, "A new stereo formulation not using pixel and disparity
+ * models").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file.  Only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark use it.  It shares no source with the HIP library.
+ *
+ * What it computes, all in 64-bit integers:
+ *   - the data-cost volume g(x, y, S) at every cross point   (Sec. 4.3, Sec. 3)
+ *   - the energy E(X) = sum_v g_v(X_v) + sum_(u,v) h~(X_u - X_v)  (Sec. 2, Sec. 3)
+ *   - the layered (Ishikawa) graph as an explicit arc list    (Sec. 3, Fig. 4)
+ *   - its exact max-flow by two unrelated textbook algorithms:
+ *       Dinic (BFS level graph + blocking flow) and
+ *       FIFO push-relabel with global relabelling (Sec. 4.4 cites this family)
+ *   - the canonical labelling: the minimal source side of the minimum cut
+ *   - brute-force enumeration of every labelling on tiny grids
+ *   - exact scanline dynamic programming for one-row images
+ *
+ * Geometry (Sec. 3, Sec. 4.1).  A site is a gaze line (x, y), x in [0,w),
+ * y in [0,h); a label is a depth number S in [0,m), S = 0 the front.  The
+ * cross point (x, S, y) joins left pixel xl = x - S + (m-1) and right pixel
+ * xr = x + S - (m-1) of row y, so disparity xl - xr = 2(m-1-S): one depth step
+ * is two pixels of disparity (Sec. 4.1).  A cross point whose pixels fall
+ * outside the image costs the truncation cap.
+ *
+ * Pairwise term (Sec. 3): h~(d) = h1*|d| + h2*(|d|-1)*T(|d|>1), h1 = penalty
+ * (smoothness), h2 = inhibit (visibility).  It is convex (Sec. 2, eq. (1)),
+ * so the energy is minimised exactly by one cut of the layered graph.
+ *
+ * Layered graph.  Per site v: nodes v_1..v_{m-1}, v_0 = s, v_m = t;
+ * "v_k on the source side" means X_v >= k.
+ *   chain     v_k -> v_{k+1}, cap g_v(k), k = 0..m-1  (cut iff X_v == k)
+ *             reverse v_{k+1} -> v_k, cap INF for 1 <= k <= m-2
+ *   level     u_k <-> v_k, cap h1 each way, k = 1..m-1
+ *   diagonal  u_{k+1} -> v_k and v_{k+1} -> u_k, cap h2, k = 1..m-2
+ * for every 4-neighbour pair (u, v) (Sec. 2), with per-direction (h1, h2).
+ * The cut induced by X has capacity exactly E(X).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_E_ARG -1
+#define ORC_E_NOMEM -2
+#define ORC_E_PREFIX -3   /* a column was cut more than once */
+#define ORC_E_TOO_BIG -4
+
+/* Larger than any cut value this oracle is asked about. */
+#define ORC_INF ((int64_t)1 << 52)
+
+/* ------------------------------------------------------------------------ */
+/* Data term: truncated absolute difference at each cross point.            */
+/* ------------------------------------------------------------------------ */
+
+/* cost[(S*h + y)*w + x] = min(|L(y, xl) - R(y, xr)|, cap), or cap when a
+ * pixel lies outside the image. */
+int orc_cost_volume(const uint8_t *left, const uint8_t *right, int w, int h,
+                    int m, int cap, int32_t *cost)
+{
+    if (w < 0 || h < 0 || m < 1 || cap < 0 || !cost) return ORC_E_ARG;
+    for (int S = 0; S < m; S++)
+        for (int y = 0; y < h; y++)
+            for (int x = 0; x < w; x++) {
+                int xl = x - S + (m - 1);
+                int xr = x + S - (m - 1);
+                int32_t g = cap;
+                if (xl >= 0 && xl < w && xr >= 0 && xr < w) {
+                    int d = (int)left[y * w + xl] - (int)right[y * w + xr];
+                    if (d < 0) d = -d;
+                    g = d < cap ? d : cap;
+                }
+                cost[((int64_t)S * h + y) * w + x] = g;
+            }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Energy, written out from its definition.                                  */
+/* ------------------------------------------------------------------------ */
+
+/* h~(d) = h1*|d| + h2*(|d|-1)*T(|d|>1)  (Sec. 3). */
+static int64_t pair_term(int64_t h1, int64_t h2, int d)
+{
+    int a = d < 0 ? -d : d;
+    return h1 * a + h2 * (int64_t)(a - 1) * (a > 1 ? 1 : 0);
+}
+
+int64_t orc_energy(const int32_t *cost, const int32_t *labels, int w, int h,
+                   int m, int pen_h, int inh_h, int pen_v, int inh_v)
+{
+    int64_t e = 0;
+    for (int y = 0; y < h; y++)
+        for (int x = 0; x < w; x++) {
+            int S = labels[y * w + x];
+            e += cost[((int64_t)S * h + y) * w + x];
+        }
+    for (int y = 0; y < h; y++)
+        for (int x = 0; x < w; x++) {
+            int S = labels[y * w + x];
+            if (x + 1 < w) e += pair_term(pen_h, inh_h, S - labels[y * w + x + 1]);
+            if (y + 1 < h) e += pair_term(pen_v, inh_v, S - labels[(y + 1) * w + x]);
+        }
+    (void)m;
+    return e;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Explicit graph in compressed adjacency form.                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t n;          /* nodes: 0 = s, 1 = t, then the grid nodes */
+    int64_t narcs;
+    int64_t *first;     /* n+1 offsets into the arc arrays */
+    int32_t *head;      /* arc target */
+    int64_t *rev;       /* index of the paired reverse arc */
+    int64_t *res;       /* residual capacity */
+    int64_t *cap0;      /* original capacity */
+    int32_t *tail;      /* arc source (for checks) */
+    int w, h, m;
+} orc_graph;
+
+static int32_t node_id(int w, int h, int x, int y, int k)
+{
+    /* k in 1..m-1 */
+    return 2 + (int32_t)((((int64_t)(k - 1) * h + y) * w) + x);
+}
+
+/* Map level k of site (x,y) to a node; k = 0 is s and k = m is t. */
+static int32_t level_node(int w, int h, int m, int x, int y, int k)
+{
+    if (k == 0) return 0;
+    if (k == m) return 1;
+    return node_id(w, h, x, y, k);
+}
+
+typedef struct {
+    orc_graph *g;
+    int fill;           /* 0: count degrees, 1: place arcs */
+    int64_t *pos;       /* next free slot per node (fill pass) */
+} arc_sink;
+
+static void add_pair(arc_sink *sk, int32_t a, int32_t b, int64_t cab, int64_t cba)
+{
+    orc_graph *g = sk->g;
+    if (!sk->fill) {
+        g->first[a + 1]++;
+        g->first[b + 1]++;
+        return;
+    }
+    int64_t ia = sk->pos[a]++;
+    int64_t ib = sk->pos[b]++;
+    g->head[ia] = b; g->tail[ia] = a; g->res[ia] = cab; g->cap0[ia] = cab; g->rev[ia] = ib;
+    g->head[ib] = a; g->tail[ib] = b; g->res[ib] = cba; g->cap0[ib] = cba; g->rev[ib] = ia;
+}
+
+/* Emit every arc of the layered graph exactly once (as arc pairs). */
+static void emit_arcs(arc_sink *sk, const int32_t *cost, int pen_h, int inh_h,
+                      int pen_v, int inh_v)
+{
+    orc_graph *g = sk->g;
+    int w = g->w, h = g->h, m = g->m;
+    for (int y = 0; y < h; y++)
+        for (int x = 0; x < w; x++) {
+            /* data chain: v_k -> v_{k+1} with cap g(k) */
+            for (int k = 0; k < m; k++) {
+                int64_t gk = cost[((int64_t)k * h + y) * w + x];
+                int32_t a = level_node(w, h, m, x, y, k);
+                int32_t b = level_node(w, h, m, x, y, k + 1);
+                int64_t back = (k >= 1 && k <= m - 2) ? ORC_INF : 0;
+                add_pair(sk, a, b, gk, back);
+            }
+        }
+    for (int dir = 0; dir < 2; dir++) {
+        int64_t h1 = dir == 0 ? pen_h : pen_v;
+        int64_t h2 = dir == 0 ? inh_h : inh_v;
+        for (int y = 0; y < h; y++)
+            for (int x = 0; x < w; x++) {
+                int ux = x, uy = y;
+                int vx = dir == 0 ? x + 1 : x;
+                int vy = dir == 0 ? y : y + 1;
+                if (vx >= w || vy >= h) continue;
+                /* same-level arcs u_k <-> v_k */
+                for (int k = 1; k <= m - 1; k++)
+                    add_pair(sk, node_id(w, h, ux, uy, k), node_id(w, h, vx, vy, k), h1, h1);
+                /* diagonal arcs u_{k+1} -> v_k and v_{k+1} -> u_k */
+                for (int k = 1; k <= m - 2; k++) {
+                    add_pair(sk, node_id(w, h, ux, uy, k + 1), node_id(w, h, vx, vy, k), h2, 0);
+                    add_pair(sk, node_id(w, h, vx, vy, k + 1), node_id(w, h, ux, uy, k), h2, 0);
+                }
+            }
+    }
+}
+
+void orc_graph_free(orc_graph *g)
+{
+    if (!g) return;
+    free(g->first); free(g->head); free(g->rev); free(g->res); free(g->cap0); free(g->tail);
+    free(g);
+}
+
+orc_graph *orc_graph_build(const int32_t *cost, int w, int h, int m, int pen_h,
+                           int inh_h, int pen_v, int inh_v)
+{
+    if (w < 0 || h < 0 || m < 1) return NULL;
+    if (pen_h < 0 || inh_h < 0 || pen_v < 0 || inh_v < 0) return NULL;
+    int64_t nn = 2 + (int64_t)w * h * (m - 1);
+    if (nn > INT32_MAX) return NULL;
+    orc_graph *g = (orc_graph *)calloc(1, sizeof(orc_graph));
+    if (!g) return NULL;
+    g->n = (int32_t)nn; g->w = w; g->h = h; g->m = m;
+    g->first = (int64_t *)calloc((size_t)nn + 1, sizeof(int64_t));
+    if (!g->first) { orc_graph_free(g); return NULL; }
+    arc_sink sk = { g, 0, NULL };
+    emit_arcs(&sk, cost, pen_h, inh_h, pen_v, inh_v);
+    for (int64_t i = 0; i < nn; i++) g->first[i + 1] += g->first[i];
+    g->narcs = g->first[nn];
+    size_t na = (size_t)g->narcs > 0 ? (size_t)g->narcs : 1;
+    g->head = (int32_t *)malloc(na * sizeof(int32_t));
+    g->tail = (int32_t *)malloc(na * sizeof(int32_t));
+    g->rev = (int64_t *)malloc(na * sizeof(int64_t));
+    g->res = (int64_t *)malloc(na * sizeof(int64_t));
+    g->cap0 = (int64_t *)malloc(na * sizeof(int64_t));
+    sk.pos = (int64_t *)malloc((size_t)nn * sizeof(int64_t));
+    if (!g->head || !g->tail || !g->rev || !g->res || !g->cap0 || !sk.pos) {
+        free(sk.pos); orc_graph_free(g); return NULL;
+    }
+    memcpy(sk.pos, g->first, (size_t)nn * sizeof(int64_t));
+    sk.fill = 1;
+    emit_arcs(&sk, cost, pen_h, inh_h, pen_v, inh_v);
+    free(sk.pos);
+    return g;
+}
+
+int32_t orc_graph_nodes(const orc_graph *g) { return g->n; }
+int64_t orc_graph_arcs(const orc_graph *g) { return g->narcs; }
+
+/* Capacity of the cut induced by a labelling: source side = {s} and every
+ * v_k with X_v >= k.  Used to check that the graph encodes E(X). */
+int64_t orc_cut_capacity(const orc_graph *g, const int32_t *labels)
+{
+    int w = g->w, h = g->h;
+    uint8_t *side = (uint8_t *)malloc((size_t)g->n);
+    if (!side) return -1;
+    side[0] = 1; side[1] = 0;
+    for (int k = 1; k <= g->m - 1; k++)
+        for (int y = 0; y < h; y++)
+            for (int x = 0; x < w; x++)
+                side[node_id(w, h, x, y, k)] = labels[y * w + x] >= k;
+    int64_t c = 0;
+    for (int64_t a = 0; a < g->narcs; a++)
+        if (side[g->tail[a]] && !side[g->head[a]]) c += g->cap0[a];
+    free(side);
+    return c;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Residual reachability and label read-out.                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Mark every node reachable by residual arcs from the seed set. */
+static int reach_from(const orc_graph *g, uint8_t *mark)
+{
+    int32_t *queue = (int32_t *)malloc((size_t)g->n * sizeof(int32_t));
+    if (!queue) return ORC_E_NOMEM;
+    int64_t qh = 0, qt = 0;
+    for (int32_t v = 0; v < g->n; v++)
+        if (mark[v]) queue[qt++] = v;
+    while (qh < qt) {
+        int32_t u = queue[qh++];
+        for (int64_t a = g->first[u]; a < g->first[u + 1]; a++) {
+            int32_t v = g->head[a];
+            if (g->res[a] > 0 && !mark[v]) { mark[v] = 1; queue[qt++] = v; }
+        }
+    }
+    free(queue);
+    return ORC_OK;
+}
+
+/* X_v = number of column nodes on the source side; the source side of a
+ * column must be a prefix v_1..v_X (guaranteed by the INF reverse arcs). */
+static int labels_from_side(const orc_graph *g, const uint8_t *side, int32_t *labels)
+{
+    int w = g->w, h = g->h, m = g->m;
+    for (int y = 0; y < h; y++)
+        for (int x = 0; x < w; x++) {
+            int X = 0, seen_out = 0;
+            for (int k = 1; k <= m - 1; k++) {
+                int in = side[node_id(w, h, x, y, k)];
+                if (in) {
+                    if (seen_out) return ORC_E_PREFIX;
+                    X++;
+                } else {
+                    seen_out = 1;
+                }
+            }
+            labels[y * w + x] = X;
+        }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Max-flow 1: Dinic.                                                        */
+/* ------------------------------------------------------------------------ */
+
+static int dinic_bfs(const orc_graph *g, int32_t *level, int32_t *queue)
+{
+    for (int32_t v = 0; v < g->n; v++) level[v] = -1;
+    int64_t qh = 0, qt = 0;
+    level[0] = 0; queue[qt++] = 0;
+    while (qh < qt) {
+        int32_t u = queue[qh++];
+        for (int64_t a = g->first[u]; a < g->first[u + 1]; a++) {
+            int32_t v = g->head[a];
+            if (g->res[a] > 0 && level[v] < 0) { level[v] = level[u] + 1; queue[qt++] = v; }
+        }
+    }
+    return level[1] >= 0;
+}
+
+/* Blocking flow with current-arc pointers and an explicit path stack. */
+static int64_t dinic_block(orc_graph *g, const int32_t *level, int64_t *cur, int64_t *path)
+{
+    int64_t total = 0;
+    int64_t depth = 0;              /* number of arcs on the path */
+    int32_t u = 0;
+    for (;;) {
+        if (u == 1) {
+            int64_t b = ORC_INF;
+            for (int64_t i = 0; i < depth; i++) if (g->res[path[i]] < b) b = g->res[path[i]];
+            for (int64_t i = 0; i < depth; i++) {
+                g->res[path[i]] -= b;
+                g->res[g->rev[path[i]]] += b;
+            }
+            total += b;
+            /* retreat to the tail of the first saturated arc */
+            int64_t cut = 0;
+            while (cut < depth && g->res[path[cut]] > 0) cut++;
+            depth = cut;
+            u = depth == 0 ? 0 : g->head[path[depth - 1]];
+            continue;
+        }
+        int advanced = 0;
+        for (; cur[u] < g->first[u + 1]; cur[u]++) {
+            int64_t a = cur[u];
+            int32_t v = g->head[a];
+            if (g->res[a] > 0 && level[v] == level[u] + 1) {
+                path[depth++] = a;
+                u = v;
+                advanced = 1;
+                break;
+            }
+        }
+        if (advanced) continue;
+        /* dead end: retreat */
+        if (depth == 0) break;
+        depth--;
+        u = g->tail[path[depth]];
+        cur[u]++;
+    }
+    return total;
+}
+
+int orc_maxflow_dinic(orc_graph *g, int64_t *flow_out)
+{
+    int32_t *level = (int32_t *)malloc((size_t)g->n * sizeof(int32_t));
+    int32_t *queue = (int32_t *)malloc((size_t)g->n * sizeof(int32_t));
+    int64_t *cur = (int64_t *)malloc((size_t)g->n * sizeof(int64_t));
+    int64_t *path = (int64_t *)malloc((size_t)g->n * sizeof(int64_t));
+    if (!level || !queue || !cur || !path) {
+        free(level); free(queue); free(cur); free(path); return ORC_E_NOMEM;
+    }
+    int64_t flow = 0;
+    while (dinic_bfs(g, level, queue)) {
+        for (int32_t v = 0; v < g->n; v++) cur[v] = g->first[v];
+        flow += dinic_block(g, level, cur, path);
+    }
+    free(level); free(queue); free(cur); free(path);
+    *flow_out = flow;
+    return ORC_OK;
+}
+
+/* Minimal source side after a max flow: residual reachability from s. */
+int orc_labels_after_flow(const orc_graph *g, int32_t *labels)
+{
+    uint8_t *mark = (uint8_t *)calloc((size_t)g->n, 1);
+    if (!mark) return ORC_E_NOMEM;
+    mark[0] = 1;
+    int rc = reach_from(g, mark);
+    if (rc == ORC_OK) rc = labels_from_side(g, mark, labels);
+    free(mark);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Max-flow 2: FIFO push-relabel with global relabelling (first phase only). */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t *excess;
+    int32_t *height;
+} orc_preflow;
+
+/* Exact distance to t in the residual graph, by backward BFS; nodes that
+ * cannot reach t get height n. */
+static void global_relabel(const orc_graph *g, int32_t *height, int32_t *queue)
+{
+    int32_t n = g->n;
+    for (int32_t v = 0; v < n; v++) height[v] = n;
+    int64_t qh = 0, qt = 0;
+    height[1] = 0; queue[qt++] = 1;
+    while (qh < qt) {
+        int32_t v = queue[qh++];
+        for (int64_t a = g->first[v]; a < g->first[v + 1]; a++) {
+            int32_t u = g->head[a];           /* arc v->u; its reverse u->v */
+            if (u == 0) continue;
+            if (height[u] == n && g->res[g->rev[a]] > 0) {
+                height[u] = height[v] + 1;
+                queue[qt++] = u;
+            }
+        }
+    }
+    height[0] = n;
+}
+
+int orc_maxflow_pushrelabel(orc_graph *g, int64_t *flow_out, int64_t *excess_out)
+{
+    int32_t n = g->n;
+    int64_t *ex = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    int32_t *ht = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    int64_t *cur = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int32_t *fifo = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    int32_t *bfsq = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    uint8_t *inq = (uint8_t *)calloc((size_t)n, 1);
+    if (!ex || !ht || !cur || !fifo || !bfsq || !inq) {
+        free(ex); free(ht); free(cur); free(fifo); free(bfsq); free(inq); return ORC_E_NOMEM;
+    }
+    /* saturate every arc out of s */
+    for (int64_t a = g->first[0]; a < g->first[1]; a++) {
+        int64_t c = g->res[a];
+        if (c <= 0) continue;
+        g->res[a] -= c; g->res[g->rev[a]] += c;
+        ex[g->head[a]] += c; ex[0] -= c;
+    }
+    global_relabel(g, ht, bfsq);
+    for (int32_t v = 0; v < n; v++) cur[v] = g->first[v];
+    /* circular FIFO of active nodes (excess > 0, height < n, not s or t) */
+    int64_t qh = 0, qn = 0;
+    for (int32_t v = 2; v < n; v++)
+        if (ex[v] > 0 && ht[v] < n) { fifo[(qh + qn) % n] = v; qn++; inq[v] = 1; }
+    int64_t work = 0;
+    const int64_t relabel_period = 6 * (int64_t)n + g->narcs / 2;
+    while (qn > 0) {
+        if (work > relabel_period) {
+            work = 0;
+            global_relabel(g, ht, bfsq);
+            for (int32_t v = 0; v < n; v++) cur[v] = g->first[v];
+            qh = 0; qn = 0;
+            for (int32_t v = 2; v < n; v++) {
+                inq[v] = 0;
+                if (ex[v] > 0 && ht[v] < n) { fifo[qn++] = v; inq[v] = 1; }
+            }
+            continue;
+        }
+        int32_t u = fifo[qh]; qh = (qh + 1) % n; qn--; inq[u] = 0;
+        /* discharge u */
+        while (ex[u] > 0 && ht[u] < n) {
+            if (cur[u] == g->first[u + 1]) {
+                /* relabel: one above the lowest residual neighbour */
+                int32_t hmin = n;
+                for (int64_t a = g->first[u]; a < g->first[u + 1]; a++)
+                    if (g->res[a] > 0 && ht[g->head[a]] < hmin) hmin = ht[g->head[a]];
+                work += 12 + (g->first[u + 1] - g->first[u]);
+                ht[u] = hmin + 1 < n ? hmin + 1 : n;
+                cur[u] = g->first[u];
+                continue;
+            }
+            int64_t a = cur[u];
+            int32_t v = g->head[a];
+            if (g->res[a] > 0 && ht[u] == ht[v] + 1) {
+                int64_t d = ex[u] < g->res[a] ? ex[u] : g->res[a];
+                g->res[a] -= d; g->res[g->rev[a]] += d;
+                ex[u] -= d; ex[v] += d;
+                if (v >= 2 && !inq[v] && ht[v] < n) {
+                    fifo[(qh + qn) % n] = v; qn++; inq[v] = 1;
+                }
+                if (g->res[a] == 0) cur[u]++;
+            } else {
+                cur[u]++;
+            }
+        }
+    }
+    *flow_out = ex[1];
+    if (excess_out) memcpy(excess_out, ex, (size_t)n * sizeof(int64_t));
+    free(ex); free(ht); free(cur); free(fifo); free(bfsq); free(inq);
+    return ORC_OK;
+}
+
+/* Minimal source side from a maximum preflow: residual reachability from s
+ * and from every node that still holds positive excess.  Every such node is
+ * on the source side of every minimum cut, and nothing reachable from it can
+ * cross a saturated minimum cut, so this is the intersection of all minimum
+ * source sides. */
+int orc_labels_after_preflow(const orc_graph *g, const int64_t *excess, int32_t *labels)
+{
+    uint8_t *mark = (uint8_t *)calloc((size_t)g->n, 1);
+    if (!mark) return ORC_E_NOMEM;
+    mark[0] = 1;
+    for (int32_t v = 2; v < g->n; v++) if (excess[v] > 0) mark[v] = 1;
+    int rc = reach_from(g, mark);
+    if (rc == ORC_OK && mark[1]) rc = ORC_E_ARG;    /* not a maximum preflow */
+    if (rc == ORC_OK) rc = labels_from_side(g, mark, labels);
+    free(mark);
+    return rc;
+}
+
+/* Maximal source side: every node that cannot reach t in the residual graph.
+ * Returns the labelling of the back-most optimal surface (diagnostics). */
+int orc_labels_max_side(const orc_graph *g, int32_t *labels)
+{
+    /* backward reachability to t */
+    int32_t n = g->n;
+    uint8_t *to_t = (uint8_t *)calloc((size_t)n, 1);
+    int32_t *queue = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    if (!to_t || !queue) { free(to_t); free(queue); return ORC_E_NOMEM; }
+    int64_t qh = 0, qt = 0;
+    to_t[1] = 1; queue[qt++] = 1;
+    while (qh < qt) {
+        int32_t v = queue[qh++];
+        for (int64_t a = g->first[v]; a < g->first[v + 1]; a++) {
+            int32_t u = g->head[a];
+            if (!to_t[u] && g->res[g->rev[a]] > 0) { to_t[u] = 1; queue[qt++] = u; }
+        }
+    }
+    for (int32_t v = 0; v < n; v++) to_t[v] = !to_t[v];
+    int rc = labels_from_side(g, to_t, labels);
+    free(to_t); free(queue);
+    return rc;
+}
+
+/* Feasibility of the current flow: 0 <= flow <= cap on every arc pair and
+ * conservation at every grid node (excess given, or zero when NULL). */
+int orc_check_flow(const orc_graph *g, const int64_t *excess)
+{
+    int64_t *net = (int64_t *)calloc((size_t)g->n, sizeof(int64_t));
+    if (!net) return ORC_E_NOMEM;
+    for (int64_t a = 0; a < g->narcs; a++) {
+        int64_t b = g->rev[a];
+        if (g->rev[b] != a) { free(net); return 1; }
+        /* flow on a = cap0(a) - res(a); paired arcs carry opposite flows */
+        int64_t fa = g->cap0[a] - g->res[a];
+        int64_t fb = g->cap0[b] - g->res[b];
+        if (fa + fb != 0) { free(net); return 2; }
+        if (g->res[a] < 0) { free(net); return 3; }
+        if (fa > 0) { net[g->head[a]] += fa; net[g->tail[a]] -= fa; }
+    }
+    for (int32_t v = 2; v < g->n; v++) {
+        int64_t want = excess ? excess[v] : 0;
+        if (net[v] != want) { free(net); return 4; }
+    }
+    free(net);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One-call solve used by the tests and the CPU baseline.                   */
+/* ------------------------------------------------------------------------ */
+
+/* algo 0 = Dinic, 1 = push-relabel.  Writes the canonical labels, the
+ * max-flow value and the energy of the labels. */
+int orc_solve(const int32_t *cost, int w, int h, int m, int pen_h, int inh_h,
+              int pen_v, int inh_v, int algo, int32_t *labels, int64_t *flow,
+              int64_t *energy)
+{
+    if (m == 1) {
+        for (int i = 0; i < w * h; i++) labels[i] = 0;
+        *energy = orc_energy(cost, labels, w, h, m, pen_h, inh_h, pen_v, inh_v);
+        *flow = *energy;
+        return ORC_OK;
+    }
+    orc_graph *g = orc_graph_build(cost, w, h, m, pen_h, inh_h, pen_v, inh_v);
+    if (!g) return ORC_E_NOMEM;
+    int rc;
+    if (algo == 0) {
+        rc = orc_maxflow_dinic(g, flow);
+        if (rc == ORC_OK) rc = orc_labels_after_flow(g, labels);
+    } else {
+        int64_t *ex = (int64_t *)malloc((size_t)g->n * sizeof(int64_t));
+        if (!ex) { orc_graph_free(g); return ORC_E_NOMEM; }
+        rc = orc_maxflow_pushrelabel(g, flow, ex);
+        if (rc == ORC_OK) rc = orc_labels_after_preflow(g, ex, labels);
+        free(ex);
+    }
+    orc_graph_free(g);
+    if (rc == ORC_OK)
+        *energy = orc_energy(cost, labels, w, h, m, pen_h, inh_h, pen_v, inh_v);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Brute force over every labelling (tiny grids only).                       */
+/* ------------------------------------------------------------------------ */
+
+/* Enumerates all m^(w*h) labellings.  Returns the minimum energy, the number
+ * of minimisers, and their pointwise minimum and maximum labellings. */
+int orc_brute_force(const int32_t *cost, int w, int h, int m, int pen_h,
+                    int inh_h, int pen_v, int inh_v, int64_t *min_energy,
+                    int64_t *n_min, int32_t *lo_labels, int32_t *hi_labels)
+{
+    int n = w * h;
+    double total = 1.0;
+    for (int i = 0; i < n; i++) total *= m;
+    if (total > 2.0e8) return ORC_E_TOO_BIG;
+    int32_t *X = (int32_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    if (!X) return ORC_E_NOMEM;
+    int64_t best = INT64_MAX, count = 0;
+    for (;;) {
+        int64_t e = orc_energy(cost, X, w, h, m, pen_h, inh_h, pen_v, inh_v);
+        if (e < best) {
+            best = e; count = 1;
+            for (int i = 0; i < n; i++) lo_labels[i] = hi_labels[i] = X[i];
+        } else if (e == best) {
+            count++;
+            for (int i = 0; i < n; i++) {
+                if (X[i] < lo_labels[i]) lo_labels[i] = X[i];
+                if (X[i] > hi_labels[i]) hi_labels[i] = X[i];
+            }
+        }
+        int i = 0;
+        while (i < n && ++X[i] == m) { X[i] = 0; i++; }
+        if (i == n) break;
+    }
+    free(X);
+    *min_energy = best;
+    *n_min = count;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact dynamic programming along one row (h == 1), a textbook routine.     */
+/* ------------------------------------------------------------------------ */
+
+/* Forward and backward min-sum messages; label S is used by some minimiser
+ * at x iff F_x(S) + B_x(S) - g_x(S) equals the minimum.  The canonical
+ * (pointwise-minimum) labelling takes the smallest such S at every x. */
+int orc_scanline_dp(const int32_t *cost, int w, int m, int pen, int inh,
+                    int64_t *min_energy, int32_t *lo_labels)
+{
+    if (w <= 0) { *min_energy = 0; return ORC_OK; }
+    int64_t *F = (int64_t *)malloc((size_t)w * m * sizeof(int64_t));
+    int64_t *B = (int64_t *)malloc((size_t)w * m * sizeof(int64_t));
+    if (!F || !B) { free(F); free(B); return ORC_E_NOMEM; }
+#define G(x, S) ((int64_t)cost[(int64_t)(S) * w + (x)])
+    for (int S = 0; S < m; S++) F[S] = G(0, S);
+    for (int x = 1; x < w; x++)
+        for (int S = 0; S < m; S++) {
+            int64_t best = INT64_MAX;
+            for (int P = 0; P < m; P++) {
+                int64_t c = F[(x - 1) * m + P] + pair_term(pen, inh, P - S);
+                if (c < best) best = c;
+            }
+            F[x * m + S] = best + G(x, S);
+        }
+    for (int S = 0; S < m; S++) B[(w - 1) * m + S] = G(w - 1, S);
+    for (int x = w - 2; x >= 0; x--)
+        for (int S = 0; S < m; S++) {
+            int64_t best = INT64_MAX;
+            for (int P = 0; P < m; P++) {
+                int64_t c = B[(x + 1) * m + P] + pair_term(pen, inh, S - P);
+                if (c < best) best = c;
+            }
+            B[x * m + S] = best + G(x, S);
+        }
+    int64_t emin = INT64_MAX;
+    for (int S = 0; S < m; S++) if (F[(w - 1) * m + S] < emin) emin = F[(w - 1) * m + S];
+    for (int x = 0; x < w; x++) {
+        lo_labels[x] = -1;
+        for (int S = 0; S < m; S++)
+            if (F[x * m + S] + B[x * m + S] - G(x, S) == emin) { lo_labels[x] = S; break; }
+    }
+#undef G
+    free(F); free(B);
+    *min_energy = emin;
+    return ORC_OK;
+}
