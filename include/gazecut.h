@@ -1,0 +1,174 @@
+/*
+ * gazecut.h -- C ABI of the gaze-line stereo graph cut on AMD Instinct MI355X
+ * (gfx950).  Method: Oguri & Shibata, "A new stereo formulation not using
+ * pixel and disparity models" (arXiv 1803.01516).
+ *
+ * The library minimises, exactly, the site-labelling energy of Sec. 2
+ *
+ *     E(X) = sum_v g_v(X_v) + sum_{(u,v) 4-neighbours} h~(X_u - X_v)
+ *
+ * whose sites are gaze lines (x, y) and whose labels are depth numbers
+ * S in [0, m) (Sec. 3; S = 0 is the front), with the convex pairwise term of
+ * Sec. 3
+ *
+ *     h~(d) = penalty * |d| + inhibit * (|d| - 1) * T(|d| > 1).
+ *
+ * Calls, in pipeline order:
+ *   stereo_cost_volume  data term g at every cross point        (Sec. 4.3)
+ *   graph_build         layered graph, terminals as overflows    (Sec. 3 Fig. 4, Sec. 4.4)
+ *   maxflow_solve       push-relabel with global relabelling     (Sec. 4.4)
+ *   extract_labels      minimal source side -> depth numbers, E  (Sec. 3: the cut is the surface)
+ *
+ * Conventions for every call:
+ *   - Buffers marked DEVICE are hipMalloc'd (e.g. torch CUDA tensors) and
+ *     owned by the caller; the library never allocates or frees device
+ *     memory.  Host pointers are read during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; results are valid once the stream is
+ *     synchronised.  maxflow_solve reads small flags back and so blocks the
+ *     calling host thread until the solve has finished.
+ *   - Every call returns a gc_status (0 = success, < 0 = error) and never
+ *     aborts.  On error no kernel has been enqueued unless the status is
+ *     GC_E_HIP or GC_E_NOT_CONVERGED.
+ *   - Calls on different graphs may run concurrently on different streams.
+ *     Calls that share a graph workspace must be ordered by the caller.
+ */
+#ifndef GAZECUT_H
+#define GAZECUT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GC_OK = 0,
+    GC_E_ARG = -1,            /* NULL pointer or invalid option value        */
+    GC_E_SHAPE = -2,          /* negative sizes, labels < 1, too many nodes  */
+    GC_E_WORKSPACE = -3,      /* workspace smaller than gc_graph_footprint_bytes */
+    GC_E_CAP_OVERFLOW = -4,   /* sites*cap + largest pair capacity >= 2^30:
+                                 int32 excess/residuals could overflow        */
+    GC_E_NOT_CONVERGED = -5,  /* iteration cap of gc_solve_opts reached       */
+    GC_E_HIP = -6,            /* a HIP runtime call failed (see gc_last_hip_error) */
+    GC_E_PREFIX = -7          /* a cut column was not a prefix (internal check) */
+} gc_status;
+
+/* Problem description (host struct).  Sites are the width x height gaze
+ * lines; labels are the m = `labels` depth numbers.  The cross point of site
+ * (x, y) at depth S joins left pixel x - S + (m-1) and right pixel
+ * x + S - (m-1) of row y (Sec. 3, Sec. 4.1: one depth step is two pixels of
+ * disparity).  `cap` truncates the absolute intensity difference.  The
+ * pairwise term uses (penalty_h, inhibit_h) between horizontal neighbours and
+ * (penalty_v, inhibit_v) between vertical ones; all four must be >= 0, which
+ * is what makes h~ convex (Sec. 2, eq. (1)). */
+typedef struct {
+    int32_t width;
+    int32_t height;
+    int32_t labels;
+    int32_t cap;
+    int32_t penalty_h;
+    int32_t inhibit_h;
+    int32_t penalty_v;
+    int32_t inhibit_v;
+} gc_problem;
+
+/* A built graph: a view of the caller's workspace plus the problem. */
+typedef struct {
+    void *ws;                 /* DEVICE, >= gc_graph_footprint_bytes, 256-B aligned */
+    size_t ws_bytes;
+    gc_problem p;
+} gc_graph;
+
+/* Solver options; a zero-filled struct selects the defaults. */
+typedef struct {
+    int32_t relabel_period;   /* push-relabel sweeps between global relabels (default 8) */
+    int32_t max_sweeps;       /* give up with GC_E_NOT_CONVERGED after this many (default 1<<20) */
+    int32_t tile_w;           /* BFS tile extent along x (default 32)          */
+    int32_t tile_h;           /* along y (default 4)                          */
+    int32_t tile_j;           /* along the depth-number axis (default 16)     */
+    int32_t local_iters;      /* max in-tile relaxation rounds per pass (default 64) */
+    int32_t reserved[2];
+} gc_solve_opts;
+
+/* Solver statistics (host struct, filled by maxflow_solve). */
+typedef struct {
+    int64_t pushes;           /* arc pushes that moved a positive amount      */
+    int32_t sweeps;           /* push + relabel sweeps over the graph         */
+    int32_t global_relabels;  /* exact distance recomputations                */
+    int32_t bfs_passes;       /* tiled relaxation passes (all BFS work)       */
+    int32_t active_last;      /* active nodes at the last check (0 when done) */
+    int32_t reserved[2];
+} gc_solve_stats;
+
+/* Human-readable name of a status code (static string). */
+const char *gc_status_str(int status);
+
+/* Last HIP error code seen by the calling thread (0 if none). */
+int gc_last_hip_error(void);
+
+/* Validates a problem: GC_OK, GC_E_ARG, GC_E_SHAPE or GC_E_CAP_OVERFLOW. */
+int gc_problem_check(const gc_problem *p);
+
+/* Bytes of DEVICE workspace graph_build needs for `p` (0 if p is invalid).
+ * Linear in the number of graph nodes width*height*(labels-1); used both to
+ * allocate and to admit work by its memory footprint. */
+size_t gc_graph_footprint_bytes(const gc_problem *p);
+
+/* Data term of Sec. 4.3 for grayscale pairs:
+ *   cost[(S*height + y)*width + x] = min(|left(y, x-S+m-1) - right(y, x+S-m+1)|, cap)
+ * and cap when either pixel falls outside the image.
+ * left, right: DEVICE uint8 [height][width], row-major, rectified pair.
+ * cost:        DEVICE int32 [labels][height][width] (label-major), written.
+ * Errors: GC_E_ARG (NULL), GC_E_SHAPE, GC_E_HIP. */
+int stereo_cost_volume(const uint8_t *left, const uint8_t *right, const gc_problem *p,
+                       int32_t *cost, void *stream);
+
+/* Builds the layered graph of Sec. 3 (Fig. 4) in `ws`: for every site the
+ * nodes v_1..v_{m-1} ("v_k on the source side" means X_v >= k) with the data
+ * chain v_k -> v_{k+1} of capacity g(k) and an unbounded reverse arc,
+ * same-level arcs of capacity penalty both ways and the diagonal arcs
+ * u_{k+1} -> v_k of capacity inhibit between 4-neighbours.  The terminal
+ * arcs are folded into node overflows as in Sec. 4.4: v_1 starts with excess
+ * g(0) and v_{m-1} with deficit g(m-1).
+ * cost: DEVICE int32 [labels][height][width] from stereo_cost_volume (or any
+ *       non-negative data term of the same layout); read only.
+ * ws:   DEVICE workspace of at least gc_graph_footprint_bytes(p) bytes,
+ *       256-byte aligned; fully (re)initialised, so a graph can be rebuilt
+ *       in place.
+ * g_out: host struct filled with (ws, ws_bytes, *p).
+ * Errors: GC_E_ARG, GC_E_SHAPE, GC_E_CAP_OVERFLOW, GC_E_WORKSPACE, GC_E_HIP. */
+int graph_build(const gc_problem *p, const int32_t *cost, void *ws, size_t ws_bytes,
+                gc_graph *g_out, void *stream);
+
+/* Exact maximum preflow by parallel push-relabel with global relabelling
+ * (Sec. 4.4): alternating push and relabel sweeps over all nodes, with an
+ * exact residual-distance recomputation every `relabel_period` sweeps; stops
+ * when no node with excess can reach a node with deficit.  The state left in
+ * the workspace is what extract_labels reads.
+ * o: host options or NULL for defaults; stats: host struct or NULL.
+ * Errors: GC_E_ARG, GC_E_NOT_CONVERGED (state is a valid preflow but not a
+ * maximum one), GC_E_HIP. */
+int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *stats, void *stream);
+
+/* Reads the minimum cut off a solved graph.  The source side is every node
+ * reachable by residual arcs from a node that still has excess; this is the
+ * minimal source side of all minimum cuts, so the labelling is the unique
+ * front-most optimal surface (Sec. 3: the cut is the surface of real cross
+ * points).  X_v = number of source-side nodes in the column of v.
+ * cost:   DEVICE int32 [labels][height][width], the same data term the graph
+ *         was built from (used to evaluate E).
+ * labels: DEVICE int32 [height][width], written.
+ * result: DEVICE int64[2], written: result[0] = E(labels) evaluated from its
+ *         definition, result[1] = value of the maximum flow.  The two are
+ *         equal when the solve finished (max-flow = min-cut).
+ * Errors: GC_E_ARG, GC_E_PREFIX, GC_E_HIP. */
+int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *labels,
+                   int64_t *result, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GAZECUT_H */

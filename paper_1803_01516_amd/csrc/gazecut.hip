@@ -1,0 +1,761 @@
+// gazecut.hip -- HIP kernels and C ABI for the gaze-line stereo graph cut
+// (Oguri & Shibata, arXiv 1803.01516) on MI355X / gfx950.
+//
+// Graph state lives in one caller-owned workspace as label-major
+// structure-of-arrays int32 words, node index n = (j*H + y)*W + x with
+// j = k-1 the depth layer (k = 1..m-1), so consecutive threads touch
+// consecutive x and every access of a sweep is coalesced.  Per node:
+//
+//   ex   excess (terminal arcs folded into overflows, Sec. 4.4)
+//   ht   height (distance label of push-relabel)
+//   rd   residual of v_k -> v_{k+1}         (data chain; reverse is unbounded)
+//   re   residual of v_k -> E_k             pair total 2*penalty_h
+//   rs   residual of v_k -> S_k             pair total 2*penalty_v
+//   rem  residual of v_k -> E_{k-1}         pair total inhibit_h
+//   rep  residual of v_k -> E_{k+1}         pair total inhibit_h
+//   rsm  residual of v_k -> S_{k-1}         pair total inhibit_v
+//   rsp  residual of v_k -> S_{k+1}         pair total inhibit_v
+//
+// Each arc pair is stored once; the opposite residual is the pair total
+// minus the stored word.  E/S are the (x+1, y) and (x, y+1) neighbours.
+//
+// Push-relabel runs as synchronous sweeps.  In the push sweep heights are
+// read-only, so along any arc pair at most one endpoint is admissible
+// (h(u) = h(v) + 1 excludes h(v) = h(u) + 1): each pair word has a single
+// writer and needs no atomic.  Inflow goes to a separate `ein` array with
+// atomics and is merged by the relabel sweep.  Relabels only raise heights,
+// so the concurrent reads of neighbour heights in the relabel sweep see
+// lower bounds and the labelling stays valid.
+//
+// Global relabelling and the cut read-out are both min-plus fixpoints over
+// a 14-bit residual arc mask per node: BFS distance to the deficit nodes
+// (step 1) and reachability from the excess nodes (step 0).  They run as
+// LDS-tiled relaxations: each workgroup iterates its site x layer tile to a
+// local fixpoint, and passes repeat until no tile changes.
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+
+#include "gazecut.h"
+
+#define GC_API extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+constexpr int32_t kInf = 1 << 30;
+constexpr int kBlock = 256;
+constexpr int kMaxFlags = 16;
+
+// Arc directions (bit index in the residual masks) and their offsets
+// (dj, dy, dx).  opposite(d) = d ^ 1 for 0..5; 6<->9, 7<->8, 10<->13, 11<->12.
+enum Dir {
+    D_DOWN = 0, D_UP = 1, D_E = 2, D_W = 3, D_S = 4, D_N = 5,
+    D_EM = 6, D_EP = 7, D_WM = 8, D_WP = 9, D_SM = 10, D_SP = 11, D_NM = 12, D_NP = 13
+};
+__host__ __device__ constexpr int dir_dj(int d)
+{
+    return d == D_DOWN ? 1 : d == D_UP ? -1
+         : (d == D_EM || d == D_WM || d == D_SM || d == D_NM) ? -1
+         : (d == D_EP || d == D_WP || d == D_SP || d == D_NP) ? 1 : 0;
+}
+__host__ __device__ constexpr int dir_dy(int d)
+{
+    return (d == D_S || d == D_SM || d == D_SP) ? 1 : (d == D_N || d == D_NM || d == D_NP) ? -1 : 0;
+}
+__host__ __device__ constexpr int dir_dx(int d)
+{
+    return (d == D_E || d == D_EM || d == D_EP) ? 1 : (d == D_W || d == D_WM || d == D_WP) ? -1 : 0;
+}
+
+struct DevHeader {
+    int32_t flags[kMaxFlags];
+    int32_t active;
+    int32_t prefix_err;
+    int32_t pad[14];
+    unsigned long long pushes;
+    unsigned long long pad2[15];
+};
+static_assert(sizeof(DevHeader) == 256, "header must stay 256 bytes");
+
+struct Graph {
+    int32_t *ex, *ht, *rd, *re, *rs, *rem, *rep, *rsm, *rsp, *ein, *aux;
+    uint16_t *mask;
+    DevHeader *hdr;
+    int32_t W, H, J;
+    int64_t plane, N;
+    int32_t te, ts, ie, is;   // pair totals: 2*pen_h, 2*pen_v, inh_h, inh_v
+};
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+thread_local int t_last_hip = 0;
+
+bool hip_ok(hipError_t e)
+{
+    if (e != hipSuccess) { t_last_hip = (int)e; return false; }
+    return true;
+}
+
+int64_t node_count(const gc_problem *p)
+{
+    return (int64_t)p->width * p->height * (p->labels > 0 ? p->labels - 1 : 0);
+}
+
+Graph view(const gc_graph *g)
+{
+    const gc_problem &p = g->p;
+    Graph s;
+    s.W = p.width; s.H = p.height; s.J = p.labels - 1;
+    s.plane = (int64_t)s.W * s.H;
+    s.N = s.plane * s.J;
+    char *b = (char *)g->ws;
+    s.hdr = (DevHeader *)b; b += align256(sizeof(DevHeader));
+    size_t w4 = align256((size_t)s.N * 4);
+    int32_t **arr[] = {&s.ex, &s.ht, &s.rd, &s.re, &s.rs, &s.rem, &s.rep, &s.rsm, &s.rsp, &s.ein, &s.aux};
+    for (int32_t **a : arr) { *a = (int32_t *)b; b += w4; }
+    s.mask = (uint16_t *)b;
+    s.te = 2 * p.penalty_h; s.ts = 2 * p.penalty_v;
+    s.ie = p.inhibit_h; s.is = p.inhibit_v;
+    return s;
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// ---------------------------------------------------------------------------
+// Small device helpers
+// ---------------------------------------------------------------------------
+
+__device__ inline int wave_sum_i32(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ inline long long wave_sum_i64(long long v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+__device__ inline bool lane0() { return (threadIdx.x & 63) == 0; }
+
+// Node counts stay below 2^29 (checked on the host), so 32-bit division is exact.
+__device__ inline void decode(const Graph &s, int64_t n, int &j, int &y, int &x)
+{
+    const int n32 = (int)n, P = (int)s.plane;
+    j = n32 / P;
+    const int r = n32 - j * P;
+    y = r / s.W;
+    x = r - y * s.W;
+}
+
+// Residual of the out-arc of node n in direction d (0 if the arc does not
+// exist).  Valid-range checks use the node coordinates.
+__device__ inline int32_t out_res(const Graph &s, int64_t n, int j, int y, int x, int d)
+{
+    const int64_t P = s.plane, W = s.W;
+    switch (d) {
+    case D_DOWN: return j + 1 < s.J ? s.rd[n] : 0;
+    case D_UP:   return j > 0 ? kInf : 0;
+    case D_E:    return x + 1 < s.W ? s.re[n] : 0;
+    case D_W:    return x > 0 ? s.te - s.re[n - 1] : 0;
+    case D_S:    return y + 1 < s.H ? s.rs[n] : 0;
+    case D_N:    return y > 0 ? s.ts - s.rs[n - W] : 0;
+    case D_EM:   return (x + 1 < s.W && j > 0) ? s.rem[n] : 0;
+    case D_EP:   return (x + 1 < s.W && j + 1 < s.J) ? s.rep[n] : 0;
+    case D_WM:   return (x > 0 && j > 0) ? s.ie - s.rep[n - P - 1] : 0;
+    case D_WP:   return (x > 0 && j + 1 < s.J) ? s.ie - s.rem[n + P - 1] : 0;
+    case D_SM:   return (y + 1 < s.H && j > 0) ? s.rsm[n] : 0;
+    case D_SP:   return (y + 1 < s.H && j + 1 < s.J) ? s.rsp[n] : 0;
+    case D_NM:   return (y > 0 && j > 0) ? s.is - s.rsp[n - P - W] : 0;
+    case D_NP:   return (y > 0 && j + 1 < s.J) ? s.is - s.rsm[n + P - W] : 0;
+    }
+    return 0;
+}
+
+// Residual of the in-arc into node n from its neighbour in direction d.
+__device__ inline int32_t in_res(const Graph &s, int64_t n, int j, int y, int x, int d)
+{
+    const int64_t P = s.plane, W = s.W;
+    switch (d) {
+    case D_DOWN: return j + 1 < s.J ? kInf : 0;                 // v_{k+1} -> v_k
+    case D_UP:   return j > 0 ? s.rd[n - P] : 0;                // v_{k-1} -> v_k
+    case D_E:    return x + 1 < s.W ? s.te - s.re[n] : 0;
+    case D_W:    return x > 0 ? s.re[n - 1] : 0;
+    case D_S:    return y + 1 < s.H ? s.ts - s.rs[n] : 0;
+    case D_N:    return y > 0 ? s.rs[n - W] : 0;
+    case D_EM:   return (x + 1 < s.W && j > 0) ? s.ie - s.rem[n] : 0;
+    case D_EP:   return (x + 1 < s.W && j + 1 < s.J) ? s.ie - s.rep[n] : 0;
+    case D_WM:   return (x > 0 && j > 0) ? s.rep[n - P - 1] : 0;
+    case D_WP:   return (x > 0 && j + 1 < s.J) ? s.rem[n + P - 1] : 0;
+    case D_SM:   return (y + 1 < s.H && j > 0) ? s.is - s.rsm[n] : 0;
+    case D_SP:   return (y + 1 < s.H && j + 1 < s.J) ? s.is - s.rsp[n] : 0;
+    case D_NM:   return (y > 0 && j > 0) ? s.rsp[n - P - W] : 0;
+    case D_NP:   return (y > 0 && j + 1 < s.J) ? s.rsm[n + P - W] : 0;
+    }
+    return 0;
+}
+
+// Move `delta` along the out-arc of n in direction d (residual bookkeeping
+// only; the caller moves the excess).
+__device__ inline void push_res(const Graph &s, int64_t n, int d, int32_t delta)
+{
+    const int64_t P = s.plane, W = s.W;
+    switch (d) {
+    case D_DOWN: s.rd[n] -= delta; break;
+    case D_UP:   s.rd[n - P] += delta; break;
+    case D_E:    s.re[n] -= delta; break;
+    case D_W:    s.re[n - 1] += delta; break;
+    case D_S:    s.rs[n] -= delta; break;
+    case D_N:    s.rs[n - W] += delta; break;
+    case D_EM:   s.rem[n] -= delta; break;
+    case D_EP:   s.rep[n] -= delta; break;
+    case D_WM:   s.rep[n - P - 1] += delta; break;
+    case D_WP:   s.rem[n + P - 1] += delta; break;
+    case D_SM:   s.rsm[n] -= delta; break;
+    case D_SP:   s.rsp[n] -= delta; break;
+    case D_NM:   s.rsp[n - P - W] += delta; break;
+    case D_NP:   s.rsm[n + P - W] += delta; break;
+    }
+}
+
+__device__ inline int64_t nbr(const Graph &s, int64_t n, int d)
+{
+    return n + dir_dj(d) * s.plane + dir_dy(d) * (int64_t)s.W + dir_dx(d);
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// Data term at every cross point (x, S, y).
+__global__ void __launch_bounds__(kBlock)
+k_cost_volume(const uint8_t *__restrict__ left, const uint8_t *__restrict__ right,
+              int W, int H, int m, int cap, int32_t *__restrict__ cost)
+{
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    int y = blockIdx.y;
+    int S = blockIdx.z;
+    if (x >= W) return;
+    int xl = x - S + (m - 1);
+    int xr = x + S - (m - 1);
+    int32_t g = cap;
+    if (xl >= 0 && xl < W && xr >= 0 && xr < W) {
+        int d = (int)left[(int64_t)y * W + xl] - (int)right[(int64_t)y * W + xr];
+        d = d < 0 ? -d : d;
+        g = d < cap ? d : cap;
+    }
+    cost[((int64_t)S * H + y) * W + x] = g;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_build(Graph s, const int32_t *__restrict__ cost, int m)
+{
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= s.N) return;
+    int j, y, x;
+    decode(s, n, j, y, x);
+    const int64_t site = (int64_t)y * s.W + x;
+    const int k = j + 1;
+    int32_t e = 0;
+    if (k == 1) e += cost[site];                                    // s -> v_1 pre-saturated
+    if (k == m - 1) e -= cost[(int64_t)(m - 1) * s.plane + site];   // v_{m-1} -> t as deficit
+    s.ex[n] = e;
+    s.ht[n] = 0;
+    s.ein[n] = 0;
+    s.rd[n] = (j + 1 < s.J) ? cost[(int64_t)k * s.plane + site] : 0;
+    const bool hasE = x + 1 < s.W, hasS = y + 1 < s.H;
+    s.re[n] = hasE ? s.te / 2 : 0;
+    s.rs[n] = hasS ? s.ts / 2 : 0;
+    s.rem[n] = (hasE && j > 0) ? s.ie : 0;      // v_k -> E_{k-1} carries the capacity
+    s.rep[n] = 0;                               // its capacity runs E_{k+1} -> v_k
+    s.rsm[n] = (hasS && j > 0) ? s.is : 0;
+    s.rsp[n] = 0;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_push(Graph s)
+{
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int cnt = 0;
+    if (n < s.N) {
+        int32_t e = s.ex[n];
+        const int32_t h = s.ht[n];
+        if (e > 0 && h < kInf) {
+            int j, y, x;
+            decode(s, n, j, y, x);
+#pragma unroll
+            for (int d = 0; d < 14; ++d) {
+                if (e == 0) continue;
+                int32_t r = out_res(s, n, j, y, x, d);
+                if (r <= 0) continue;
+                int64_t v = nbr(s, n, d);
+                if (s.ht[v] != h - 1) continue;
+                int32_t delta = e < r ? e : r;
+                push_res(s, n, d, delta);
+                atomicAdd(&s.ein[v], delta);
+                e -= delta;
+                ++cnt;
+            }
+            s.ex[n] = e;
+        }
+    }
+    cnt = wave_sum_i32(cnt);
+    if (lane0() && cnt) atomicAdd(&s.hdr->pushes, (unsigned long long)cnt);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_relabel(Graph s)
+{
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= s.N) return;
+    int32_t in = s.ein[n];
+    int32_t e = s.ex[n];
+    if (in != 0) {
+        e += in;
+        s.ex[n] = e;
+        s.ein[n] = 0;
+    }
+    const int32_t h = s.ht[n];
+    if (e <= 0 || h >= kInf) return;
+    int j, y, x;
+    decode(s, n, j, y, x);
+    int32_t hmin = kInf;
+#pragma unroll
+    for (int d = 0; d < 14; ++d) {
+        if (out_res(s, n, j, y, x, d) <= 0) continue;
+        int32_t hv = s.ht[nbr(s, n, d)];
+        hmin = hv < hmin ? hv : hmin;
+    }
+    int32_t nh = hmin >= kInf ? kInf : hmin + 1;
+    if (nh > h) s.ht[n] = nh;
+}
+
+// mode 0: out-arc mask (distance to deficits); mode 1: in-arc mask
+// (reachability from excess).
+__global__ void __launch_bounds__(kBlock)
+k_mask(Graph s, int mode)
+{
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= s.N) return;
+    int j, y, x;
+    decode(s, n, j, y, x);
+    unsigned mk = 0;
+#pragma unroll
+    for (int d = 0; d < 14; ++d) {
+        int32_t r = mode == 0 ? out_res(s, n, j, y, x, d) : in_res(s, n, j, y, x, d);
+        mk |= (r > 0 ? 1u : 0u) << d;
+    }
+    s.mask[n] = (uint16_t)mk;
+}
+
+// Seeds: mode 0 -> ht = 1 at deficit nodes, INF elsewhere;
+//        mode 1 -> aux = 0 at excess nodes, INF elsewhere.
+__global__ void __launch_bounds__(kBlock)
+k_seed(Graph s, int mode)
+{
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= s.N) return;
+    int32_t e = s.ex[n];
+    if (mode == 0) s.ht[n] = e < 0 ? 1 : kInf;
+    else s.aux[n] = e > 0 ? 0 : kInf;
+}
+
+// One tiled min-plus relaxation pass: val(u) = min(val(u), val(w) + step)
+// over the neighbours w selected by mask(u), iterated inside the tile (in
+// LDS) until nothing changes or `max_iters` rounds have run.  Values only
+// decrease, so tiles can run in any order and the pass sequence converges
+// to the exact fixpoint.  flag <- 1 if any value changed.
+__global__ void __launch_bounds__(kBlock)
+k_relax(Graph s, int32_t *__restrict__ val, int step, int TW, int TH, int TJ,
+        int max_iters, int32_t *flag)
+{
+    extern __shared__ int32_t smem[];
+    __shared__ int s_flag;
+    const int HW = TW + 2, HH = TH + 2, HJ = TJ + 2;
+    const int n_halo = HW * HH * HJ, n_in = TW * TH * TJ;
+    int32_t *sv = smem;
+    uint16_t *sm = (uint16_t *)(smem + n_halo);
+    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH, j0 = blockIdx.z * TJ;
+    const int tid = threadIdx.x, nt = blockDim.x;
+
+    for (int i = tid; i < n_halo; i += nt) {
+        int lx = i % HW, t = i / HW, ly = t % HH, lj = t / HH;
+        int gx = x0 + lx - 1, gy = y0 + ly - 1, gj = j0 + lj - 1;
+        int32_t v = kInf;
+        if (gx >= 0 && gx < s.W && gy >= 0 && gy < s.H && gj >= 0 && gj < s.J)
+            v = val[((int64_t)gj * s.H + gy) * s.W + gx];
+        sv[i] = v;
+    }
+    for (int i = tid; i < n_in; i += nt) {
+        int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
+        int gx = x0 + lx, gy = y0 + ly, gj = j0 + lj;
+        uint16_t mk = 0;
+        if (gx < s.W && gy < s.H && gj < s.J) mk = s.mask[((int64_t)gj * s.H + gy) * s.W + gx];
+        sm[i] = mk;
+    }
+    int hoff[14];
+#pragma unroll
+    for (int d = 0; d < 14; ++d) hoff[d] = (dir_dj(d) * HH + dir_dy(d)) * HW + dir_dx(d);
+    __syncthreads();
+
+    bool changed_any = false;
+    for (int it = 0; it < max_iters; ++it) {
+        if (tid == 0) s_flag = 0;
+        __syncthreads();
+        bool ch = false;
+        for (int i = tid; i < n_in; i += nt) {
+            unsigned mk = sm[i];
+            if (!mk) continue;
+            int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
+            int hi = ((lj + 1) * HH + (ly + 1)) * HW + (lx + 1);
+            int32_t cur = sv[hi], best = cur;
+#pragma unroll
+            for (int d = 0; d < 14; ++d)
+                if (mk & (1u << d)) {
+                    int32_t nv = sv[hi + hoff[d]] + step;
+                    best = nv < best ? nv : best;
+                }
+            if (best < cur) { sv[hi] = best; ch = true; }
+        }
+        if (ch) s_flag = 1;
+        __syncthreads();
+        const int f = s_flag;
+        __syncthreads();
+        if (!f) break;
+        changed_any = true;
+    }
+    if (!changed_any) return;
+    for (int i = tid; i < n_in; i += nt) {
+        int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
+        int gx = x0 + lx, gy = y0 + ly, gj = j0 + lj;
+        if (gx < s.W && gy < s.H && gj < s.J)
+            val[((int64_t)gj * s.H + gy) * s.W + gx] = sv[((lj + 1) * HH + (ly + 1)) * HW + (lx + 1)];
+    }
+    if (tid == 0) *flag = 1;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_count_active(Graph s)
+{
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int a = 0;
+    if (n < s.N) a = (s.ex[n] > 0 && s.ht[n] < kInf) ? 1 : 0;
+    a = wave_sum_i32(a);
+    if (lane0() && a) atomicAdd(&s.hdr->active, a);
+}
+
+__global__ void k_zero_header(DevHeader *h, int what)
+{
+    int i = threadIdx.x;
+    if (what == 0) {                 // everything
+        if (i < kMaxFlags) h->flags[i] = 0;
+        if (i == 0) { h->active = 0; h->prefix_err = 0; h->pushes = 0; }
+    } else if (what == 1) {          // relaxation flags
+        if (i < kMaxFlags) h->flags[i] = 0;
+    } else if (what == 2) {          // active counter
+        if (i == 0) h->active = 0;
+    }
+}
+
+__global__ void k_zero_result(int64_t *r, DevHeader *h)
+{
+    if (threadIdx.x == 0) { r[0] = 0; r[1] = 0; if (h) h->prefix_err = 0; }
+}
+
+// Labels from the reachability values: X = reached nodes in the column,
+// which must form the prefix v_1..v_X.
+__global__ void __launch_bounds__(kBlock)
+k_labels(Graph s, int32_t *__restrict__ labels)
+{
+    int64_t site = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (site >= s.plane) return;
+    int X = 0;
+    bool gap = false, bad = false;
+    for (int j = 0; j < s.J; ++j) {
+        bool in = s.aux[(int64_t)j * s.plane + site] == 0;
+        if (in) { if (gap) bad = true; ++X; }
+        else gap = true;
+    }
+    labels[site] = X;
+    if (bad) atomicOr(&s.hdr->prefix_err, 1);
+}
+
+__device__ inline long long pair_term(int h1, int h2, int d)
+{
+    int a = d < 0 ? -d : d;
+    return (long long)h1 * a + (a > 1 ? (long long)h2 * (a - 1) : 0LL);
+}
+
+// E(X) from its definition, and the terminal capacity sum for the flow.
+__global__ void __launch_bounds__(kBlock)
+k_energy(const int32_t *__restrict__ cost, const int32_t *__restrict__ labels, int W, int H,
+         int m, int ph, int ih, int pv, int iv, int64_t *__restrict__ result)
+{
+    int64_t site = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    long long e = 0, tcap = 0;
+    const int64_t plane = (int64_t)W * H;
+    if (site < plane) {
+        int y = (int)(site / W), x = (int)(site - (int64_t)y * W);
+        int X = labels[site];
+        e = cost[(int64_t)X * plane + site];
+        if (x + 1 < W) e += pair_term(ph, ih, X - labels[site + 1]);
+        if (y + 1 < H) e += pair_term(pv, iv, X - labels[site + W]);
+        tcap = cost[(int64_t)(m - 1) * plane + site];
+    }
+    e = wave_sum_i64(e);
+    tcap = wave_sum_i64(tcap);
+    if (lane0()) {
+        atomicAdd((unsigned long long *)&result[0], (unsigned long long)e);
+        atomicAdd((unsigned long long *)&result[1], (unsigned long long)tcap);
+    }
+}
+
+// flow = sum of terminal capacities minus the deficits still unfilled.
+__global__ void __launch_bounds__(kBlock)
+k_deficit(Graph s, int64_t *__restrict__ result)
+{
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    long long d = 0;
+    if (n < s.N) { int32_t e = s.ex[n]; d = e < 0 ? -(long long)e : 0; }
+    d = wave_sum_i64(d);
+    if (lane0() && d) atomicAdd((unsigned long long *)&result[1], (unsigned long long)(-d));
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+struct Opts {
+    int period, max_sweeps, tw, th, tj, local_iters;
+};
+
+Opts resolve(const gc_solve_opts *o)
+{
+    Opts r{8, 1 << 20, 32, 4, 16, 64};
+    if (o) {
+        if (o->relabel_period > 0) r.period = o->relabel_period;
+        if (o->max_sweeps > 0) r.max_sweeps = o->max_sweeps;
+        if (o->tile_w > 0) r.tw = o->tile_w;
+        if (o->tile_h > 0) r.th = o->tile_h;
+        if (o->tile_j > 0) r.tj = o->tile_j;
+        if (o->local_iters > 0) r.local_iters = o->local_iters;
+    }
+    return r;
+}
+
+int check_opts(const Opts &o)
+{
+    size_t lds = (size_t)(o.tw + 2) * (o.th + 2) * (o.tj + 2) * 4 + (size_t)o.tw * o.th * o.tj * 2;
+    if (lds > 60 * 1024) return GC_E_ARG;
+    if (o.tw > 1024 || o.th > 1024 || o.tj > 1024) return GC_E_ARG;
+    return GC_OK;
+}
+
+// Runs relaxation passes until a pass changes nothing.  Returns the passes.
+int relax_to_fixpoint(const Graph &s, int32_t *val, int step, const Opts &o,
+                      hipStream_t st, int *passes_out)
+{
+    dim3 grid((unsigned)((s.W + o.tw - 1) / o.tw), (unsigned)((s.H + o.th - 1) / o.th),
+              (unsigned)((s.J + o.tj - 1) / o.tj));
+    size_t lds = (size_t)(o.tw + 2) * (o.th + 2) * (o.tj + 2) * 4 + (size_t)o.tw * o.th * o.tj * 2;
+    const int batch = 2;
+    int passes = 0;
+    for (;;) {
+        hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, st, s.hdr, 1);
+        for (int b = 0; b < batch; ++b)
+            hipLaunchKernelGGL(k_relax, grid, dim3(kBlock), lds, st, s, val, step, o.tw, o.th,
+                               o.tj, o.local_iters, &s.hdr->flags[b]);
+        if (!hip_ok(hipGetLastError())) return GC_E_HIP;
+        int32_t flags[kMaxFlags];
+        if (!hip_ok(hipMemcpyAsync(flags, s.hdr->flags, sizeof(int32_t) * batch,
+                                   hipMemcpyDeviceToHost, st)))
+            return GC_E_HIP;
+        if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
+        bool done = false;
+        for (int b = 0; b < batch; ++b) {
+            ++passes;
+            if (!flags[b]) { done = true; break; }
+        }
+        if (done) break;
+    }
+    *passes_out += passes;
+    return GC_OK;
+}
+
+int read_i32(const int32_t *dev, int32_t *host, hipStream_t st)
+{
+    if (!hip_ok(hipMemcpyAsync(host, dev, sizeof(int32_t), hipMemcpyDeviceToHost, st))) return GC_E_HIP;
+    if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
+    return GC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+GC_API const char *gc_status_str(int status)
+{
+    switch (status) {
+    case GC_OK: return "ok";
+    case GC_E_ARG: return "invalid argument";
+    case GC_E_SHAPE: return "invalid shape";
+    case GC_E_WORKSPACE: return "workspace too small or misaligned";
+    case GC_E_CAP_OVERFLOW: return "capacities could overflow int32";
+    case GC_E_NOT_CONVERGED: return "iteration cap reached before convergence";
+    case GC_E_HIP: return "HIP runtime error";
+    case GC_E_PREFIX: return "cut column is not a prefix";
+    }
+    return "unknown status";
+}
+
+GC_API int gc_last_hip_error(void) { return t_last_hip; }
+
+GC_API int gc_problem_check(const gc_problem *p)
+{
+    if (!p) return GC_E_ARG;
+    if (p->width < 0 || p->height < 0 || p->labels < 1) return GC_E_SHAPE;
+    if (p->cap < 0 || p->penalty_h < 0 || p->inhibit_h < 0 || p->penalty_v < 0 || p->inhibit_v < 0)
+        return GC_E_ARG;
+    int64_t n = node_count(p);
+    if (n >= (int64_t(1) << 29)) return GC_E_SHAPE;
+    int64_t sites = (int64_t)p->width * p->height;
+    int64_t big = p->cap;
+    int64_t pairs[4] = {2 * (int64_t)p->penalty_h, 2 * (int64_t)p->penalty_v, p->inhibit_h, p->inhibit_v};
+    for (int64_t v : pairs) big = v > big ? v : big;
+    if (sites * (int64_t)p->cap + big >= (int64_t(1) << 30)) return GC_E_CAP_OVERFLOW;
+    return GC_OK;
+}
+
+GC_API size_t gc_graph_footprint_bytes(const gc_problem *p)
+{
+    if (gc_problem_check(p) != GC_OK) return 0;
+    size_t n = (size_t)node_count(p);
+    return align256(sizeof(DevHeader)) + 11 * align256(n * 4) + align256(n * 2);
+}
+
+GC_API int stereo_cost_volume(const uint8_t *left, const uint8_t *right, const gc_problem *p,
+                              int32_t *cost, void *stream)
+{
+    int rc = gc_problem_check(p);
+    if (rc == GC_E_CAP_OVERFLOW) rc = GC_OK;     // the cost volume itself cannot overflow
+    if (rc != GC_OK) return rc;
+    if (!left || !right || !cost) return GC_E_ARG;
+    if (p->width == 0 || p->height == 0) return GC_OK;
+    if (p->height > 65535 || p->labels > 65535) return GC_E_SHAPE;
+    hipStream_t st = (hipStream_t)stream;
+    dim3 grid(grid_for(p->width), (unsigned)p->height, (unsigned)p->labels);
+    hipLaunchKernelGGL(k_cost_volume, grid, dim3(kBlock), 0, st, left, right, p->width,
+                       p->height, p->labels, p->cap, cost);
+    return hip_ok(hipGetLastError()) ? GC_OK : GC_E_HIP;
+}
+
+GC_API int graph_build(const gc_problem *p, const int32_t *cost, void *ws, size_t ws_bytes,
+                       gc_graph *g_out, void *stream)
+{
+    int rc = gc_problem_check(p);
+    if (rc != GC_OK) return rc;
+    if (!cost || !ws || !g_out) return GC_E_ARG;
+    if (((uintptr_t)ws & 255) != 0 || ws_bytes < gc_graph_footprint_bytes(p)) return GC_E_WORKSPACE;
+    g_out->ws = ws;
+    g_out->ws_bytes = ws_bytes;
+    g_out->p = *p;
+    Graph s = view(g_out);
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, st, s.hdr, 0);
+    if (s.N > 0)
+        hipLaunchKernelGGL(k_build, dim3(grid_for(s.N)), dim3(kBlock), 0, st, s, cost, p->labels);
+    return hip_ok(hipGetLastError()) ? GC_OK : GC_E_HIP;
+}
+
+static int graph_check(const gc_graph *g)
+{
+    if (!g || !g->ws) return GC_E_ARG;
+    int rc = gc_problem_check(&g->p);
+    if (rc != GC_OK) return rc;
+    if (g->ws_bytes < gc_graph_footprint_bytes(&g->p)) return GC_E_WORKSPACE;
+    return GC_OK;
+}
+
+GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *stats, void *stream)
+{
+    int rc = graph_check(g);
+    if (rc != GC_OK) return rc;
+    Opts opt = resolve(o);
+    if ((rc = check_opts(opt)) != GC_OK) return rc;
+    gc_solve_stats st_local;
+    memset(&st_local, 0, sizeof(st_local));
+    Graph s = view(g);
+    hipStream_t st = (hipStream_t)stream;
+    if (s.N == 0) {
+        if (stats) *stats = st_local;
+        return GC_OK;
+    }
+    const unsigned grid = grid_for(s.N);
+    int status = GC_OK;
+    for (;;) {
+        // exact global relabelling: BFS distance to the deficit nodes
+        hipLaunchKernelGGL(k_mask, dim3(grid), dim3(kBlock), 0, st, s, 0);
+        hipLaunchKernelGGL(k_seed, dim3(grid), dim3(kBlock), 0, st, s, 0);
+        if (!hip_ok(hipGetLastError())) return GC_E_HIP;
+        if ((rc = relax_to_fixpoint(s, s.ht, 1, opt, st, &st_local.bfs_passes)) != GC_OK) return rc;
+        st_local.global_relabels++;
+        hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, st, s.hdr, 2);
+        hipLaunchKernelGGL(k_count_active, dim3(grid), dim3(kBlock), 0, st, s);
+        int32_t active = 0;
+        if ((rc = read_i32(&s.hdr->active, &active, st)) != GC_OK) return rc;
+        st_local.active_last = active;
+        if (active == 0) break;
+        if (st_local.sweeps >= opt.max_sweeps) { status = GC_E_NOT_CONVERGED; break; }
+        for (int i = 0; i < opt.period; ++i) {
+            hipLaunchKernelGGL(k_push, dim3(grid), dim3(kBlock), 0, st, s);
+            hipLaunchKernelGGL(k_relabel, dim3(grid), dim3(kBlock), 0, st, s);
+            st_local.sweeps++;
+        }
+        if (!hip_ok(hipGetLastError())) return GC_E_HIP;
+    }
+    unsigned long long pushes = 0;
+    if (!hip_ok(hipMemcpyAsync(&pushes, &s.hdr->pushes, sizeof(pushes), hipMemcpyDeviceToHost, st)))
+        return GC_E_HIP;
+    if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
+    st_local.pushes = (int64_t)pushes;
+    if (stats) *stats = st_local;
+    return status;
+}
+
+GC_API int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *labels,
+                          int64_t *result, void *stream)
+{
+    int rc = graph_check(g);
+    if (rc != GC_OK) return rc;
+    if (!cost || !labels || !result) return GC_E_ARG;
+    Graph s = view(g);
+    hipStream_t st = (hipStream_t)stream;
+    const gc_problem &p = g->p;
+    Opts opt = resolve(nullptr);
+    int passes = 0;
+    if (s.N > 0) {
+        const unsigned grid = grid_for(s.N);
+        hipLaunchKernelGGL(k_mask, dim3(grid), dim3(kBlock), 0, st, s, 1);
+        hipLaunchKernelGGL(k_seed, dim3(grid), dim3(kBlock), 0, st, s, 1);
+        if (!hip_ok(hipGetLastError())) return GC_E_HIP;
+        if ((rc = relax_to_fixpoint(s, s.aux, 0, opt, st, &passes)) != GC_OK) return rc;
+    }
+    hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(64), 0, st, result, s.hdr);
+    if (s.plane > 0) {
+        hipLaunchKernelGGL(k_labels, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
+        hipLaunchKernelGGL(k_energy, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, cost, labels,
+                           p.width, p.height, p.labels, p.penalty_h, p.inhibit_h, p.penalty_v,
+                           p.inhibit_v, result);
+    }
+    if (s.N > 0)
+        hipLaunchKernelGGL(k_deficit, dim3(grid_for(s.N)), dim3(kBlock), 0, st, s, result);
+    if (!hip_ok(hipGetLastError())) return GC_E_HIP;
+    int32_t perr = 0;
+    if ((rc = read_i32(&s.hdr->prefix_err, &perr, st)) != GC_OK) return rc;
+    return perr ? GC_E_PREFIX : GC_OK;
+}

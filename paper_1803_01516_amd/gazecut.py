@@ -1,0 +1,187 @@
+"""Thin ctypes binding of the gazecut C ABI (include/gazecut.h).
+
+Argument marshalling only: every step of the path runs in the HIP library
+``libgazecut.so`` built from ``csrc/gazecut.hip``.  Device buffers are torch
+CUDA tensors (PyTorch is used for device memory and streams only).  There is
+no CPU fallback: if the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgazecut.so")
+
+GC_OK = 0
+GC_E_NOT_CONVERGED = -5
+
+
+class GcProblem(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in (
+        "width", "height", "labels", "cap", "penalty_h", "inhibit_h", "penalty_v", "inhibit_v")]
+
+
+class GcGraph(ctypes.Structure):
+    _fields_ = [("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t), ("p", GcProblem)]
+
+
+class GcSolveOpts(ctypes.Structure):
+    _fields_ = [("relabel_period", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("tile_j", ctypes.c_int32), ("local_iters", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+class GcSolveStats(ctypes.Structure):
+    _fields_ = [("pushes", ctypes.c_int64), ("sweeps", ctypes.c_int32),
+                ("global_relabels", ctypes.c_int32), ("bfs_passes", ctypes.c_int32),
+                ("active_last", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+
+    def as_dict(self):
+        return {"pushes": int(self.pushes), "sweeps": int(self.sweeps),
+                "global_relabels": int(self.global_relabels),
+                "bfs_passes": int(self.bfs_passes), "active_last": int(self.active_last)}
+
+
+EXPORTS = ("gc_status_str", "gc_last_hip_error", "gc_problem_check", "gc_graph_footprint_bytes",
+           "stereo_cost_volume", "graph_build", "maxflow_solve", "extract_labels")
+
+_lib = None
+
+
+class GazecutError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        lib = _lib
+        msg = lib.gc_status_str(status).decode() if lib is not None else str(status)
+        extra = ""
+        if lib is not None and status == -6:
+            extra = f" (hipError {lib.gc_last_hip_error()})"
+        super().__init__(f"{what}: {msg} [{status}]{extra}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH):
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"gazecut HIP library not found at {path}; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.gc_status_str.argtypes = [ctypes.c_int]
+    lib.gc_status_str.restype = ctypes.c_char_p
+    lib.gc_last_hip_error.argtypes = []
+    lib.gc_last_hip_error.restype = ctypes.c_int
+    lib.gc_problem_check.argtypes = [ctypes.POINTER(GcProblem)]
+    lib.gc_problem_check.restype = ctypes.c_int
+    lib.gc_graph_footprint_bytes.argtypes = [ctypes.POINTER(GcProblem)]
+    lib.gc_graph_footprint_bytes.restype = ctypes.c_size_t
+    lib.stereo_cost_volume.argtypes = [P, P, ctypes.POINTER(GcProblem), P, P]
+    lib.stereo_cost_volume.restype = ctypes.c_int
+    lib.graph_build.argtypes = [ctypes.POINTER(GcProblem), P, P, ctypes.c_size_t,
+                                ctypes.POINTER(GcGraph), P]
+    lib.graph_build.restype = ctypes.c_int
+    lib.maxflow_solve.argtypes = [ctypes.POINTER(GcGraph), ctypes.POINTER(GcSolveOpts),
+                                  ctypes.POINTER(GcSolveStats), P]
+    lib.maxflow_solve.restype = ctypes.c_int
+    lib.extract_labels.argtypes = [ctypes.POINTER(GcGraph), P, P, P, P]
+    lib.extract_labels.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def problem(width, height, labels, cap, penalty_h, inhibit_h, penalty_v=None, inhibit_v=None):
+    return GcProblem(int(width), int(height), int(labels), int(cap), int(penalty_h),
+                     int(inhibit_h), int(penalty_h if penalty_v is None else penalty_v),
+                     int(inhibit_h if inhibit_v is None else inhibit_v))
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check(rc: int, what: str):
+    if rc != GC_OK:
+        raise GazecutError(rc, what)
+
+
+def problem_check(p: GcProblem) -> int:
+    return load().gc_problem_check(ctypes.byref(p))
+
+
+def footprint_bytes(p: GcProblem) -> int:
+    return int(load().gc_graph_footprint_bytes(ctypes.byref(p)))
+
+
+def stereo_cost_volume(left, right, p: GcProblem, cost, stream=None):
+    """left/right: uint8 [h][w] CUDA tensors; cost: int32 [m][h][w] CUDA tensor."""
+    _check(load().stereo_cost_volume(ctypes.c_void_p(left.data_ptr()), ctypes.c_void_p(right.data_ptr()),
+                                     ctypes.byref(p), ctypes.c_void_p(cost.data_ptr()),
+                                     _stream_ptr(stream)), "stereo_cost_volume")
+
+
+@dataclass
+class Graph:
+    handle: GcGraph
+    ws: object          # the torch uint8 workspace tensor (kept alive here)
+
+
+def graph_build(p: GcProblem, cost, ws, stream=None) -> Graph:
+    """ws: uint8 CUDA tensor of at least footprint_bytes(p) bytes."""
+    g = GcGraph()
+    _check(load().graph_build(ctypes.byref(p), ctypes.c_void_p(cost.data_ptr()),
+                              ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                              ctypes.byref(g), _stream_ptr(stream)), "graph_build")
+    return Graph(g, ws)
+
+
+def maxflow_solve(graph: Graph, opts: GcSolveOpts | None = None, stream=None,
+                  allow_not_converged: bool = False) -> GcSolveStats:
+    st = GcSolveStats()
+    rc = load().maxflow_solve(ctypes.byref(graph.handle),
+                              ctypes.byref(opts) if opts is not None else None,
+                              ctypes.byref(st), _stream_ptr(stream))
+    if not (allow_not_converged and rc == GC_E_NOT_CONVERGED):
+        _check(rc, "maxflow_solve")
+    return st
+
+
+def extract_labels(graph: Graph, cost, labels, result, stream=None):
+    """labels: int32 [h][w] CUDA tensor; result: int64 [2] CUDA tensor
+    (energy, flow)."""
+    _check(load().extract_labels(ctypes.byref(graph.handle), ctypes.c_void_p(cost.data_ptr()),
+                                 ctypes.c_void_p(labels.data_ptr()), ctypes.c_void_p(result.data_ptr()),
+                                 _stream_ptr(stream)), "extract_labels")
+
+
+def alloc_workspace(p: GcProblem, device="cuda"):
+    import torch
+    nbytes = footprint_bytes(p)
+    if nbytes == 0:
+        _check(problem_check(p) or -1, "footprint")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def solve_pair(left, right, p: GcProblem, opts: GcSolveOpts | None = None, stream=None,
+               ws=None):
+    """Runs the whole path on one pair of uint8 CUDA tensors.  Returns
+    (labels tensor, cost tensor, energy, flow, stats)."""
+    import torch
+    dev = left.device
+    cost = torch.empty((p.labels, p.height, p.width), dtype=torch.int32, device=dev)
+    labels = torch.empty((p.height, p.width), dtype=torch.int32, device=dev)
+    result = torch.zeros(2, dtype=torch.int64, device=dev)
+    if ws is None:
+        ws = alloc_workspace(p, dev)
+    stereo_cost_volume(left, right, p, cost, stream)
+    g = graph_build(p, cost, ws, stream)
+    st = maxflow_solve(g, opts, stream)
+    extract_labels(g, cost, labels, result, stream)
+    r = result.cpu()
+    return labels, cost, int(r[0]), int(r[1]), st

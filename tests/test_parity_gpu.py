@@ -1,0 +1,165 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer work throughout, so the bar is bit-exact: cost volume, labels (the
+canonical minimal-source-side labelling), energy and max-flow value.
+"""
+import dataclasses
+import os
+
+import numpy as np
+import pytest
+
+from paper_1803_01516_amd import gazecut as gc
+from paper_1803_01516_amd import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gc.load()
+    return torch
+
+
+def _cost_gpu(torch, left, right, p):
+    L = torch.from_numpy(np.ascontiguousarray(left)).cuda()
+    R = torch.from_numpy(np.ascontiguousarray(right)).cuda()
+    cost = torch.empty((p.labels, p.height, p.width), dtype=torch.int32, device="cuda")
+    gc.stereo_cost_volume(L, R, p, cost)
+    return cost
+
+
+def _solve_cost_gpu(torch, cost_np, pen_h, inh_h, pen_v=None, inh_v=None, opts=None):
+    m, h, w = cost_np.shape
+    p = gc.problem(w, h, m, 30, pen_h, inh_h, pen_v, inh_v)
+    cost = torch.from_numpy(np.ascontiguousarray(cost_np, dtype=np.int32)).cuda()
+    ws = gc.alloc_workspace(p)
+    g = gc.graph_build(p, cost, ws)
+    st = gc.maxflow_solve(g, opts)
+    labels = torch.empty((h, w), dtype=torch.int32, device="cuda")
+    res = torch.zeros(2, dtype=torch.int64, device="cuda")
+    gc.extract_labels(g, cost, labels, res)
+    r = res.cpu().numpy()
+    return labels.cpu().numpy(), int(r[0]), int(r[1]), st
+
+
+def _check_against_oracle(orc, cost_np, lab, energy, flow, params):
+    ol, of, oe = orc.solve(cost_np, *params)
+    assert flow == of, f"flow {flow} != oracle {of}"
+    assert energy == oe, f"energy {energy} != oracle {oe}"
+    assert orc.energy(cost_np, lab, *params) == energy
+    bad = int((lab != ol).sum())
+    assert bad == 0, f"{bad} labels differ from the oracle"
+
+
+@pytest.mark.parametrize("spec,seed", [(sg.TINY, (1, 0)), (sg.MID, (2, 0)), (sg.LARGE, (3, 0)),
+                                       (sg.spec_like(sg.TINY, 37, 19, 5), (9, 9))])
+def test_cost_volume_bit_exact(torch_cuda, orc, spec, seed):
+    p_ = sg.make_pair(spec, seed)
+    p = gc.problem(spec.w, spec.h, spec.m, spec.cap, 1, 1023)
+    cost = _cost_gpu(torch_cuda, p_.left, p_.right, p).cpu().numpy()
+    ref = orc.cost_volume(p_.left, p_.right, spec.m, spec.cap)
+    assert (cost == ref).all()
+
+
+def _image_cases():
+    yield "tiny-s10", sg.TINY, (1, 0), (1, 1023, 1, 1023)
+    yield "tiny-s11", sg.TINY, (1, 1), (1, 1023, 1, 1023)
+    yield "tiny-lam2", sg.TINY, (1, 2), (2, 1023, 2, 1023)
+    yield "tiny-lam0-inh0", sg.TINY, (1, 3), (0, 0, 0, 0)
+    yield "tiny-soft", sg.TINY, (1, 4), (2, 3, 1, 2)
+    yield "tiny-inhibit-h-only", sg.TINY, (1, 5), (1, 1023, 1, 0)
+    yield "ragged-37x19x5", sg.spec_like(sg.TINY, 37, 19, 5), (9, 9), (1, 1023, 1, 1023)
+    yield "ragged-70x33x9", sg.spec_like(sg.MID, 70, 33, 9), (9, 8), (1, 1023, 1, 1023)
+    yield "tall-1x40x6", sg.spec_like(sg.TINY, 8, 40, 4), (9, 7), (1, 1023, 1, 1023)
+
+
+@pytest.mark.parametrize("name,spec,seed,params", list(_image_cases()),
+                         ids=[c[0] for c in _image_cases()])
+def test_solve_parity_small(torch_cuda, orc, name, spec, seed, params):
+    pr = sg.make_pair(spec, seed)
+    cost_np = orc.cost_volume(pr.left, pr.right, spec.m, spec.cap)
+    lab, energy, flow, st = _solve_cost_gpu(torch_cuda, cost_np, *params)
+    _check_against_oracle(orc, cost_np, lab, energy, flow, params)
+    assert st.active_last == 0
+
+
+def _cost_cases():
+    rng = np.random.default_rng(77)
+    tiny = sg.make_pair(sg.TINY, (1, 0))
+    import oracle
+    full = oracle.cost_volume(tiny.left, tiny.right, 8, 20)
+    yield "crop-3x3x4", np.ascontiguousarray(full[0:4, 22:25, 30:33]), (1, 1023, 1, 1023)
+    yield "random-45x29x7", rng.integers(0, 31, (7, 29, 45)).astype(np.int32), (1, 1023, 1, 1023)
+    yield "random-soft-50x21x11", rng.integers(0, 31, (11, 21, 50)).astype(np.int32), (3, 4, 2, 5)
+    yield "ties-33x17x6", rng.integers(0, 2, (6, 17, 33)).astype(np.int32), (1, 1, 1, 1)
+    yield "m2-20x9", rng.integers(0, 31, (2, 9, 20)).astype(np.int32), (1, 1023, 1, 1023)
+    yield "m1-13x5", rng.integers(0, 31, (1, 5, 13)).astype(np.int32), (1, 1023, 1, 1023)
+    yield "w1-1x30x5", rng.integers(0, 31, (5, 30, 1)).astype(np.int32), (1, 1023, 1, 1023)
+    yield "h1-300x1x12", rng.integers(0, 31, (12, 1, 300)).astype(np.int32), (1, 1023, 1, 1023)
+    yield "one-site-1x1x9", rng.integers(0, 31, (9, 1, 1)).astype(np.int32), (1, 1023, 1, 1023)
+
+
+@pytest.mark.parametrize("name,cost,params", list(_cost_cases()), ids=[c[0] for c in _cost_cases()])
+def test_solve_parity_cost_volumes(torch_cuda, orc, name, cost, params):
+    lab, energy, flow, st = _solve_cost_gpu(torch_cuda, cost, *params)
+    _check_against_oracle(orc, cost, lab, energy, flow, params)
+
+
+def test_empty_problem(torch_cuda):
+    p = gc.problem(0, 0, 8, 20, 1, 1023)
+    ws = torch_cuda.empty(max(256, gc.footprint_bytes(p)), dtype=torch_cuda.uint8, device="cuda")
+    cost = torch_cuda.empty(1, dtype=torch_cuda.int32, device="cuda")
+    g = gc.graph_build(p, cost, ws)
+    st = gc.maxflow_solve(g)
+    assert st.sweeps == 0
+    res = torch_cuda.zeros(2, dtype=torch_cuda.int64, device="cuda")
+    lab = torch_cuda.empty(1, dtype=torch_cuda.int32, device="cuda")
+    gc.extract_labels(g, cost, lab, res)
+    assert res.cpu().tolist() == [0, 0]
+
+
+@pytest.mark.parametrize("lam", [1, 2])
+def test_mid_parity_full_size(torch_cuda, orc, lam):
+    """384x288x16, the workload the benchmark times."""
+    pr = sg.make_pair(sg.MID, (2, 0))
+    p = gc.problem(sg.MID.w, sg.MID.h, sg.MID.m, sg.MID.cap, lam, 1023)
+    L = torch_cuda.from_numpy(pr.left).cuda()
+    R = torch_cuda.from_numpy(pr.right).cuda()
+    labels, cost, energy, flow, st = gc.solve_pair(L, R, p)
+    cost_np = cost.cpu().numpy()
+    assert (cost_np == orc.cost_volume(pr.left, pr.right, sg.MID.m, sg.MID.cap)).all()
+    _check_against_oracle(orc, cost_np, labels.cpu().numpy(), energy, flow, (lam, 1023, lam, 1023))
+
+
+def test_large_parity_full_size(torch_cuda, orc):
+    """450x375x64 against the stored oracle result (written by
+    tests/golden/make_golden.py, which calls only the oracle)."""
+    gold = np.load(os.path.join(GOLDEN, "large_450x375x64_seed3-0_lam1.npz"))
+    seed = tuple(int(v) for v in gold["seed"])
+    pr = sg.make_pair(sg.LARGE, seed)
+    p = gc.problem(sg.LARGE.w, sg.LARGE.h, sg.LARGE.m, sg.LARGE.cap, 1, 1023)
+    L = torch_cuda.from_numpy(pr.left).cuda()
+    R = torch_cuda.from_numpy(pr.right).cuda()
+    labels, cost, energy, flow, st = gc.solve_pair(L, R, p)
+    assert flow == int(gold["flow"]) and energy == int(gold["energy"])
+    assert (labels.cpu().numpy() == gold["labels"].astype(np.int32)).all()
+
+
+def test_repeat_solves_identical(torch_cuda, orc):
+    """The cut is schedule-independent: rebuilding and re-solving in place,
+    with different relabel periods and tiles, gives identical results."""
+    pr = sg.make_pair(sg.spec_like(sg.MID, 128, 96, 16), (5, 5))
+    cost_np = orc.cost_volume(pr.left, pr.right, 16, 30)
+    outs = []
+    for period, tw, th, tj in [(8, 32, 4, 16), (1, 16, 8, 8), (23, 64, 2, 4), (4, 8, 8, 32)]:
+        o = gc.GcSolveOpts(relabel_period=period, tile_w=tw, tile_h=th, tile_j=tj)
+        lab, e, f, st = _solve_cost_gpu(torch_cuda, cost_np, 1, 1023, opts=o)
+        outs.append((lab, e, f))
+    for lab, e, f in outs[1:]:
+        assert (lab == outs[0][0]).all() and e == outs[0][1] and f == outs[0][2]
+    _check_against_oracle(orc, cost_np, outs[0][0], outs[0][1], outs[0][2], (1, 1023, 1, 1023))
