@@ -1,0 +1,214 @@
+#!/usr/bin/env python3
+"""Benchmark of the gaze-line stereo graph-cut hot path on one MI355X.
+
+One step = the whole path on one synthetic stereo pair already resident in
+HBM: stereo_cost_volume -> graph_build -> maxflow_solve -> extract_labels
+(exact minimum cut, canonical labels, energy and flow).  The workload is the
+384x288 pair with 16 depth numbers (slanted-plane scene, truncated AD cap 30,
+penalty 1, inhibit 1023).
+
+Prints one JSON line (rank 0) with throughput in pairs/s, per-pair latency,
+Medge-pushes/s, a roofline entry for the dominant kernel (device time from
+HIP events recorded on the solve stream during the timed steps) and the CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("ms/stereo pair + Medge-pushes/s at 384×288×16; "
+          "batched pairs/s at p99 latency")
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--pairs", type=int, default=8, help="distinct resident pairs cycled")
+    ap.add_argument("--lam", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=3, help="pairs the oracle solves")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(kind: str, nodes: int, active_mean: float) -> float:
+    """Bytes a launch must move, per the kernel's own definition.
+
+    relax:   one tiled BFS pass reads every node's 16-bit arc mask and 32-bit
+             value and writes the value back: 10 B per node.
+    push:    reads excess and height of every node (8 B); an active node also
+             reads its 7 stored residual words, the 7 words its neighbours
+             store for it and 14 neighbour heights, and writes excess plus
+             up to 7 words: counted as 36 B read + 36 B written per active
+             node on top of the 8 B.
+    relabel: reads inflow, excess and height (12 B per node); an active node
+             also reads 14 residuals and 14 heights (112 B) and writes 4 B.
+    """
+    if kind == "relax":
+        return 10.0 * nodes
+    if kind == "push":
+        return 8.0 * nodes + 72.0 * active_mean
+    if kind == "relabel":
+        return 12.0 * nodes + 116.0 * active_mean
+    return 0.0
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(pairs shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1803_01516_amd import gazecut as gc
+    from paper_1803_01516_amd import scenegen as sg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    gc.load()
+    spec = sg.MID
+    p = gc.problem(spec.w, spec.h, spec.m, spec.cap, args.lam, spec.inhibit)
+    nodes = spec.w * spec.h * (spec.m - 1)
+
+    pairs = [sg.make_pair(spec, (2, i)) for i in range(args.pairs)]
+    lefts = [torch.from_numpy(q.left).to(dev) for q in pairs]
+    rights = [torch.from_numpy(q.right).to(dev) for q in pairs]
+    cost = torch.empty((spec.m, spec.h, spec.w), dtype=torch.int32, device=dev)
+    labels = torch.empty((spec.h, spec.w), dtype=torch.int32, device=dev)
+    result = torch.zeros(2, dtype=torch.int64, device=dev)
+    ws = gc.alloc_workspace(p, dev)
+    stream = torch.cuda.current_stream()
+    opts = gc.GcSolveOpts()
+    if not args.no_timing:
+        opts.flags = gc.GC_OPT_TIME_KERNELS
+
+    def step(i):
+        k = i % len(pairs)
+        gc.stereo_cost_volume(lefts[k], rights[k], p, cost, stream)
+        g = gc.graph_build(p, cost, ws, stream)
+        st = gc.maxflow_solve(g, opts, stream)
+        gc.extract_labels(g, cost, labels, result, stream)
+        return st
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    lat = []
+    stats = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        a = time.perf_counter()
+        stats.append(step(i).as_dict())
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - a)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    elapsed = t1 - t0
+    pushes = sum(s["pushes"] for s in stats)
+    ms_per_step = 1e3 * elapsed / args.steps
+    lat_ms = np.array(lat) * 1e3
+
+    # energy/flow of the last step and of the first pair, for the record
+    r = result.cpu().numpy()
+    last_pair = (args.steps - 1) % len(pairs)
+    err, pct = sg.eq2_error(pairs[last_pair].gt, labels.cpu().numpy())
+
+    roof = None
+    if not args.no_timing:
+        tot = {k: sum(s[f"{k}_ms"] for s in stats) for k in ("push", "relabel", "relax")}
+        launches = {k: sum(s[f"{k}_launches"] for s in stats) for k in ("push", "relabel", "relax")}
+        kind = max(tot, key=tot.get)
+        # mean active nodes per sweep is not recorded; bound it by pushes per sweep
+        sweeps = max(1, sum(s["sweeps"] for s in stats))
+        active_mean = min(float(nodes), pushes / sweeps)
+        per_launch_ms = tot[kind] / max(1, launches[kind])
+        bytes_launch = algorithmic_bytes(kind, nodes, active_mean)
+        achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": {"relax": "k_relax", "push": "k_push", "relabel": "k_relabel"}[kind],
+                "avg_launch_us": round(per_launch_ms * 1e3, 2),
+                "launches_per_step": round(launches[kind] / args.steps, 1),
+                "bytes_per_launch": int(bytes_launch),
+                "device_ms_per_step": {k: round(v / args.steps, 3) for k, v in tot.items()}}
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n = max(1, args.cpu_sample)
+        t = 0.0
+        ok = True
+        for i in range(n):
+            q = pairs[i % len(pairs)]
+            a = time.perf_counter()
+            c = oracle.cost_volume(q.left, q.right, spec.m, spec.cap)
+            lab, flow, energy = oracle.solve(c, args.lam, spec.inhibit)
+            t += time.perf_counter() - a
+            # the GPU result for the same pair
+            gc.stereo_cost_volume(lefts[i % len(pairs)], rights[i % len(pairs)], p, cost, stream)
+            g = gc.graph_build(p, cost, ws, stream)
+            gc.maxflow_solve(g, None, stream)
+            gc.extract_labels(g, cost, labels, result, stream)
+            rr = result.cpu().numpy()
+            ok = ok and int(rr[0]) == energy and int(rr[1]) == flow and \
+                bool((labels.cpu().numpy() == lab).all())
+        cpu = {"value": round(n / t, 4), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+               "sample": f"{n} pairs of the same 384x288x16 workload (seeds (2,0..{n - 1})), "
+                         f"cost volume + graph + FIFO push-relabel max-flow + labels, "
+                         f"single-threaded C -O2"}
+        parity = {"pairs_checked": n, "bit_exact": ok}
+
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps / elapsed, 3),
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "384x288 grayscale pair, 16 depth numbers, seeded 6-10 slanted "
+                               "planes, sigma 3, truncated AD cap 30, penalty "
+                               f"{args.lam}, inhibit 1023, exact min cut",
+                   "width": spec.w, "height": spec.h, "labels": spec.m, "nodes": nodes,
+                   "pairs_cycled": len(pairs)},
+        "ms_per_pair_p50": round(float(np.percentile(lat_ms, 50)), 3),
+        "ms_per_pair_p99": round(float(np.percentile(lat_ms, 99)), 3),
+        "medge_pushes_per_s": round(pushes / elapsed / 1e6, 2),
+        "sweeps_per_pair": round(sum(s["sweeps"] for s in stats) / args.steps, 2),
+        "global_relabels_per_pair": round(sum(s["global_relabels"] for s in stats) / args.steps, 2),
+        "bfs_passes_per_pair": round(sum(s["bfs_passes"] for s in stats) / args.steps, 2),
+        "energy_last": int(r[0]), "flow_last": int(r[1]),
+        "eq2_error_last": err, "pct_exact_last": pct,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -89,8 +89,21 @@ typedef struct {
     int32_t tile_h;           /* along y (default 4)                          */
     int32_t tile_j;           /* along the depth-number axis (default 16)     */
     int32_t local_iters;      /* max in-tile relaxation rounds per pass (default 64) */
-    int32_t reserved[2];
+    int32_t flags;            /* GC_OPT_* bits                                */
+    int32_t reserved;
 } gc_solve_opts;
+
+/* gc_solve_opts.flags: bracket every kernel launch of the solve with a pair
+ * of hipEvents on the solve stream and report summed device time per kernel
+ * class in gc_solve_stats (adds a few microseconds per launch). */
+#define GC_OPT_TIME_KERNELS 1
+
+/* Kernel classes of gc_solve_stats.kernel_ms / kernel_launches. */
+#define GC_K_PUSH 0           /* push sweep                                   */
+#define GC_K_RELABEL 1        /* relabel sweep (also merges inflow)           */
+#define GC_K_RELAX 2          /* one tiled BFS relaxation pass                */
+#define GC_K_OTHER 3          /* arc masks, BFS seeds, active count           */
+#define GC_K_CLASSES 4
 
 /* Solver statistics (host struct, filled by maxflow_solve). */
 typedef struct {
@@ -99,7 +112,8 @@ typedef struct {
     int32_t global_relabels;  /* exact distance recomputations                */
     int32_t bfs_passes;       /* tiled relaxation passes (all BFS work)       */
     int32_t active_last;      /* active nodes at the last check (0 when done) */
-    int32_t reserved[2];
+    int32_t kernel_launches[GC_K_CLASSES];  /* with GC_OPT_TIME_KERNELS only */
+    double kernel_ms[GC_K_CLASSES];         /* summed event time per class   */
 } gc_solve_stats;
 
 /* Human-readable name of a status code (static string). */

@@ -37,6 +37,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <vector>
 
 #include "gazecut.h"
 
@@ -79,10 +80,23 @@ struct DevHeader {
 };
 static_assert(sizeof(DevHeader) == 256, "header must stay 256 bytes");
 
+// Reduction targets, one 64-byte line each: a block adds its partial sum to
+// slot blockIdx % kSlots, so no single address takes every block's atomic.
+struct Slot {
+    unsigned long long pushes;
+    long long e0, e1;
+    int32_t active;
+    int32_t pad;
+    long long pad2[4];
+};
+static_assert(sizeof(Slot) == 64, "one slot per cache line");
+constexpr int kSlots = 256;
+
 struct Graph {
     int32_t *ex, *ht, *rd, *re, *rs, *rem, *rep, *rsm, *rsp, *ein, *aux;
     uint16_t *mask;
     DevHeader *hdr;
+    Slot *slots;
     int32_t W, H, J;
     int64_t plane, N;
     int32_t te, ts, ie, is;   // pair totals: 2*pen_h, 2*pen_v, inh_h, inh_v
@@ -112,6 +126,7 @@ Graph view(const gc_graph *g)
     s.N = s.plane * s.J;
     char *b = (char *)g->ws;
     s.hdr = (DevHeader *)b; b += align256(sizeof(DevHeader));
+    s.slots = (Slot *)b; b += align256(kSlots * sizeof(Slot));
     size_t w4 = align256((size_t)s.N * 4);
     int32_t **arr[] = {&s.ex, &s.ht, &s.rd, &s.re, &s.rs, &s.rem, &s.rep, &s.rsm, &s.rsp, &s.ein, &s.aux};
     for (int32_t **a : arr) { *a = (int32_t *)b; b += w4; }
@@ -140,6 +155,23 @@ __device__ inline long long wave_sum_i64(long long v)
 }
 
 __device__ inline bool lane0() { return (threadIdx.x & 63) == 0; }
+
+// Sum over a kBlock-thread block; the result is valid in thread 0.  Every
+// thread of the block must call it.
+template <typename T>
+__device__ inline T block_sum(T v)
+{
+    __shared__ T part[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (lane0()) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / 64; ++i) t += part[i];
+    return t;
+}
+
+__device__ inline Slot &my_slot(Slot *slots) { return slots[blockIdx.x & (kSlots - 1)]; }
 
 // Node counts stay below 2^29 (checked on the host), so 32-bit division is exact.
 __device__ inline void decode(const Graph &s, int64_t n, int &j, int &y, int &x)
@@ -275,6 +307,64 @@ k_build(Graph s, const int32_t *__restrict__ cost, int m)
     s.rsp[n] = 0;
 }
 
+// Which of the 14 arcs of node (j, y, x) exist, as a bit mask over Dir.
+__device__ inline unsigned arc_exists(const Graph &s, int j, int y, int x)
+{
+    const bool hE = x + 1 < s.W, hW = x > 0, hS = y + 1 < s.H, hN = y > 0;
+    const bool hU = j > 0, hD = j + 1 < s.J;
+    return (unsigned)hD << D_DOWN | (unsigned)hU << D_UP | (unsigned)hE << D_E |
+           (unsigned)hW << D_W | (unsigned)hS << D_S | (unsigned)hN << D_N |
+           (unsigned)(hE && hU) << D_EM | (unsigned)(hE && hD) << D_EP |
+           (unsigned)(hW && hU) << D_WM | (unsigned)(hW && hD) << D_WP |
+           (unsigned)(hS && hU) << D_SM | (unsigned)(hS && hD) << D_SP |
+           (unsigned)(hN && hU) << D_NM | (unsigned)(hN && hD) << D_NP;
+}
+
+// The stored pair word of the arc of node n in direction d.  For the
+// directions whose word lives at n the word is the out-residual; for the
+// others it is the residual of the opposite arc.
+__device__ inline int32_t *word_ptr(const Graph &s, int64_t n, int d)
+{
+    const int64_t P = s.plane, W = s.W;
+    switch (d) {
+    case D_DOWN: return s.rd + n;
+    case D_UP:   return s.rd + (n - P);
+    case D_E:    return s.re + n;
+    case D_W:    return s.re + (n - 1);
+    case D_S:    return s.rs + n;
+    case D_N:    return s.rs + (n - W);
+    case D_EM:   return s.rem + n;
+    case D_EP:   return s.rep + n;
+    case D_WM:   return s.rep + (n - P - 1);
+    case D_WP:   return s.rem + (n + P - 1);
+    case D_SM:   return s.rsm + n;
+    case D_SP:   return s.rsp + n;
+    case D_NM:   return s.rsp + (n - P - W);
+    default:     return s.rsm + (n + P - W);       // D_NP
+    }
+}
+
+__host__ __device__ constexpr bool word_is_forward(int d)
+{
+    return d == D_DOWN || d == D_E || d == D_S || d == D_EM || d == D_EP || d == D_SM || d == D_SP;
+}
+
+// Out-residual from the stored word.
+__device__ inline int32_t res_from_word(const Graph &s, int d, int32_t w)
+{
+    if (word_is_forward(d)) return w;
+    switch (d) {
+    case D_UP: return kInf;
+    case D_W:  return s.te - w;
+    case D_N:  return s.ts - w;
+    case D_WM: case D_WP: return s.ie - w;
+    default:   return s.is - w;                        // D_NM, D_NP
+    }
+}
+
+// Push sweep.  All 14 stored words and neighbour heights of an active node
+// are loaded up front (one round of memory latency); pushes then run in
+// registers and write the new words directly.
 __global__ void __launch_bounds__(kBlock)
 k_push(Graph s)
 {
@@ -286,26 +376,35 @@ k_push(Graph s)
         if (e > 0 && h < kInf) {
             int j, y, x;
             decode(s, n, j, y, x);
+            const unsigned ex_mask = arc_exists(s, j, y, x);
+            int32_t w[14], hv[14];
 #pragma unroll
             for (int d = 0; d < 14; ++d) {
-                if (e == 0) continue;
-                int32_t r = out_res(s, n, j, y, x, d);
-                if (r <= 0) continue;
-                int64_t v = nbr(s, n, d);
-                if (s.ht[v] != h - 1) continue;
-                int32_t delta = e < r ? e : r;
-                push_res(s, n, d, delta);
-                atomicAdd(&s.ein[v], delta);
-                e -= delta;
-                ++cnt;
+                const bool ok = (ex_mask >> d) & 1u;
+                w[d] = ok ? *word_ptr(s, n, d) : 0;
+                hv[d] = ok ? s.ht[nbr(s, n, d)] : kInf;
+            }
+#pragma unroll
+            for (int d = 0; d < 14; ++d) {
+                if (!((ex_mask >> d) & 1u)) continue;
+                const int32_t r = res_from_word(s, d, w[d]);
+                if (e > 0 && r > 0 && hv[d] == h - 1) {
+                    const int32_t delta = e < r ? e : r;
+                    *word_ptr(s, n, d) = word_is_forward(d) ? w[d] - delta : w[d] + delta;
+                    atomicAdd(&s.ein[nbr(s, n, d)], delta);
+                    e -= delta;
+                    ++cnt;
+                }
             }
             s.ex[n] = e;
         }
     }
-    cnt = wave_sum_i32(cnt);
-    if (lane0() && cnt) atomicAdd(&s.hdr->pushes, (unsigned long long)cnt);
+    cnt = block_sum(cnt);
+    if (threadIdx.x == 0 && cnt) atomicAdd(&my_slot(s.slots).pushes, (unsigned long long)cnt);
 }
 
+// Relabel sweep: merges the inflow of the push sweep, then lifts every
+// active node to one above its lowest residual neighbour.
 __global__ void __launch_bounds__(kBlock)
 k_relabel(Graph s)
 {
@@ -322,14 +421,20 @@ k_relabel(Graph s)
     if (e <= 0 || h >= kInf) return;
     int j, y, x;
     decode(s, n, j, y, x);
-    int32_t hmin = kInf;
+    const unsigned ex_mask = arc_exists(s, j, y, x);
+    int32_t w[14], hv[14];
 #pragma unroll
     for (int d = 0; d < 14; ++d) {
-        if (out_res(s, n, j, y, x, d) <= 0) continue;
-        int32_t hv = s.ht[nbr(s, n, d)];
-        hmin = hv < hmin ? hv : hmin;
+        const bool ok = (ex_mask >> d) & 1u;
+        w[d] = ok ? *word_ptr(s, n, d) : 0;
+        hv[d] = ok ? s.ht[nbr(s, n, d)] : kInf;
     }
-    int32_t nh = hmin >= kInf ? kInf : hmin + 1;
+    int32_t hmin = kInf;
+#pragma unroll
+    for (int d = 0; d < 14; ++d)
+        if (((ex_mask >> d) & 1u) && res_from_word(s, d, w[d]) > 0)
+            hmin = hv[d] < hmin ? hv[d] : hmin;
+    const int32_t nh = hmin >= kInf ? kInf : hmin + 1;
     if (nh > h) s.ht[n] = nh;
 }
 
@@ -367,74 +472,89 @@ k_seed(Graph s, int mode)
 // over the neighbours w selected by mask(u), iterated inside the tile (in
 // LDS) until nothing changes or `max_iters` rounds have run.  Values only
 // decrease, so tiles can run in any order and the pass sequence converges
-// to the exact fixpoint.  flag <- 1 if any value changed.
+// to the exact fixpoint.  Each thread owns NI/256 fixed nodes whose masks
+// and LDS slots stay in registers; only values that changed are written
+// back, and flag <- 1 if any did.
+template <int TW, int TH, int TJ>
 __global__ void __launch_bounds__(kBlock)
-k_relax(Graph s, int32_t *__restrict__ val, int step, int TW, int TH, int TJ,
-        int max_iters, int32_t *flag)
+k_relax(Graph s, int32_t *__restrict__ val, int step, int max_iters, int32_t *flag)
 {
-    extern __shared__ int32_t smem[];
+    constexpr int HW = TW + 2, HH = TH + 2, HJ = TJ + 2;
+    constexpr int NH = HW * HH * HJ, NI = TW * TH * TJ;
+    static_assert(NI % kBlock == 0, "tile must hold a multiple of the block size");
+    constexpr int NPT = NI / kBlock;
+    __shared__ int32_t sv[NH];
     __shared__ int s_flag;
-    const int HW = TW + 2, HH = TH + 2, HJ = TJ + 2;
-    const int n_halo = HW * HH * HJ, n_in = TW * TH * TJ;
-    int32_t *sv = smem;
-    uint16_t *sm = (uint16_t *)(smem + n_halo);
     const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH, j0 = blockIdx.z * TJ;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x;
 
-    for (int i = tid; i < n_halo; i += nt) {
-        int lx = i % HW, t = i / HW, ly = t % HH, lj = t / HH;
-        int gx = x0 + lx - 1, gy = y0 + ly - 1, gj = j0 + lj - 1;
+    for (int i = tid; i < NH; i += kBlock) {
+        const int lx = i % HW, t = i / HW, ly = t % HH, lj = t / HH;
+        const int gx = x0 + lx - 1, gy = y0 + ly - 1, gj = j0 + lj - 1;
         int32_t v = kInf;
         if (gx >= 0 && gx < s.W && gy >= 0 && gy < s.H && gj >= 0 && gj < s.J)
             v = val[((int64_t)gj * s.H + gy) * s.W + gx];
         sv[i] = v;
     }
-    for (int i = tid; i < n_in; i += nt) {
-        int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
-        int gx = x0 + lx, gy = y0 + ly, gj = j0 + lj;
-        uint16_t mk = 0;
-        if (gx < s.W && gy < s.H && gj < s.J) mk = s.mask[((int64_t)gj * s.H + gy) * s.W + gx];
-        sm[i] = mk;
-    }
-    int hoff[14];
+    unsigned mk[NPT];
+    int hid[NPT];
+    int32_t orig[NPT];
 #pragma unroll
-    for (int d = 0; d < 14; ++d) hoff[d] = (dir_dj(d) * HH + dir_dy(d)) * HW + dir_dx(d);
+    for (int k = 0; k < NPT; ++k) {
+        const int i = tid + k * kBlock;
+        const int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
+        const int gx = x0 + lx, gy = y0 + ly, gj = j0 + lj;
+        mk[k] = (gx < s.W && gy < s.H && gj < s.J) ? s.mask[((int64_t)gj * s.H + gy) * s.W + gx] : 0u;
+        hid[k] = ((lj + 1) * HH + (ly + 1)) * HW + (lx + 1);
+    }
+    constexpr int hoff[14] = {
+        (dir_dj(0) * HH + dir_dy(0)) * HW + dir_dx(0),   (dir_dj(1) * HH + dir_dy(1)) * HW + dir_dx(1),
+        (dir_dj(2) * HH + dir_dy(2)) * HW + dir_dx(2),   (dir_dj(3) * HH + dir_dy(3)) * HW + dir_dx(3),
+        (dir_dj(4) * HH + dir_dy(4)) * HW + dir_dx(4),   (dir_dj(5) * HH + dir_dy(5)) * HW + dir_dx(5),
+        (dir_dj(6) * HH + dir_dy(6)) * HW + dir_dx(6),   (dir_dj(7) * HH + dir_dy(7)) * HW + dir_dx(7),
+        (dir_dj(8) * HH + dir_dy(8)) * HW + dir_dx(8),   (dir_dj(9) * HH + dir_dy(9)) * HW + dir_dx(9),
+        (dir_dj(10) * HH + dir_dy(10)) * HW + dir_dx(10), (dir_dj(11) * HH + dir_dy(11)) * HW + dir_dx(11),
+        (dir_dj(12) * HH + dir_dy(12)) * HW + dir_dx(12), (dir_dj(13) * HH + dir_dy(13)) * HW + dir_dx(13)};
     __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) orig[k] = sv[hid[k]];
 
-    bool changed_any = false;
     for (int it = 0; it < max_iters; ++it) {
         if (tid == 0) s_flag = 0;
         __syncthreads();
         bool ch = false;
-        for (int i = tid; i < n_in; i += nt) {
-            unsigned mk = sm[i];
-            if (!mk) continue;
-            int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
-            int hi = ((lj + 1) * HH + (ly + 1)) * HW + (lx + 1);
-            int32_t cur = sv[hi], best = cur;
+#pragma unroll
+        for (int k = 0; k < NPT; ++k) {
+            const unsigned m = mk[k];
+            if (!m) continue;
+            const int32_t cur = sv[hid[k]];
+            int32_t best = cur;
 #pragma unroll
             for (int d = 0; d < 14; ++d)
-                if (mk & (1u << d)) {
-                    int32_t nv = sv[hi + hoff[d]] + step;
+                if ((m >> d) & 1u) {
+                    const int32_t nv = sv[hid[k] + hoff[d]] + step;
                     best = nv < best ? nv : best;
                 }
-            if (best < cur) { sv[hi] = best; ch = true; }
+            if (best < cur) { sv[hid[k]] = best; ch = true; }
         }
         if (ch) s_flag = 1;
         __syncthreads();
         const int f = s_flag;
         __syncthreads();
         if (!f) break;
-        changed_any = true;
     }
-    if (!changed_any) return;
-    for (int i = tid; i < n_in; i += nt) {
-        int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
-        int gx = x0 + lx, gy = y0 + ly, gj = j0 + lj;
-        if (gx < s.W && gy < s.H && gj < s.J)
-            val[((int64_t)gj * s.H + gy) * s.W + gx] = sv[((lj + 1) * HH + (ly + 1)) * HW + (lx + 1)];
+    bool wrote = false;
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+        const int32_t v = sv[hid[k]];
+        if (v != orig[k]) {
+            const int i = tid + k * kBlock;
+            const int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
+            val[((int64_t)(j0 + lj) * s.H + (y0 + ly)) * s.W + (x0 + lx)] = v;
+            wrote = true;
+        }
     }
-    if (tid == 0) *flag = 1;
+    if (wrote) *flag = 1;
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -443,8 +563,8 @@ k_count_active(Graph s)
     int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int a = 0;
     if (n < s.N) a = (s.ex[n] > 0 && s.ht[n] < kInf) ? 1 : 0;
-    a = wave_sum_i32(a);
-    if (lane0() && a) atomicAdd(&s.hdr->active, a);
+    a = block_sum(a);
+    if (threadIdx.x == 0 && a) atomicAdd(&my_slot(s.slots).active, a);
 }
 
 __global__ void k_zero_header(DevHeader *h, int what)
@@ -492,7 +612,7 @@ __device__ inline long long pair_term(int h1, int h2, int d)
 // E(X) from its definition, and the terminal capacity sum for the flow.
 __global__ void __launch_bounds__(kBlock)
 k_energy(const int32_t *__restrict__ cost, const int32_t *__restrict__ labels, int W, int H,
-         int m, int ph, int ih, int pv, int iv, int64_t *__restrict__ result)
+         int m, int ph, int ih, int pv, int iv, Slot *__restrict__ slots)
 {
     int64_t site = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     long long e = 0, tcap = 0;
@@ -505,23 +625,56 @@ k_energy(const int32_t *__restrict__ cost, const int32_t *__restrict__ labels, i
         if (y + 1 < H) e += pair_term(pv, iv, X - labels[site + W]);
         tcap = cost[(int64_t)(m - 1) * plane + site];
     }
-    e = wave_sum_i64(e);
-    tcap = wave_sum_i64(tcap);
-    if (lane0()) {
-        atomicAdd((unsigned long long *)&result[0], (unsigned long long)e);
-        atomicAdd((unsigned long long *)&result[1], (unsigned long long)tcap);
+    e = block_sum(e);
+    __syncthreads();
+    tcap = block_sum(tcap);
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long *)&my_slot(slots).e0, (unsigned long long)e);
+        atomicAdd((unsigned long long *)&my_slot(slots).e1, (unsigned long long)tcap);
     }
 }
 
 // flow = sum of terminal capacities minus the deficits still unfilled.
 __global__ void __launch_bounds__(kBlock)
-k_deficit(Graph s, int64_t *__restrict__ result)
+k_deficit(Graph s)
 {
     int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     long long d = 0;
     if (n < s.N) { int32_t e = s.ex[n]; d = e < 0 ? -(long long)e : 0; }
-    d = wave_sum_i64(d);
-    if (lane0() && d) atomicAdd((unsigned long long *)&result[1], (unsigned long long)(-d));
+    d = block_sum(d);
+    if (threadIdx.x == 0 && d)
+        atomicAdd((unsigned long long *)&my_slot(s.slots).e1, (unsigned long long)(-d));
+}
+
+// Clears slot fields: what 0 = everything, 1 = active, 2 = energy/flow.
+__global__ void __launch_bounds__(kSlots)
+k_zero_slots(Slot *slots, int what)
+{
+    Slot &sl = slots[threadIdx.x];
+    if (what == 0) { sl.pushes = 0; sl.active = 0; sl.e0 = 0; sl.e1 = 0; }
+    else if (what == 1) sl.active = 0;
+    else { sl.e0 = 0; sl.e1 = 0; }
+}
+
+// Folds the slots: what 0 -> hdr->active, 1 -> hdr->pushes,
+// 2 -> result[0] = energy, result[1] = flow.
+__global__ void __launch_bounds__(kSlots)
+k_fold_slots(const Slot *slots, DevHeader *hdr, int what, int64_t *result)
+{
+    static_assert(kSlots == kBlock, "one thread per slot");
+    const Slot &sl = slots[threadIdx.x];
+    if (what == 0) {
+        int a = block_sum(sl.active);
+        if (threadIdx.x == 0) hdr->active = a;
+    } else if (what == 1) {
+        unsigned long long p = block_sum(sl.pushes);
+        if (threadIdx.x == 0) hdr->pushes = p;
+    } else {
+        long long e0 = block_sum(sl.e0);
+        __syncthreads();
+        long long e1 = block_sum(sl.e1);
+        if (threadIdx.x == 0) { result[0] = e0; result[1] = e1; }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -529,12 +682,12 @@ k_deficit(Graph s, int64_t *__restrict__ result)
 // ---------------------------------------------------------------------------
 
 struct Opts {
-    int period, max_sweeps, tw, th, tj, local_iters;
+    int period, max_sweeps, tw, th, tj, local_iters, flags;
 };
 
 Opts resolve(const gc_solve_opts *o)
 {
-    Opts r{8, 1 << 20, 32, 4, 16, 64};
+    Opts r{8, 1 << 20, 8, 8, 16, 8, 0};
     if (o) {
         if (o->relabel_period > 0) r.period = o->relabel_period;
         if (o->max_sweeps > 0) r.max_sweeps = o->max_sweeps;
@@ -542,44 +695,111 @@ Opts resolve(const gc_solve_opts *o)
         if (o->tile_h > 0) r.th = o->tile_h;
         if (o->tile_j > 0) r.tj = o->tile_j;
         if (o->local_iters > 0) r.local_iters = o->local_iters;
+        r.flags = o->flags;
     }
     return r;
 }
 
+typedef void (*RelaxFn)(Graph, int32_t *, int, int, int32_t *);
+
+// Tile shapes compiled for the relaxation pass (x, y, depth layers).
+#define GC_RELAX_SHAPES(X)                                                        \
+    X(8, 8, 16) X(16, 8, 16) X(16, 16, 16) X(32, 8, 16) X(32, 4, 16) X(64, 4, 16) \
+    X(16, 16, 8) X(32, 8, 8) X(32, 16, 8) X(64, 8, 8) X(16, 16, 4) X(32, 16, 4)   \
+    X(32, 32, 4) X(64, 16, 4) X(8, 8, 32) X(16, 8, 32) X(16, 16, 32)
+
+RelaxFn relax_kernel(int tw, int th, int tj)
+{
+#define GC_RELAX_CASE(a, b, c) \
+    if (tw == a && th == b && tj == c) return k_relax<a, b, c>;
+    GC_RELAX_SHAPES(GC_RELAX_CASE)
+#undef GC_RELAX_CASE
+    return nullptr;
+}
+
 int check_opts(const Opts &o)
 {
-    size_t lds = (size_t)(o.tw + 2) * (o.th + 2) * (o.tj + 2) * 4 + (size_t)o.tw * o.th * o.tj * 2;
-    if (lds > 60 * 1024) return GC_E_ARG;
-    if (o.tw > 1024 || o.th > 1024 || o.tj > 1024) return GC_E_ARG;
+    if (!relax_kernel(o.tw, o.th, o.tj)) return GC_E_ARG;
     return GC_OK;
 }
 
-// Runs relaxation passes until a pass changes nothing.  Returns the passes.
+// Optional per-launch device timing: a pair of events around each launch on
+// the solve stream, summed per kernel class once the stream has drained.
+thread_local std::vector<hipEvent_t> t_events;
+
+struct Launcher {
+    hipStream_t st;
+    bool timing;
+    std::vector<int> cls;
+
+    hipEvent_t event(size_t i)
+    {
+        while (t_events.size() <= i) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            t_events.push_back(e);
+        }
+        return t_events[i];
+    }
+
+    template <typename F>
+    void run(int klass, F &&launch)
+    {
+        if (!timing) { launch(); return; }
+        hipEvent_t a = event(2 * cls.size()), b = event(2 * cls.size() + 1);
+        if (!a || !b) { launch(); return; }
+        (void)hipEventRecord(a, st);
+        launch();
+        (void)hipEventRecord(b, st);
+        cls.push_back(klass);
+    }
+
+    // Call after the stream has been synchronised.
+    void collect(gc_solve_stats *out)
+    {
+        for (size_t i = 0; i < cls.size(); ++i) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, t_events[2 * i], t_events[2 * i + 1]) == hipSuccess) {
+                out->kernel_ms[cls[i]] += ms;
+                out->kernel_launches[cls[i]]++;
+            }
+        }
+        cls.clear();
+    }
+};
+
+// Runs relaxation passes until a pass changes nothing.  Passes are issued in
+// growing batches with one flag read-back per batch.
 int relax_to_fixpoint(const Graph &s, int32_t *val, int step, const Opts &o,
-                      hipStream_t st, int *passes_out)
+                      Launcher &L, int *passes_out)
 {
     dim3 grid((unsigned)((s.W + o.tw - 1) / o.tw), (unsigned)((s.H + o.th - 1) / o.th),
               (unsigned)((s.J + o.tj - 1) / o.tj));
-    size_t lds = (size_t)(o.tw + 2) * (o.th + 2) * (o.tj + 2) * 4 + (size_t)o.tw * o.th * o.tj * 2;
-    const int batch = 2;
-    int passes = 0;
+    RelaxFn fn = relax_kernel(o.tw, o.th, o.tj);
+    if (!fn) return GC_E_ARG;
+    const int max_passes = 1 << 22;
+    int passes = 0, batch = 2;
     for (;;) {
-        hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, st, s.hdr, 1);
+        hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, L.st, s.hdr, 1);
         for (int b = 0; b < batch; ++b)
-            hipLaunchKernelGGL(k_relax, grid, dim3(kBlock), lds, st, s, val, step, o.tw, o.th,
-                               o.tj, o.local_iters, &s.hdr->flags[b]);
+            L.run(GC_K_RELAX, [&] {
+                hipLaunchKernelGGL(fn, grid, dim3(kBlock), 0, L.st, s, val, step, o.local_iters,
+                                   &s.hdr->flags[b]);
+            });
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
         int32_t flags[kMaxFlags];
         if (!hip_ok(hipMemcpyAsync(flags, s.hdr->flags, sizeof(int32_t) * batch,
-                                   hipMemcpyDeviceToHost, st)))
+                                   hipMemcpyDeviceToHost, L.st)))
             return GC_E_HIP;
-        if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
+        if (!hip_ok(hipStreamSynchronize(L.st))) return GC_E_HIP;
         bool done = false;
         for (int b = 0; b < batch; ++b) {
             ++passes;
             if (!flags[b]) { done = true; break; }
         }
         if (done) break;
+        if (passes >= max_passes) return GC_E_NOT_CONVERGED;
+        batch = batch * 2 > 8 ? 8 : batch * 2;
     }
     *passes_out += passes;
     return GC_OK;
@@ -635,7 +855,8 @@ GC_API size_t gc_graph_footprint_bytes(const gc_problem *p)
 {
     if (gc_problem_check(p) != GC_OK) return 0;
     size_t n = (size_t)node_count(p);
-    return align256(sizeof(DevHeader)) + 11 * align256(n * 4) + align256(n * 2);
+    return align256(sizeof(DevHeader)) + align256(kSlots * sizeof(Slot)) + 11 * align256(n * 4) +
+           align256(n * 2);
 }
 
 GC_API int stereo_cost_volume(const uint8_t *left, const uint8_t *right, const gc_problem *p,
@@ -667,6 +888,7 @@ GC_API int graph_build(const gc_problem *p, const int32_t *cost, void *ws, size_
     Graph s = view(g_out);
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, st, s.hdr, 0);
+    hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 0);
     if (s.N > 0)
         hipLaunchKernelGGL(k_build, dim3(grid_for(s.N)), dim3(kBlock), 0, st, s, cost, p->labels);
     return hip_ok(hipGetLastError()) ? GC_OK : GC_E_HIP;
@@ -695,34 +917,38 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
         if (stats) *stats = st_local;
         return GC_OK;
     }
+    Launcher L{st, (opt.flags & GC_OPT_TIME_KERNELS) != 0, {}};
     const unsigned grid = grid_for(s.N);
     int status = GC_OK;
     for (;;) {
         // exact global relabelling: BFS distance to the deficit nodes
-        hipLaunchKernelGGL(k_mask, dim3(grid), dim3(kBlock), 0, st, s, 0);
-        hipLaunchKernelGGL(k_seed, dim3(grid), dim3(kBlock), 0, st, s, 0);
+        L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_mask, dim3(grid), dim3(kBlock), 0, st, s, 0); });
+        L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_seed, dim3(grid), dim3(kBlock), 0, st, s, 0); });
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
-        if ((rc = relax_to_fixpoint(s, s.ht, 1, opt, st, &st_local.bfs_passes)) != GC_OK) return rc;
+        if ((rc = relax_to_fixpoint(s, s.ht, 1, opt, L, &st_local.bfs_passes)) != GC_OK) return rc;
         st_local.global_relabels++;
-        hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, st, s.hdr, 2);
-        hipLaunchKernelGGL(k_count_active, dim3(grid), dim3(kBlock), 0, st, s);
+        hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 1);
+        L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_count_active, dim3(grid), dim3(kBlock), 0, st, s); });
+        hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, s.slots, s.hdr, 0, nullptr);
         int32_t active = 0;
         if ((rc = read_i32(&s.hdr->active, &active, st)) != GC_OK) return rc;
         st_local.active_last = active;
         if (active == 0) break;
         if (st_local.sweeps >= opt.max_sweeps) { status = GC_E_NOT_CONVERGED; break; }
         for (int i = 0; i < opt.period; ++i) {
-            hipLaunchKernelGGL(k_push, dim3(grid), dim3(kBlock), 0, st, s);
-            hipLaunchKernelGGL(k_relabel, dim3(grid), dim3(kBlock), 0, st, s);
+            L.run(GC_K_PUSH, [&] { hipLaunchKernelGGL(k_push, dim3(grid), dim3(kBlock), 0, st, s); });
+            L.run(GC_K_RELABEL, [&] { hipLaunchKernelGGL(k_relabel, dim3(grid), dim3(kBlock), 0, st, s); });
             st_local.sweeps++;
         }
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
     }
     unsigned long long pushes = 0;
+    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, s.slots, s.hdr, 1, nullptr);
     if (!hip_ok(hipMemcpyAsync(&pushes, &s.hdr->pushes, sizeof(pushes), hipMemcpyDeviceToHost, st)))
         return GC_E_HIP;
     if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
     st_local.pushes = (int64_t)pushes;
+    L.collect(&st_local);
     if (stats) *stats = st_local;
     return status;
 }
@@ -737,23 +963,26 @@ GC_API int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *label
     hipStream_t st = (hipStream_t)stream;
     const gc_problem &p = g->p;
     Opts opt = resolve(nullptr);
+    Launcher L{st, false, {}};
     int passes = 0;
     if (s.N > 0) {
         const unsigned grid = grid_for(s.N);
         hipLaunchKernelGGL(k_mask, dim3(grid), dim3(kBlock), 0, st, s, 1);
         hipLaunchKernelGGL(k_seed, dim3(grid), dim3(kBlock), 0, st, s, 1);
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
-        if ((rc = relax_to_fixpoint(s, s.aux, 0, opt, st, &passes)) != GC_OK) return rc;
+        if ((rc = relax_to_fixpoint(s, s.aux, 0, opt, L, &passes)) != GC_OK) return rc;
     }
     hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(64), 0, st, result, s.hdr);
+    hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 2);
     if (s.plane > 0) {
         hipLaunchKernelGGL(k_labels, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
         hipLaunchKernelGGL(k_energy, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, cost, labels,
                            p.width, p.height, p.labels, p.penalty_h, p.inhibit_h, p.penalty_v,
-                           p.inhibit_v, result);
+                           p.inhibit_v, s.slots);
     }
     if (s.N > 0)
-        hipLaunchKernelGGL(k_deficit, dim3(grid_for(s.N)), dim3(kBlock), 0, st, s, result);
+        hipLaunchKernelGGL(k_deficit, dim3(grid_for(s.N)), dim3(kBlock), 0, st, s);
+    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, s.slots, s.hdr, 2, result);
     if (!hip_ok(hipGetLastError())) return GC_E_HIP;
     int32_t perr = 0;
     if ((rc = read_i32(&s.hdr->prefix_err, &perr, st)) != GC_OK) return rc;

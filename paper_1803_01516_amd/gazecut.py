@@ -31,18 +31,27 @@ class GcSolveOpts(ctypes.Structure):
     _fields_ = [("relabel_period", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("tile_j", ctypes.c_int32), ("local_iters", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+GC_OPT_TIME_KERNELS = 1
+KERNEL_CLASSES = ("push", "relabel", "relax", "other")
 
 
 class GcSolveStats(ctypes.Structure):
     _fields_ = [("pushes", ctypes.c_int64), ("sweeps", ctypes.c_int32),
                 ("global_relabels", ctypes.c_int32), ("bfs_passes", ctypes.c_int32),
-                ("active_last", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("active_last", ctypes.c_int32), ("kernel_launches", ctypes.c_int32 * 4),
+                ("kernel_ms", ctypes.c_double * 4)]
 
     def as_dict(self):
-        return {"pushes": int(self.pushes), "sweeps": int(self.sweeps),
-                "global_relabels": int(self.global_relabels),
-                "bfs_passes": int(self.bfs_passes), "active_last": int(self.active_last)}
+        d = {"pushes": int(self.pushes), "sweeps": int(self.sweeps),
+             "global_relabels": int(self.global_relabels),
+             "bfs_passes": int(self.bfs_passes), "active_last": int(self.active_last)}
+        for i, k in enumerate(KERNEL_CLASSES):
+            d[f"{k}_launches"] = int(self.kernel_launches[i])
+            d[f"{k}_ms"] = float(self.kernel_ms[i])
+        return d
 
 
 EXPORTS = ("gc_status_str", "gc_last_hip_error", "gc_problem_check", "gc_graph_footprint_bytes",

@@ -33,7 +33,7 @@ def test_problem_validation_and_footprint():
     assert gc.problem_check(ok) == 0
     n = 384 * 288 * 15
     fp = gc.footprint_bytes(ok)
-    assert fp >= 46 * n and fp < 46 * n + 64 * 1024
+    assert fp >= 46 * n and fp < 46 * n + 96 * 1024
     assert gc.problem_check(gc.problem(4, 4, 0, 30, 1, 1023)) == -2      # labels < 1
     assert gc.problem_check(gc.problem(-1, 4, 4, 30, 1, 1023)) == -2
     assert gc.problem_check(gc.problem(4, 4, 4, 30, -1, 1023)) == -1     # eq. (1) needs >= 0

@@ -156,10 +156,13 @@ def test_repeat_solves_identical(torch_cuda, orc):
     pr = sg.make_pair(sg.spec_like(sg.MID, 128, 96, 16), (5, 5))
     cost_np = orc.cost_volume(pr.left, pr.right, 16, 30)
     outs = []
-    for period, tw, th, tj in [(8, 32, 4, 16), (1, 16, 8, 8), (23, 64, 2, 4), (4, 8, 8, 32)]:
+    for period, tw, th, tj in [(8, 16, 16, 16), (1, 32, 8, 8), (23, 64, 16, 4), (4, 8, 8, 32)]:
         o = gc.GcSolveOpts(relabel_period=period, tile_w=tw, tile_h=th, tile_j=tj)
         lab, e, f, st = _solve_cost_gpu(torch_cuda, cost_np, 1, 1023, opts=o)
         outs.append((lab, e, f))
+    with pytest.raises(gc.GazecutError):
+        _solve_cost_gpu(torch_cuda, cost_np, 1, 1023,
+                        opts=gc.GcSolveOpts(tile_w=7, tile_h=3, tile_j=5))
     for lab, e, f in outs[1:]:
         assert (lab == outs[0][0]).all() and e == outs[0][1] and f == outs[0][2]
     _check_against_oracle(orc, cost_np, outs[0][0], outs[0][1], outs[0][2], (1, 1023, 1, 1023))
