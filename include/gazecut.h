@@ -83,12 +83,12 @@ typedef struct {
 
 /* Solver options; a zero-filled struct selects the defaults. */
 typedef struct {
-    int32_t relabel_period;   /* push-relabel sweeps between global relabels (default 8) */
+    int32_t relabel_period;   /* push-relabel sweeps between global relabels (default 64) */
     int32_t max_sweeps;       /* give up with GC_E_NOT_CONVERGED after this many (default 1<<20) */
-    int32_t tile_w;           /* BFS tile extent along x (default 32)          */
-    int32_t tile_h;           /* along y (default 4)                          */
+    int32_t tile_w;           /* BFS tile extent along x (default 8)           */
+    int32_t tile_h;           /* along y (default 8)                          */
     int32_t tile_j;           /* along the depth-number axis (default 16)     */
-    int32_t local_iters;      /* max in-tile relaxation rounds per pass (default 64) */
+    int32_t local_iters;      /* max in-tile relaxation rounds per pass (default 8) */
     int32_t flags;            /* GC_OPT_* bits                                */
     int32_t reserved;
 } gc_solve_opts;

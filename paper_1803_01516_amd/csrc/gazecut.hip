@@ -95,6 +95,7 @@ constexpr int kSlots = 256;
 struct Graph {
     int32_t *ex, *ht, *rd, *re, *rs, *rem, *rep, *rsm, *rsp, *ein, *aux;
     uint16_t *mask;
+    int32_t *stamps;          // per relaxation tile: last pass that changed it
     DevHeader *hdr;
     Slot *slots;
     int32_t W, H, J;
@@ -117,6 +118,16 @@ int64_t node_count(const gc_problem *p)
     return (int64_t)p->width * p->height * (p->labels > 0 ? p->labels - 1 : 0);
 }
 
+// Relaxation tiles are at least 8 x 4 x 4 nodes, which bounds the tile count.
+constexpr int kMinTileW = 8, kMinTileH = 4, kMinTileJ = 4;
+size_t max_tiles(const gc_problem *p)
+{
+    const int64_t J = p->labels > 0 ? p->labels - 1 : 0;
+    return (size_t)(((int64_t)p->width + kMinTileW - 1) / kMinTileW) *
+           (size_t)(((int64_t)p->height + kMinTileH - 1) / kMinTileH) *
+           (size_t)((J + kMinTileJ - 1) / kMinTileJ);
+}
+
 Graph view(const gc_graph *g)
 {
     const gc_problem &p = g->p;
@@ -130,7 +141,8 @@ Graph view(const gc_graph *g)
     size_t w4 = align256((size_t)s.N * 4);
     int32_t **arr[] = {&s.ex, &s.ht, &s.rd, &s.re, &s.rs, &s.rem, &s.rep, &s.rsm, &s.rsp, &s.ein, &s.aux};
     for (int32_t **a : arr) { *a = (int32_t *)b; b += w4; }
-    s.mask = (uint16_t *)b;
+    s.mask = (uint16_t *)b; b += align256((size_t)s.N * 2);
+    s.stamps = (int32_t *)b;
     s.te = 2 * p.penalty_h; s.ts = 2 * p.penalty_v;
     s.ie = p.inhibit_h; s.is = p.inhibit_v;
     return s;
@@ -469,24 +481,59 @@ k_seed(Graph s, int mode)
 }
 
 // One tiled min-plus relaxation pass: val(u) = min(val(u), val(w) + step)
-// over the neighbours w selected by mask(u), iterated inside the tile (in
-// LDS) until nothing changes or `max_iters` rounds have run.  Values only
-// decrease, so tiles can run in any order and the pass sequence converges
-// to the exact fixpoint.  Each thread owns NI/256 fixed nodes whose masks
-// and LDS slots stay in registers; only values that changed are written
-// back, and flag <- 1 if any did.
+// over the neighbours w selected by mask(u).  Values only decrease, so
+// tiles may run in any order and read each other's halos while they change;
+// the pass sequence converges to the exact fixpoint.
+//
+// Work is skipped at two levels.  Across tiles: stamps[t] = 2*pass + u
+// records the last pass in which tile t changed (u = 1 if it stopped before
+// its local fixpoint), and in pass p > 1 a tile runs only if a tile of its
+// 3x3x3 neighbourhood changed in pass p-1.  A tile's interior is at its
+// local fixpoint after it ran, so on re-entry only its face layer can
+// change.  Inside the tile: an LDS bitmap lists the nodes to re-evaluate in
+// the next round (neighbours of a changed node whose mask points back at
+// it); rounds stop when it is empty.  flags[p % kMaxFlags] <- 1 if any
+// value changed; pass p returns at once when pass p-1 changed nothing.
 template <int TW, int TH, int TJ>
 __global__ void __launch_bounds__(kBlock)
-k_relax(Graph s, int32_t *__restrict__ val, int step, int max_iters, int32_t *flag)
+k_relax(Graph s, int32_t *__restrict__ val, int step, int max_rounds, int32_t *flags, int pass,
+        int32_t *__restrict__ stamps, int ntx, int nty, int ntz)
 {
     constexpr int HW = TW + 2, HH = TH + 2, HJ = TJ + 2;
     constexpr int NH = HW * HH * HJ, NI = TW * TH * TJ;
-    static_assert(NI % kBlock == 0, "tile must hold a multiple of the block size");
+    static_assert(NI % kBlock == 0 && NI / kBlock <= 32, "tile must hold 1..32 nodes per thread");
     constexpr int NPT = NI / kBlock;
     __shared__ int32_t sv[NH];
+    __shared__ uint16_t smk[NI];
+    __shared__ uint32_t dirty[2][kBlock];
     __shared__ int s_flag;
-    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH, j0 = blockIdx.z * TJ;
     const int tid = threadIdx.x;
+    if (pass > 1 && flags[(pass - 1) % kMaxFlags] == 0) return;     // converged already
+    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    const int tile = (bz * nty + by) * ntx + bx;
+    // Neighbouring tiles may rewrite their stamps during this pass, so one
+    // thread decides for the whole block.
+    __shared__ int s_run, s_full;
+    if (tid == 0) {
+        int run = pass == 1, full_ = pass == 1;
+        if (pass > 1) {
+            for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const int tz = bz + dz, ty = by + dy, tx = bx + dx;
+                        if (tz < 0 || tz >= ntz || ty < 0 || ty >= nty || tx < 0 || tx >= ntx) continue;
+                        const int st = stamps[(tz * nty + ty) * ntx + tx];
+                        if ((st >> 1) == pass - 1) run = 1;
+                    }
+            full_ = (stamps[tile] & 1) != 0;
+        }
+        s_run = run;
+        s_full = full_;
+    }
+    __syncthreads();
+    if (!s_run) return;
+    const bool full = s_full != 0;
+    const int x0 = bx * TW, y0 = by * TH, j0 = bz * TJ;
 
     for (int i = tid; i < NH; i += kBlock) {
         const int lx = i % HW, t = i / HW, ly = t % HH, lj = t / HH;
@@ -496,17 +543,20 @@ k_relax(Graph s, int32_t *__restrict__ val, int step, int max_iters, int32_t *fl
             v = val[((int64_t)gj * s.H + gy) * s.W + gx];
         sv[i] = v;
     }
-    unsigned mk[NPT];
-    int hid[NPT];
-    int32_t orig[NPT];
+    uint32_t bits = 0;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int i = tid + k * kBlock;
         const int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
         const int gx = x0 + lx, gy = y0 + ly, gj = j0 + lj;
-        mk[k] = (gx < s.W && gy < s.H && gj < s.J) ? s.mask[((int64_t)gj * s.H + gy) * s.W + gx] : 0u;
-        hid[k] = ((lj + 1) * HH + (ly + 1)) * HW + (lx + 1);
+        const unsigned mk =
+            (gx < s.W && gy < s.H && gj < s.J) ? s.mask[((int64_t)gj * s.H + gy) * s.W + gx] : 0u;
+        smk[i] = (uint16_t)mk;
+        const bool face = lx == 0 || lx == TW - 1 || ly == 0 || ly == TH - 1 || lj == 0 || lj == TJ - 1;
+        if (mk && (full || face)) bits |= 1u << k;
     }
+    dirty[0][tid] = bits;
+    dirty[1][tid] = 0;
     constexpr int hoff[14] = {
         (dir_dj(0) * HH + dir_dy(0)) * HW + dir_dx(0),   (dir_dj(1) * HH + dir_dy(1)) * HW + dir_dx(1),
         (dir_dj(2) * HH + dir_dy(2)) * HW + dir_dx(2),   (dir_dj(3) * HH + dir_dy(3)) * HW + dir_dx(3),
@@ -515,46 +565,93 @@ k_relax(Graph s, int32_t *__restrict__ val, int step, int max_iters, int32_t *fl
         (dir_dj(8) * HH + dir_dy(8)) * HW + dir_dx(8),   (dir_dj(9) * HH + dir_dy(9)) * HW + dir_dx(9),
         (dir_dj(10) * HH + dir_dy(10)) * HW + dir_dx(10), (dir_dj(11) * HH + dir_dy(11)) * HW + dir_dx(11),
         (dir_dj(12) * HH + dir_dy(12)) * HW + dir_dx(12), (dir_dj(13) * HH + dir_dy(13)) * HW + dir_dx(13)};
+    constexpr int ioff[14] = {
+        (dir_dj(0) * TH + dir_dy(0)) * TW + dir_dx(0),   (dir_dj(1) * TH + dir_dy(1)) * TW + dir_dx(1),
+        (dir_dj(2) * TH + dir_dy(2)) * TW + dir_dx(2),   (dir_dj(3) * TH + dir_dy(3)) * TW + dir_dx(3),
+        (dir_dj(4) * TH + dir_dy(4)) * TW + dir_dx(4),   (dir_dj(5) * TH + dir_dy(5)) * TW + dir_dx(5),
+        (dir_dj(6) * TH + dir_dy(6)) * TW + dir_dx(6),   (dir_dj(7) * TH + dir_dy(7)) * TW + dir_dx(7),
+        (dir_dj(8) * TH + dir_dy(8)) * TW + dir_dx(8),   (dir_dj(9) * TH + dir_dy(9)) * TW + dir_dx(9),
+        (dir_dj(10) * TH + dir_dy(10)) * TW + dir_dx(10), (dir_dj(11) * TH + dir_dy(11)) * TW + dir_dx(11),
+        (dir_dj(12) * TH + dir_dy(12)) * TW + dir_dx(12), (dir_dj(13) * TH + dir_dy(13)) * TW + dir_dx(13)};
     __syncthreads();
+    int32_t orig[NPT];
 #pragma unroll
-    for (int k = 0; k < NPT; ++k) orig[k] = sv[hid[k]];
+    for (int k = 0; k < NPT; ++k) {
+        const int i = tid + k * kBlock;
+        const int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
+        orig[k] = sv[((lj + 1) * HH + (ly + 1)) * HW + (lx + 1)];
+    }
 
-    for (int it = 0; it < max_iters; ++it) {
+    int cur = 0;
+    bool capped = true;
+    for (int round = 0; round < max_rounds; ++round) {
         if (tid == 0) s_flag = 0;
+        uint32_t todo = dirty[cur][tid];
+        dirty[cur][tid] = 0;
         __syncthreads();
         bool ch = false;
-#pragma unroll
-        for (int k = 0; k < NPT; ++k) {
-            const unsigned m = mk[k];
-            if (!m) continue;
-            const int32_t cur = sv[hid[k]];
-            int32_t best = cur;
+        while (todo) {
+            const int k = __builtin_ctz(todo);
+            todo &= todo - 1;
+            const int i = tid + k * kBlock;
+            const unsigned m = smk[i];
+            const int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
+            const int hi = ((lj + 1) * HH + (ly + 1)) * HW + (lx + 1);
+            const int32_t c = sv[hi];
+            int32_t best = c;
 #pragma unroll
             for (int d = 0; d < 14; ++d)
                 if ((m >> d) & 1u) {
-                    const int32_t nv = sv[hid[k] + hoff[d]] + step;
+                    const int32_t nv = sv[hi + hoff[d]] + step;
                     best = nv < best ? nv : best;
                 }
-            if (best < cur) { sv[hid[k]] = best; ch = true; }
+            if (best < c) {
+                sv[hi] = best;
+                ch = true;
+                // wake interior neighbours whose mask points back at this node
+#pragma unroll
+                for (int d = 0; d < 14; ++d) {
+                    const int nx = lx + dir_dx(d), ny = ly + dir_dy(d), nj = lj + dir_dj(d);
+                    if (nx < 0 || nx >= TW || ny < 0 || ny >= TH || nj < 0 || nj >= TJ) continue;
+                    const int ni = i + ioff[d];
+                    const int back = d <= D_N ? (d ^ 1) : (d == D_EM ? D_WP : d == D_WP ? D_EM :
+                                     d == D_EP ? D_WM : d == D_WM ? D_EP : d == D_SM ? D_NP :
+                                     d == D_NP ? D_SM : d == D_SP ? D_NM : D_SP);
+                    if ((smk[ni] >> back) & 1u)
+                        atomicOr(&dirty[cur ^ 1][ni % kBlock], 1u << (ni / kBlock));
+                }
+            }
         }
         if (ch) s_flag = 1;
         __syncthreads();
         const int f = s_flag;
         __syncthreads();
-        if (!f) break;
+        if (!f) { capped = false; break; }
+        cur ^= 1;
     }
     bool wrote = false;
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
-        const int32_t v = sv[hid[k]];
+        const int i = tid + k * kBlock;
+        const int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
+        const int32_t v = sv[((lj + 1) * HH + (ly + 1)) * HW + (lx + 1)];
         if (v != orig[k]) {
-            const int i = tid + k * kBlock;
-            const int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
             val[((int64_t)(j0 + lj) * s.H + (y0 + ly)) * s.W + (x0 + lx)] = v;
             wrote = true;
         }
     }
-    if (wrote) *flag = 1;
+    if (tid == 0) s_flag = 0;
+    __syncthreads();
+    if (wrote) s_flag = 1;
+    __syncthreads();
+    if (tid == 0) {
+        if (s_flag || capped) {
+            stamps[tile] = (pass << 1) | (capped ? 1 : 0);
+            flags[pass % kMaxFlags] = 1;
+        } else if (pass == 1) {
+            stamps[tile] = 0;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -578,6 +675,13 @@ __global__ void k_zero_header(DevHeader *h, int what)
     } else if (what == 2) {          // active counter
         if (i == 0) h->active = 0;
     }
+}
+
+// Clears the change flags of passes first .. first+count-1.
+__global__ void k_zero_flags(DevHeader *h, int first, int count)
+{
+    int i = threadIdx.x;
+    if (i < count) h->flags[(first + i) % kMaxFlags] = 0;
 }
 
 __global__ void k_zero_result(int64_t *r, DevHeader *h)
@@ -687,7 +791,7 @@ struct Opts {
 
 Opts resolve(const gc_solve_opts *o)
 {
-    Opts r{8, 1 << 20, 8, 8, 16, 8, 0};
+    Opts r{64, 1 << 20, 8, 8, 16, 8, 0};
     if (o) {
         if (o->relabel_period > 0) r.period = o->relabel_period;
         if (o->max_sweeps > 0) r.max_sweeps = o->max_sweeps;
@@ -700,7 +804,7 @@ Opts resolve(const gc_solve_opts *o)
     return r;
 }
 
-typedef void (*RelaxFn)(Graph, int32_t *, int, int, int32_t *);
+typedef void (*RelaxFn)(Graph, int32_t *, int, int, int32_t *, int, int32_t *, int, int, int);
 
 // Tile shapes compiled for the relaxation pass (x, y, depth layers).
 #define GC_RELAX_SHAPES(X)                                                        \
@@ -710,6 +814,7 @@ typedef void (*RelaxFn)(Graph, int32_t *, int, int, int32_t *);
 
 RelaxFn relax_kernel(int tw, int th, int tj)
 {
+    if (tw < kMinTileW || th < kMinTileH || tj < kMinTileJ) return nullptr;
 #define GC_RELAX_CASE(a, b, c) \
     if (tw == a && th == b && tj == c) return k_relax<a, b, c>;
     GC_RELAX_SHAPES(GC_RELAX_CASE)
@@ -769,33 +874,34 @@ struct Launcher {
 };
 
 // Runs relaxation passes until a pass changes nothing.  Passes are issued in
-// growing batches with one flag read-back per batch.
+// growing batches with one flag read-back per batch; a pass that follows a
+// pass without change returns at once, so over-issuing is cheap.
 int relax_to_fixpoint(const Graph &s, int32_t *val, int step, const Opts &o,
                       Launcher &L, int *passes_out)
 {
-    dim3 grid((unsigned)((s.W + o.tw - 1) / o.tw), (unsigned)((s.H + o.th - 1) / o.th),
-              (unsigned)((s.J + o.tj - 1) / o.tj));
+    const int ntx = (s.W + o.tw - 1) / o.tw, nty = (s.H + o.th - 1) / o.th,
+              ntz = (s.J + o.tj - 1) / o.tj;
+    dim3 grid((unsigned)ntx, (unsigned)nty, (unsigned)ntz);
     RelaxFn fn = relax_kernel(o.tw, o.th, o.tj);
     if (!fn) return GC_E_ARG;
     const int max_passes = 1 << 22;
     int passes = 0, batch = 2;
     for (;;) {
-        hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, L.st, s.hdr, 1);
-        for (int b = 0; b < batch; ++b)
+        hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, L.st, s.hdr, passes + 1, batch);
+        for (int b = 1; b <= batch; ++b)
             L.run(GC_K_RELAX, [&] {
                 hipLaunchKernelGGL(fn, grid, dim3(kBlock), 0, L.st, s, val, step, o.local_iters,
-                                   &s.hdr->flags[b]);
+                                   s.hdr->flags, passes + b, s.stamps, ntx, nty, ntz);
             });
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
         int32_t flags[kMaxFlags];
-        if (!hip_ok(hipMemcpyAsync(flags, s.hdr->flags, sizeof(int32_t) * batch,
-                                   hipMemcpyDeviceToHost, L.st)))
+        if (!hip_ok(hipMemcpyAsync(flags, s.hdr->flags, sizeof(flags), hipMemcpyDeviceToHost, L.st)))
             return GC_E_HIP;
         if (!hip_ok(hipStreamSynchronize(L.st))) return GC_E_HIP;
         bool done = false;
-        for (int b = 0; b < batch; ++b) {
+        for (int b = 1; b <= batch; ++b) {
             ++passes;
-            if (!flags[b]) { done = true; break; }
+            if (!flags[passes % kMaxFlags]) { done = true; break; }
         }
         if (done) break;
         if (passes >= max_passes) return GC_E_NOT_CONVERGED;
@@ -856,7 +962,7 @@ GC_API size_t gc_graph_footprint_bytes(const gc_problem *p)
     if (gc_problem_check(p) != GC_OK) return 0;
     size_t n = (size_t)node_count(p);
     return align256(sizeof(DevHeader)) + align256(kSlots * sizeof(Slot)) + 11 * align256(n * 4) +
-           align256(n * 2);
+           align256(n * 2) + align256(max_tiles(p) * 4);
 }
 
 GC_API int stereo_cost_volume(const uint8_t *left, const uint8_t *right, const gc_problem *p,
