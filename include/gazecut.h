@@ -79,6 +79,8 @@ typedef struct {
     void *ws;                 /* DEVICE, >= gc_graph_footprint_bytes, 256-B aligned */
     size_t ws_bytes;
     gc_problem p;
+    int32_t window_block;     /* 0: full graph; b > 0: thin-skin graph of block size b */
+    int32_t reserved;
 } gc_graph;
 
 /* Solver options; a zero-filled struct selects the defaults. */
@@ -180,6 +182,46 @@ int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *stats, vo
  * Errors: GC_E_ARG, GC_E_PREFIX, GC_E_HIP. */
 int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *labels,
                    int64_t *result, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Hierarchical approximation, level 1 (Sec. 4.5).  b x b x b neighbouring
+ * cross points form one delegate point; a first exact cut on the delegate
+ * points decides which of them hold the surface, and a second exact cut
+ * finds the real cross points inside the thin skin around it.  Pipeline:
+ *   gc_coarse_problem -> coarse_cost_volume -> graph_build -> maxflow_solve
+ *   -> extract_labels (delegate labels) -> graph_build_window ->
+ *   maxflow_solve -> extract_labels (fine labels, exact E of the result).
+ * Block size 1 reproduces the exact minimisation.
+ * ---------------------------------------------------------------------- */
+
+/* Delegate-point problem of block size `block` (host only): ceil(w/b) x
+ * ceil(h/b) sites and ceil(m/b) labels; coarse site (X, Y) covers sites
+ * x / b = X, y / b = Y, coarse label Sc covers S / b = Sc.  cap and penalties
+ * scale by b*b (a one-group step between coarse sites stands for a ramp of b
+ * depth numbers over b rows of fine pairs); inhibit is unchanged.
+ * Errors: GC_E_ARG (block < 1), the errors of gc_problem_check. */
+int gc_coarse_problem(const gc_problem *p, int32_t block, gc_problem *coarse);
+
+/* Delegate-point data term: coarse_cost[(Sc*hc + Y)*wc + X] = sum over the
+ * sites of coarse site (X, Y) of min over S in group Sc of cost(x, y, S).
+ * cost: DEVICE int32 [labels][height][width]; coarse_cost: DEVICE int32
+ * [ceil(m/b)][ceil(h/b)][ceil(w/b)], written. */
+int coarse_cost_volume(const gc_problem *p, const int32_t *cost, int32_t block,
+                       int32_t *coarse_cost, void *stream);
+
+/* Thin-skin graph (Sec. 4.5, second cut): like graph_build on the full
+ * problem, but site (x, y) may only take labels in
+ *   [max(0, b*(Sc-1)), min(m-1, b*(Sc+2)-1)],  Sc = coarse_labels[y/b][x/b],
+ * the delegate group of the first cut and the groups directly above and
+ * below.  Levels outside the window are forced to the source (above) or sink
+ * (below) side and their arcs are folded into overflows.  maxflow_solve and
+ * extract_labels accept the result; extract_labels then returns the exact
+ * energy of the restricted optimum, and result[1] the restricted min-cut
+ * value (equal to it).
+ * coarse_labels: DEVICE int32 [ceil(h/b)][ceil(w/b)] labels in [0, ceil(m/b)).
+ * ws: as for graph_build (same footprint). */
+int graph_build_window(const gc_problem *p, const int32_t *cost, const int32_t *coarse_labels,
+                       int32_t block, void *ws, size_t ws_bytes, gc_graph *g_out, void *stream);
 
 #ifdef __cplusplus
 }

@@ -82,6 +82,16 @@ def _load():
     lib.orc_brute_force.restype = I
     lib.orc_scanline_dp.argtypes = [P, I, I, I, I, P, P]
     lib.orc_scanline_dp.restype = I
+    lib.orc_solve_window.argtypes = [P, I, I, I, I, I, I, I, P, P, I, P, P, P]
+    lib.orc_solve_window.restype = I
+    lib.orc_coarse_cost.argtypes = [P, I, I, I, I, P]
+    lib.orc_coarse_cost.restype = I
+    lib.orc_skin_windows.argtypes = [P, I, I, I, I, P, P]
+    lib.orc_skin_windows.restype = I
+    lib.orc_approx_level1.argtypes = [P, I, I, I, I, I, I, I, I, P, P, P]
+    lib.orc_approx_level1.restype = I
+    lib.orc_brute_force_window.argtypes = [P, I, I, I, I, I, I, I, P, P, P, P]
+    lib.orc_brute_force_window.restype = I
     _lib = lib
     return lib
 
@@ -227,4 +237,70 @@ def scanline_dp(cost: np.ndarray, pen: int, inh: int):
     e = np.zeros(1, dtype=np.int64)
     _check(_load().orc_scanline_dp(_ptr(cost), w, m, int(pen), int(inh), _ptr(e), _ptr(lab)),
            "scanline_dp")
+    return int(e[0]), lab
+
+
+# ---------------------------------------------------------------------------
+# Label windows and the hierarchical approximation (Sec. 4.5, level 1)
+# ---------------------------------------------------------------------------
+
+def solve_window(cost: np.ndarray, lo: np.ndarray, hi: np.ndarray, pen_h: int, inh_h: int,
+                 pen_v: int | None = None, inh_v: int | None = None, algo: str = "pushrelabel"):
+    """Exact minimiser of E with lo <= X <= hi per site.  Returns (labels, flow, energy)."""
+    cost = np.ascontiguousarray(cost, dtype=np.int32)
+    m, h, w = cost.shape
+    lo = np.ascontiguousarray(lo, dtype=np.int32)
+    hi = np.ascontiguousarray(hi, dtype=np.int32)
+    lab = np.empty((h, w), dtype=np.int32)
+    f = np.zeros(1, dtype=np.int64)
+    e = np.zeros(1, dtype=np.int64)
+    a = {"dinic": 0, "pushrelabel": 1}[algo]
+    _check(_load().orc_solve_window(_ptr(cost), w, h, m, *_params(pen_h, inh_h, pen_v, inh_v),
+                                    _ptr(lo), _ptr(hi), a, _ptr(lab), _ptr(f), _ptr(e)),
+           "solve_window")
+    return lab, int(f[0]), int(e[0])
+
+
+def coarse_cost(cost: np.ndarray, b: int) -> np.ndarray:
+    """Delegate-point data term: int32 [ceil(m/b)][ceil(h/b)][ceil(w/b)]."""
+    cost = np.ascontiguousarray(cost, dtype=np.int32)
+    m, h, w = cost.shape
+    out = np.empty((-(-m // b), -(-h // b), -(-w // b)), dtype=np.int32)
+    _check(_load().orc_coarse_cost(_ptr(cost), w, h, m, int(b), _ptr(out)), "coarse_cost")
+    return out
+
+
+def skin_windows(coarse_labels: np.ndarray, w: int, h: int, m: int, b: int):
+    cl = np.ascontiguousarray(coarse_labels, dtype=np.int32)
+    lo = np.empty((h, w), dtype=np.int32)
+    hi = np.empty((h, w), dtype=np.int32)
+    _check(_load().orc_skin_windows(_ptr(cl), w, h, m, int(b), _ptr(lo), _ptr(hi)), "skin_windows")
+    return lo, hi
+
+
+def approx_level1(cost: np.ndarray, b: int, pen_h: int, inh_h: int, pen_v: int | None = None,
+                  inh_v: int | None = None):
+    """Returns (labels, energy, coarse labels)."""
+    cost = np.ascontiguousarray(cost, dtype=np.int32)
+    m, h, w = cost.shape
+    lab = np.empty((h, w), dtype=np.int32)
+    cl = np.empty((-(-h // b), -(-w // b)), dtype=np.int32)
+    e = np.zeros(1, dtype=np.int64)
+    _check(_load().orc_approx_level1(_ptr(cost), w, h, m, *_params(pen_h, inh_h, pen_v, inh_v),
+                                     int(b), _ptr(lab), _ptr(e), _ptr(cl)), "approx_level1")
+    return lab, int(e[0]), cl
+
+
+def brute_force_window(cost: np.ndarray, lo: np.ndarray, hi: np.ndarray, pen_h: int, inh_h: int,
+                       pen_v: int | None = None, inh_v: int | None = None):
+    """Returns (min energy, pointwise-min minimiser) over windowed labellings."""
+    cost = np.ascontiguousarray(cost, dtype=np.int32)
+    m, h, w = cost.shape
+    lo = np.ascontiguousarray(lo, dtype=np.int32)
+    hi = np.ascontiguousarray(hi, dtype=np.int32)
+    lab = np.empty((h, w), dtype=np.int32)
+    e = np.zeros(1, dtype=np.int64)
+    _check(_load().orc_brute_force_window(_ptr(cost), w, h, m, *_params(pen_h, inh_h, pen_v, inh_v),
+                                          _ptr(lo), _ptr(hi), _ptr(e), _ptr(lab)),
+           "brute_force_window")
     return int(e[0]), lab

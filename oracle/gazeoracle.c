@@ -121,6 +121,7 @@ typedef struct {
     int64_t *cap0;      /* original capacity */
     int32_t *tail;      /* arc source (for checks) */
     int w, h, m;
+    int32_t *lo, *hi;   /* optional per-site label windows (NULL: [0, m-1]) */
 } orc_graph;
 
 static int32_t node_id(int w, int h, int x, int y, int k)
@@ -129,12 +130,17 @@ static int32_t node_id(int w, int h, int x, int y, int k)
     return 2 + (int32_t)((((int64_t)(k - 1) * h + y) * w) + x);
 }
 
-/* Map level k of site (x,y) to a node; k = 0 is s and k = m is t. */
-static int32_t level_node(int w, int h, int m, int x, int y, int k)
+/* Map level k of site (x,y) to a node; k = 0 is s and k = m is t.  With a
+ * label window [lo, hi] for the site, every level k <= lo is forced to the
+ * source side (it is s) and every level k > hi to the sink side (it is t),
+ * which restricts X_v to the window. */
+static int32_t level_node(const orc_graph *g, int x, int y, int k)
 {
-    if (k == 0) return 0;
-    if (k == m) return 1;
-    return node_id(w, h, x, y, k);
+    int lo = g->lo ? g->lo[y * g->w + x] : 0;
+    int hi = g->hi ? g->hi[y * g->w + x] : g->m - 1;
+    if (k <= lo) return 0;
+    if (k > hi) return 1;
+    return node_id(g->w, g->h, x, y, k);
 }
 
 typedef struct {
@@ -146,6 +152,7 @@ typedef struct {
 static void add_pair(arc_sink *sk, int32_t a, int32_t b, int64_t cab, int64_t cba)
 {
     orc_graph *g = sk->g;
+    if (a == b) return;                 /* both ends forced to the same terminal */
     if (!sk->fill) {
         g->first[a + 1]++;
         g->first[b + 1]++;
@@ -168,8 +175,8 @@ static void emit_arcs(arc_sink *sk, const int32_t *cost, int pen_h, int inh_h,
             /* data chain: v_k -> v_{k+1} with cap g(k) */
             for (int k = 0; k < m; k++) {
                 int64_t gk = cost[((int64_t)k * h + y) * w + x];
-                int32_t a = level_node(w, h, m, x, y, k);
-                int32_t b = level_node(w, h, m, x, y, k + 1);
+                int32_t a = level_node(g, x, y, k);
+                int32_t b = level_node(g, x, y, k + 1);
                 int64_t back = (k >= 1 && k <= m - 2) ? ORC_INF : 0;
                 add_pair(sk, a, b, gk, back);
             }
@@ -185,11 +192,11 @@ static void emit_arcs(arc_sink *sk, const int32_t *cost, int pen_h, int inh_h,
                 if (vx >= w || vy >= h) continue;
                 /* same-level arcs u_k <-> v_k */
                 for (int k = 1; k <= m - 1; k++)
-                    add_pair(sk, node_id(w, h, ux, uy, k), node_id(w, h, vx, vy, k), h1, h1);
+                    add_pair(sk, level_node(g, ux, uy, k), level_node(g, vx, vy, k), h1, h1);
                 /* diagonal arcs u_{k+1} -> v_k and v_{k+1} -> u_k */
                 for (int k = 1; k <= m - 2; k++) {
-                    add_pair(sk, node_id(w, h, ux, uy, k + 1), node_id(w, h, vx, vy, k), h2, 0);
-                    add_pair(sk, node_id(w, h, vx, vy, k + 1), node_id(w, h, ux, uy, k), h2, 0);
+                    add_pair(sk, level_node(g, ux, uy, k + 1), level_node(g, vx, vy, k), h2, 0);
+                    add_pair(sk, level_node(g, vx, vy, k + 1), level_node(g, ux, uy, k), h2, 0);
                 }
             }
     }
@@ -199,11 +206,15 @@ void orc_graph_free(orc_graph *g)
 {
     if (!g) return;
     free(g->first); free(g->head); free(g->rev); free(g->res); free(g->cap0); free(g->tail);
+    free(g->lo); free(g->hi);
     free(g);
 }
 
-orc_graph *orc_graph_build(const int32_t *cost, int w, int h, int m, int pen_h,
-                           int inh_h, int pen_v, int inh_v)
+/* Layered graph with optional per-site label windows lo[site] <= X <= hi[site]
+ * (NULL for the unrestricted problem). */
+orc_graph *orc_graph_build_window(const int32_t *cost, int w, int h, int m, int pen_h,
+                                  int inh_h, int pen_v, int inh_v, const int32_t *lo,
+                                  const int32_t *hi)
 {
     if (w < 0 || h < 0 || m < 1) return NULL;
     if (pen_h < 0 || inh_h < 0 || pen_v < 0 || inh_v < 0) return NULL;
@@ -212,6 +223,16 @@ orc_graph *orc_graph_build(const int32_t *cost, int w, int h, int m, int pen_h,
     orc_graph *g = (orc_graph *)calloc(1, sizeof(orc_graph));
     if (!g) return NULL;
     g->n = (int32_t)nn; g->w = w; g->h = h; g->m = m;
+    if (lo && hi) {
+        size_t ns = (size_t)w * h;
+        g->lo = (int32_t *)malloc((ns ? ns : 1) * sizeof(int32_t));
+        g->hi = (int32_t *)malloc((ns ? ns : 1) * sizeof(int32_t));
+        if (!g->lo || !g->hi) { orc_graph_free(g); return NULL; }
+        for (size_t i = 0; i < ns; i++) {
+            if (lo[i] < 0 || hi[i] > m - 1 || lo[i] > hi[i]) { orc_graph_free(g); return NULL; }
+            g->lo[i] = lo[i]; g->hi[i] = hi[i];
+        }
+    }
     g->first = (int64_t *)calloc((size_t)nn + 1, sizeof(int64_t));
     if (!g->first) { orc_graph_free(g); return NULL; }
     arc_sink sk = { g, 0, NULL };
@@ -233,6 +254,12 @@ orc_graph *orc_graph_build(const int32_t *cost, int w, int h, int m, int pen_h,
     emit_arcs(&sk, cost, pen_h, inh_h, pen_v, inh_v);
     free(sk.pos);
     return g;
+}
+
+orc_graph *orc_graph_build(const int32_t *cost, int w, int h, int m, int pen_h,
+                           int inh_h, int pen_v, int inh_v)
+{
+    return orc_graph_build_window(cost, w, h, m, pen_h, inh_h, pen_v, inh_v, NULL, NULL);
 }
 
 int32_t orc_graph_nodes(const orc_graph *g) { return g->n; }
@@ -289,7 +316,7 @@ static int labels_from_side(const orc_graph *g, const uint8_t *side, int32_t *la
         for (int x = 0; x < w; x++) {
             int X = 0, seen_out = 0;
             for (int k = 1; k <= m - 1; k++) {
-                int in = side[node_id(w, h, x, y, k)];
+                int in = side[level_node(g, x, y, k)];
                 if (in) {
                     if (seen_out) return ORC_E_PREFIX;
                     X++;
@@ -571,9 +598,9 @@ int orc_check_flow(const orc_graph *g, const int64_t *excess)
 
 /* algo 0 = Dinic, 1 = push-relabel.  Writes the canonical labels, the
  * max-flow value and the energy of the labels. */
-int orc_solve(const int32_t *cost, int w, int h, int m, int pen_h, int inh_h,
-              int pen_v, int inh_v, int algo, int32_t *labels, int64_t *flow,
-              int64_t *energy)
+int orc_solve_window(const int32_t *cost, int w, int h, int m, int pen_h, int inh_h,
+                     int pen_v, int inh_v, const int32_t *lo, const int32_t *hi, int algo,
+                     int32_t *labels, int64_t *flow, int64_t *energy)
 {
     if (m == 1) {
         for (int i = 0; i < w * h; i++) labels[i] = 0;
@@ -581,7 +608,7 @@ int orc_solve(const int32_t *cost, int w, int h, int m, int pen_h, int inh_h,
         *flow = *energy;
         return ORC_OK;
     }
-    orc_graph *g = orc_graph_build(cost, w, h, m, pen_h, inh_h, pen_v, inh_v);
+    orc_graph *g = orc_graph_build_window(cost, w, h, m, pen_h, inh_h, pen_v, inh_v, lo, hi);
     if (!g) return ORC_E_NOMEM;
     int rc;
     if (algo == 0) {
@@ -598,6 +625,126 @@ int orc_solve(const int32_t *cost, int w, int h, int m, int pen_h, int inh_h,
     if (rc == ORC_OK)
         *energy = orc_energy(cost, labels, w, h, m, pen_h, inh_h, pen_v, inh_v);
     return rc;
+}
+
+int orc_solve(const int32_t *cost, int w, int h, int m, int pen_h, int inh_h,
+              int pen_v, int inh_v, int algo, int32_t *labels, int64_t *flow,
+              int64_t *energy)
+{
+    return orc_solve_window(cost, w, h, m, pen_h, inh_h, pen_v, inh_v, NULL, NULL, algo,
+                            labels, flow, energy);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hierarchical approximation, level 1 (Sec. 4.5).                           */
+/*                                                                          */
+/* b x b x b neighbouring cross points form one delegate point: coarse site  */
+/* (X, Y) = (x / b, y / b), coarse label Sc = S / b.  A first exact cut on   */
+/* the delegate points picks, per coarse site, the label group holding the   */
+/* surface; a second exact cut finds the real cross points inside a thin     */
+/* skin around it: every fine site may only take the labels of its coarse    */
+/* group and of the groups directly above and below.  Readings (the paper    */
+/* omits the details): a delegate point costs the sum over its sites of the  */
+/* cheapest label in its group; the coarse pairwise term keeps the fine      */
+/* inhibit and scales the penalty by b^2 (a one-group step between coarse    */
+/* sites is a b-level ramp over b rows of fine pairs).  b = 1 is the exact   */
+/* minimisation.                                                             */
+/* ------------------------------------------------------------------------ */
+
+int orc_coarse_cost(const int32_t *cost, int w, int h, int m, int b, int32_t *coarse)
+{
+    if (b < 1 || w < 0 || h < 0 || m < 1) return ORC_E_ARG;
+    int wc = (w + b - 1) / b, hc = (h + b - 1) / b, mc = (m + b - 1) / b;
+    for (int Sc = 0; Sc < mc; Sc++)
+        for (int Y = 0; Y < hc; Y++)
+            for (int X = 0; X < wc; X++) {
+                int64_t sum = 0;
+                for (int y = Y * b; y < Y * b + b && y < h; y++)
+                    for (int x = X * b; x < X * b + b && x < w; x++) {
+                        int32_t best = INT32_MAX;
+                        for (int S = Sc * b; S < Sc * b + b && S < m; S++) {
+                            int32_t g = cost[((int64_t)S * h + y) * w + x];
+                            if (g < best) best = g;
+                        }
+                        sum += best;
+                    }
+                coarse[((int64_t)Sc * hc + Y) * wc + X] = (int32_t)sum;
+            }
+    return ORC_OK;
+}
+
+/* Thin skin: labels of the coarse group and the groups above and below. */
+int orc_skin_windows(const int32_t *coarse_labels, int w, int h, int m, int b, int32_t *lo,
+                     int32_t *hi)
+{
+    if (b < 1) return ORC_E_ARG;
+    int wc = (w + b - 1) / b;
+    for (int y = 0; y < h; y++)
+        for (int x = 0; x < w; x++) {
+            int Sc = coarse_labels[(y / b) * wc + x / b];
+            int l = b * (Sc - 1), u = b * (Sc + 2) - 1;
+            lo[y * w + x] = l < 0 ? 0 : l;
+            hi[y * w + x] = u > m - 1 ? m - 1 : u;
+        }
+    return ORC_OK;
+}
+
+/* Level-1 approximation.  coarse_labels (optional) receives the first cut. */
+int orc_approx_level1(const int32_t *cost, int w, int h, int m, int pen_h, int inh_h,
+                      int pen_v, int inh_v, int b, int32_t *labels, int64_t *energy,
+                      int32_t *coarse_labels)
+{
+    if (b < 1) return ORC_E_ARG;
+    int wc = (w + b - 1) / b, hc = (h + b - 1) / b, mc = (m + b - 1) / b;
+    size_t nc = (size_t)wc * hc;
+    int32_t *cc = (int32_t *)malloc(((size_t)mc * nc + 1) * sizeof(int32_t));
+    int32_t *cl = (int32_t *)malloc((nc + 1) * sizeof(int32_t));
+    int32_t *lo = (int32_t *)malloc(((size_t)w * h + 1) * sizeof(int32_t));
+    int32_t *hi = (int32_t *)malloc(((size_t)w * h + 1) * sizeof(int32_t));
+    int rc = ORC_E_NOMEM;
+    if (cc && cl && lo && hi) {
+        int64_t f, e;
+        rc = orc_coarse_cost(cost, w, h, m, b, cc);
+        if (rc == ORC_OK)
+            rc = orc_solve(cc, wc, hc, mc, b * b * pen_h, inh_h, b * b * pen_v, inh_v, 1, cl, &f, &e);
+        if (rc == ORC_OK) rc = orc_skin_windows(cl, w, h, m, b, lo, hi);
+        if (rc == ORC_OK)
+            rc = orc_solve_window(cost, w, h, m, pen_h, inh_h, pen_v, inh_v, lo, hi, 1, labels,
+                                  &f, energy);
+        if (rc == ORC_OK && coarse_labels) memcpy(coarse_labels, cl, nc * sizeof(int32_t));
+    }
+    free(cc); free(cl); free(lo); free(hi);
+    return rc;
+}
+
+/* Brute force restricted to per-site windows (tiny grids only). */
+int orc_brute_force_window(const int32_t *cost, int w, int h, int m, int pen_h, int inh_h,
+                           int pen_v, int inh_v, const int32_t *lo, const int32_t *hi,
+                           int64_t *min_energy, int32_t *lo_labels)
+{
+    int n = w * h;
+    double total = 1.0;
+    for (int i = 0; i < n; i++) total *= (hi[i] - lo[i] + 1);
+    if (total > 2.0e8) return ORC_E_TOO_BIG;
+    int32_t *X = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    if (!X) return ORC_E_NOMEM;
+    for (int i = 0; i < n; i++) X[i] = lo[i];
+    int64_t best = INT64_MAX;
+    for (;;) {
+        int64_t e = orc_energy(cost, X, w, h, m, pen_h, inh_h, pen_v, inh_v);
+        if (e < best) {
+            best = e;
+            for (int i = 0; i < n; i++) lo_labels[i] = X[i];
+        } else if (e == best) {
+            for (int i = 0; i < n; i++) if (X[i] < lo_labels[i]) lo_labels[i] = X[i];
+        }
+        int i = 0;
+        while (i < n && ++X[i] > hi[i]) { X[i] = lo[i]; i++; }
+        if (i == n) break;
+    }
+    free(X);
+    *min_energy = best;
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -76,7 +76,9 @@ struct DevHeader {
     int32_t prefix_err;
     int32_t pad[14];
     unsigned long long pushes;
-    unsigned long long pad2[15];
+    long long tcap;           // capacity of all arcs into the sink side
+    long long c0;             // capacity of arcs from forced-source to forced-sink nodes
+    unsigned long long pad2[13];
 };
 static_assert(sizeof(DevHeader) == 256, "header must stay 256 bytes");
 
@@ -87,7 +89,8 @@ struct Slot {
     long long e0, e1;
     int32_t active;
     int32_t pad;
-    long long pad2[4];
+    long long tcap, c0;
+    long long pad2[2];
 };
 static_assert(sizeof(Slot) == 64, "one slot per cache line");
 constexpr int kSlots = 256;
@@ -96,6 +99,7 @@ struct Graph {
     int32_t *ex, *ht, *rd, *re, *rs, *rem, *rep, *rsm, *rsp, *ein, *aux;
     uint16_t *mask;
     int32_t *stamps;          // per relaxation tile: last pass that changed it
+    int32_t *wlo, *whi;       // per-site label window of a thin-skin graph
     DevHeader *hdr;
     Slot *slots;
     int32_t W, H, J;
@@ -142,6 +146,8 @@ Graph view(const gc_graph *g)
     int32_t **arr[] = {&s.ex, &s.ht, &s.rd, &s.re, &s.rs, &s.rem, &s.rep, &s.rsm, &s.rsp, &s.ein, &s.aux};
     for (int32_t **a : arr) { *a = (int32_t *)b; b += w4; }
     s.mask = (uint16_t *)b; b += align256((size_t)s.N * 2);
+    s.wlo = (int32_t *)b; b += align256((size_t)s.plane * 4);
+    s.whi = (int32_t *)b; b += align256((size_t)s.plane * 4);
     s.stamps = (int32_t *)b;
     s.te = 2 * p.penalty_h; s.ts = 2 * p.penalty_v;
     s.ie = p.inhibit_h; s.is = p.inhibit_v;
@@ -294,30 +300,11 @@ k_cost_volume(const uint8_t *__restrict__ left, const uint8_t *__restrict__ righ
     cost[((int64_t)S * H + y) * W + x] = g;
 }
 
-__global__ void __launch_bounds__(kBlock)
-k_build(Graph s, const int32_t *__restrict__ cost, int m)
-{
-    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (n >= s.N) return;
-    int j, y, x;
-    decode(s, n, j, y, x);
-    const int64_t site = (int64_t)y * s.W + x;
-    const int k = j + 1;
-    int32_t e = 0;
-    if (k == 1) e += cost[site];                                    // s -> v_1 pre-saturated
-    if (k == m - 1) e -= cost[(int64_t)(m - 1) * s.plane + site];   // v_{m-1} -> t as deficit
-    s.ex[n] = e;
-    s.ht[n] = 0;
-    s.ein[n] = 0;
-    s.rd[n] = (j + 1 < s.J) ? cost[(int64_t)k * s.plane + site] : 0;
-    const bool hasE = x + 1 < s.W, hasS = y + 1 < s.H;
-    s.re[n] = hasE ? s.te / 2 : 0;
-    s.rs[n] = hasS ? s.ts / 2 : 0;
-    s.rem[n] = (hasE && j > 0) ? s.ie : 0;      // v_k -> E_{k-1} carries the capacity
-    s.rep[n] = 0;                               // its capacity runs E_{k+1} -> v_k
-    s.rsm[n] = (hasS && j > 0) ? s.is : 0;
-    s.rsp[n] = 0;
-}
+// Node classes of a thin-skin graph: a level inside the site's window is
+// free; levels at or above its top are forced to the source side, levels
+// below its bottom to the sink side.
+enum NodeClass { FREE = 0, FSRC = 1, FSNK = 2 };
+__device__ inline int node_class(int k, int lo, int hi) { return k <= lo ? FSRC : k > hi ? FSNK : FREE; }
 
 // Which of the 14 arcs of node (j, y, x) exist, as a bit mask over Dir.
 __device__ inline unsigned arc_exists(const Graph &s, int j, int y, int x)
@@ -372,6 +359,152 @@ __device__ inline int32_t res_from_word(const Graph &s, int d, int32_t w)
     case D_WM: case D_WP: return s.ie - w;
     default:   return s.is - w;                        // D_NM, D_NP
     }
+}
+
+// Graph initialisation.  Terminal arcs are folded into node overflows: the
+// arc from s into v_1 is pre-saturated (excess g(0)) and the arc from
+// v_{m-1} to t becomes a deficit g(m-1).  For a thin-skin graph (kWindow) the
+// same folding applies to every arc between a free node and a forced one:
+// arcs from forced-source nodes are pre-saturated into the free node's
+// excess, arcs into forced-sink nodes become deficits, and forced nodes are
+// inert (no excess, infinite height, no residual arc from a free node into
+// them).  tcap sums the sink-side capacity, c0 the capacity of arcs running
+// straight from forced-source to forced-sink nodes (cut by every labelling).
+template <bool kWindow>
+__global__ void __launch_bounds__(kBlock)
+k_build(Graph s, const int32_t *__restrict__ cost, int m)
+{
+    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    long long tsum = 0, c0 = 0;
+    if (n < s.N) {
+        int j, y, x;
+        decode(s, n, j, y, x);
+        const int64_t site = (int64_t)y * s.W + x;
+        const int k = j + 1;
+        const bool hasE = x + 1 < s.W, hasS = y + 1 < s.H;
+        if (!kWindow) {
+            int32_t e = 0;
+            if (k == 1) e += cost[site];                                    // s -> v_1
+            if (k == m - 1) {                                                // v_{m-1} -> t
+                const int32_t gt = cost[(int64_t)(m - 1) * s.plane + site];
+                e -= gt;
+                tsum = gt;
+            }
+            s.ex[n] = e;
+            s.ht[n] = 0;
+            s.ein[n] = 0;
+            s.rd[n] = (j + 1 < s.J) ? cost[(int64_t)k * s.plane + site] : 0;
+            s.re[n] = hasE ? s.te / 2 : 0;
+            s.rs[n] = hasS ? s.ts / 2 : 0;
+            s.rem[n] = (hasE && j > 0) ? s.ie : 0;      // v_k -> E_{k-1} carries the capacity
+            s.rep[n] = 0;                               // its capacity runs E_{k+1} -> v_k
+            s.rsm[n] = (hasS && j > 0) ? s.is : 0;
+            s.rsp[n] = 0;
+        } else {
+            const int lo = s.wlo[site], hi = s.whi[site];
+            const int cn = node_class(k, lo, hi);
+            const unsigned ex_mask = arc_exists(s, j, y, x);
+            const int ph = s.te / 2, pv = s.ts / 2;
+            int32_t e = 0;
+#pragma unroll
+            for (int d = 0; d < 14; ++d) {
+                if (!((ex_mask >> d) & 1u)) continue;
+                const int dx = dir_dx(d), dy = dir_dy(d);
+                const int64_t psite = site + dy * (int64_t)s.W + dx;
+                const int cp = (dx == 0 && dy == 0) ? node_class(k + dir_dj(d), lo, hi)
+                                                    : node_class(k + dir_dj(d), s.wlo[psite], s.whi[psite]);
+                // capacities of n -> partner and partner -> n; the unbounded
+                // chain reverse never meets a forced partner of a free node
+                int32_t cout = 0, cin = 0;
+                switch (d) {
+                case D_DOWN: cout = cost[(int64_t)k * s.plane + site]; break;
+                case D_UP:   cin = cost[(int64_t)j * s.plane + site]; break;
+                case D_E: case D_W: cout = cin = ph; break;
+                case D_S: case D_N: cout = cin = pv; break;
+                case D_EM: case D_WM: cout = s.ie; break;
+                case D_EP: case D_WP: cin = s.ie; break;
+                case D_SM: case D_NM: cout = s.is; break;
+                default: cin = s.is; break;                  // D_SP, D_NP
+                }
+                if (cn == FREE) {
+                    if (cp == FSRC) e += cin;
+                    else if (cp == FSNK) { e -= cout; tsum += cout; }
+                } else if (cn == FSRC && cp == FSNK) {
+                    c0 += cout;
+                }
+                if (word_is_forward(d)) {
+                    int32_t wd = 0;
+                    if (cn == FREE) wd = cp == FREE ? cout : cp == FSRC ? cout + cin : 0;
+                    else if (cn == FSNK && cp == FREE) wd = cout + cin;
+                    *word_ptr(s, n, d) = wd;
+                }
+            }
+            if (!((ex_mask >> D_DOWN) & 1u)) s.rd[n] = 0;
+            if (!((ex_mask >> D_E) & 1u)) s.re[n] = 0;
+            if (!((ex_mask >> D_S) & 1u)) s.rs[n] = 0;
+            if (!((ex_mask >> D_EM) & 1u)) s.rem[n] = 0;
+            if (!((ex_mask >> D_EP) & 1u)) s.rep[n] = 0;
+            if (!((ex_mask >> D_SM) & 1u)) s.rsm[n] = 0;
+            if (!((ex_mask >> D_SP) & 1u)) s.rsp[n] = 0;
+            if (cn == FREE) {
+                if (j == 0) e += cost[site];                                  // from s
+                if (j + 1 == s.J) {                                           // into t
+                    const int32_t gt = cost[(int64_t)(m - 1) * s.plane + site];
+                    e -= gt;
+                    tsum += gt;
+                }
+            }
+            s.ex[n] = cn == FREE ? e : 0;
+            s.ht[n] = cn == FREE ? 0 : kInf;
+            s.ein[n] = 0;
+        }
+    }
+    tsum = block_sum(tsum);
+    __syncthreads();
+    c0 = block_sum(c0);
+    if (threadIdx.x == 0) {
+        if (tsum) atomicAdd((unsigned long long *)&my_slot(s.slots).tcap, (unsigned long long)tsum);
+        if (c0) atomicAdd((unsigned long long *)&my_slot(s.slots).c0, (unsigned long long)c0);
+    }
+}
+
+// Thin-skin windows from the delegate-point labels (Sec. 4.5): the labels of
+// the coarse group and of the groups directly above and below.
+__global__ void __launch_bounds__(kBlock)
+k_windows(Graph s, const int32_t *__restrict__ coarse_labels, int b, int m)
+{
+    int64_t site = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (site >= s.plane) return;
+    const int y = (int)(site / s.W), x = (int)(site - (int64_t)y * s.W);
+    const int wc = (s.W + b - 1) / b;
+    const int Sc = coarse_labels[(int64_t)(y / b) * wc + x / b];
+    const int lo = b * (Sc - 1), hi = b * (Sc + 2) - 1;
+    s.wlo[site] = lo < 0 ? 0 : lo;
+    s.whi[site] = hi > m - 1 ? m - 1 : hi;
+}
+
+// Delegate-point data term: the sum over the b x b sites of a coarse site of
+// the cheapest label in the coarse label group.
+__global__ void __launch_bounds__(kBlock)
+k_coarse_cost(const int32_t *__restrict__ cost, int W, int H, int m, int b,
+              int32_t *__restrict__ coarse)
+{
+    const int wc = (W + b - 1) / b, hc = (H + b - 1) / b;
+    const int X = blockIdx.x * blockDim.x + threadIdx.x;
+    const int Y = blockIdx.y, Sc = blockIdx.z;
+    if (X >= wc) return;
+    const int64_t plane = (int64_t)W * H;
+    int32_t sum = 0;
+    for (int y = Y * b; y < Y * b + b && y < H; ++y)
+        for (int x = X * b; x < X * b + b && x < W; ++x) {
+            int32_t best = 0x7fffffff;
+            for (int S = Sc * b; S < Sc * b + b && S < m; ++S) {
+                const int32_t g = cost[(int64_t)S * plane + (int64_t)y * W + x];
+                best = g < best ? g : best;
+            }
+            sum += best;
+        }
+    coarse[((int64_t)Sc * hc + Y) * wc + X] = sum;
 }
 
 // Push sweep.  All 14 stored words and neighbour heights of an active node
@@ -450,8 +583,16 @@ k_relabel(Graph s)
     if (nh > h) s.ht[n] = nh;
 }
 
+__device__ inline bool is_frozen(const Graph &s, int j, int y, int x)
+{
+    const int64_t site = (int64_t)y * s.W + x;
+    return node_class(j + 1, s.wlo[site], s.whi[site]) != FREE;
+}
+
 // mode 0: out-arc mask (distance to deficits); mode 1: in-arc mask
-// (reachability from excess).
+// (reachability from excess).  Forced nodes of a thin-skin graph get no
+// arcs, so relaxation never gives them a finite value.
+template <bool kWindow>
 __global__ void __launch_bounds__(kBlock)
 k_mask(Graph s, int mode)
 {
@@ -459,6 +600,7 @@ k_mask(Graph s, int mode)
     if (n >= s.N) return;
     int j, y, x;
     decode(s, n, j, y, x);
+    if (kWindow && is_frozen(s, j, y, x)) { s.mask[n] = 0; return; }
     unsigned mk = 0;
 #pragma unroll
     for (int d = 0; d < 14; ++d) {
@@ -470,12 +612,18 @@ k_mask(Graph s, int mode)
 
 // Seeds: mode 0 -> ht = 1 at deficit nodes, INF elsewhere;
 //        mode 1 -> aux = 0 at excess nodes, INF elsewhere.
+template <bool kWindow>
 __global__ void __launch_bounds__(kBlock)
 k_seed(Graph s, int mode)
 {
     int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (n >= s.N) return;
     int32_t e = s.ex[n];
+    if (kWindow) {
+        int j, y, x;
+        decode(s, n, j, y, x);
+        if (is_frozen(s, j, y, x)) e = 0;          // inert: never a seed
+    }
     if (mode == 0) s.ht[n] = e < 0 ? 1 : kInf;
     else s.aux[n] = e > 0 ? 0 : kInf;
 }
@@ -689,16 +837,19 @@ __global__ void k_zero_result(int64_t *r, DevHeader *h)
     if (threadIdx.x == 0) { r[0] = 0; r[1] = 0; if (h) h->prefix_err = 0; }
 }
 
-// Labels from the reachability values: X = reached nodes in the column,
-// which must form the prefix v_1..v_X.
+// Labels from the reachability values: X = source-side nodes in the column,
+// which must form the prefix v_1..v_X.  In a thin-skin graph the levels at
+// or above the window's top are source side by construction.
+template <bool kWindow>
 __global__ void __launch_bounds__(kBlock)
 k_labels(Graph s, int32_t *__restrict__ labels)
 {
     int64_t site = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (site >= s.plane) return;
-    int X = 0;
+    const int lo = kWindow ? s.wlo[site] : 0, hi = kWindow ? s.whi[site] : s.J;
+    int X = lo;
     bool gap = false, bad = false;
-    for (int j = 0; j < s.J; ++j) {
+    for (int j = lo; j < hi; ++j) {
         bool in = s.aux[(int64_t)j * s.plane + site] == 0;
         if (in) { if (gap) bad = true; ++X; }
         else gap = true;
@@ -713,7 +864,7 @@ __device__ inline long long pair_term(int h1, int h2, int d)
     return (long long)h1 * a + (a > 1 ? (long long)h2 * (a - 1) : 0LL);
 }
 
-// E(X) from its definition, and the terminal capacity sum for the flow.
+// E(X) from its definition (and the direct s -> t flow when m == 1).
 __global__ void __launch_bounds__(kBlock)
 k_energy(const int32_t *__restrict__ cost, const int32_t *__restrict__ labels, int W, int H,
          int m, int ph, int ih, int pv, int iv, Slot *__restrict__ slots)
@@ -727,7 +878,7 @@ k_energy(const int32_t *__restrict__ cost, const int32_t *__restrict__ labels, i
         e = cost[(int64_t)X * plane + site];
         if (x + 1 < W) e += pair_term(ph, ih, X - labels[site + 1]);
         if (y + 1 < H) e += pair_term(pv, iv, X - labels[site + W]);
-        tcap = cost[(int64_t)(m - 1) * plane + site];
+        if (m == 1) tcap = cost[site];          // no nodes: every s -> t arc carries g(0)
     }
     e = block_sum(e);
     __syncthreads();
@@ -738,7 +889,7 @@ k_energy(const int32_t *__restrict__ cost, const int32_t *__restrict__ labels, i
     }
 }
 
-// flow = sum of terminal capacities minus the deficits still unfilled.
+// Deficits still unfilled (subtracted from the sink-side capacity).
 __global__ void __launch_bounds__(kBlock)
 k_deficit(Graph s)
 {
@@ -755,13 +906,14 @@ __global__ void __launch_bounds__(kSlots)
 k_zero_slots(Slot *slots, int what)
 {
     Slot &sl = slots[threadIdx.x];
-    if (what == 0) { sl.pushes = 0; sl.active = 0; sl.e0 = 0; sl.e1 = 0; }
+    if (what == 0) { sl.pushes = 0; sl.active = 0; sl.e0 = 0; sl.e1 = 0; sl.tcap = 0; sl.c0 = 0; }
     else if (what == 1) sl.active = 0;
     else { sl.e0 = 0; sl.e1 = 0; }
 }
 
 // Folds the slots: what 0 -> hdr->active, 1 -> hdr->pushes,
-// 2 -> result[0] = energy, result[1] = flow.
+// 2 -> result[0] = energy, result[1] = flow (sink capacity + c0 - deficits),
+// 3 -> hdr->tcap, hdr->c0 after a build.
 __global__ void __launch_bounds__(kSlots)
 k_fold_slots(const Slot *slots, DevHeader *hdr, int what, int64_t *result)
 {
@@ -773,11 +925,16 @@ k_fold_slots(const Slot *slots, DevHeader *hdr, int what, int64_t *result)
     } else if (what == 1) {
         unsigned long long p = block_sum(sl.pushes);
         if (threadIdx.x == 0) hdr->pushes = p;
-    } else {
+    } else if (what == 2) {
         long long e0 = block_sum(sl.e0);
         __syncthreads();
         long long e1 = block_sum(sl.e1);
-        if (threadIdx.x == 0) { result[0] = e0; result[1] = e1; }
+        if (threadIdx.x == 0) { result[0] = e0; result[1] = e1 + hdr->tcap + hdr->c0; }
+    } else {
+        long long t = block_sum(sl.tcap);
+        __syncthreads();
+        long long c = block_sum(sl.c0);
+        if (threadIdx.x == 0) { hdr->tcap = t; hdr->c0 = c; }
     }
 }
 
@@ -961,8 +1118,9 @@ GC_API size_t gc_graph_footprint_bytes(const gc_problem *p)
 {
     if (gc_problem_check(p) != GC_OK) return 0;
     size_t n = (size_t)node_count(p);
+    const size_t sites = (size_t)p->width * p->height;
     return align256(sizeof(DevHeader)) + align256(kSlots * sizeof(Slot)) + 11 * align256(n * 4) +
-           align256(n * 2) + align256(max_tiles(p) * 4);
+           align256(n * 2) + 2 * align256(sites * 4) + align256(max_tiles(p) * 4);
 }
 
 GC_API int stereo_cost_volume(const uint8_t *left, const uint8_t *right, const gc_problem *p,
@@ -981,8 +1139,8 @@ GC_API int stereo_cost_volume(const uint8_t *left, const uint8_t *right, const g
     return hip_ok(hipGetLastError()) ? GC_OK : GC_E_HIP;
 }
 
-GC_API int graph_build(const gc_problem *p, const int32_t *cost, void *ws, size_t ws_bytes,
-                       gc_graph *g_out, void *stream)
+static int build_common(const gc_problem *p, const int32_t *cost, void *ws, size_t ws_bytes,
+                        gc_graph *g_out, int32_t block)
 {
     int rc = gc_problem_check(p);
     if (rc != GC_OK) return rc;
@@ -991,18 +1149,90 @@ GC_API int graph_build(const gc_problem *p, const int32_t *cost, void *ws, size_
     g_out->ws = ws;
     g_out->ws_bytes = ws_bytes;
     g_out->p = *p;
+    g_out->window_block = block;
+    g_out->reserved = 0;
+    return GC_OK;
+}
+
+GC_API int graph_build(const gc_problem *p, const int32_t *cost, void *ws, size_t ws_bytes,
+                       gc_graph *g_out, void *stream)
+{
+    int rc = build_common(p, cost, ws, ws_bytes, g_out, 0);
+    if (rc != GC_OK) return rc;
     Graph s = view(g_out);
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, st, s.hdr, 0);
     hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 0);
     if (s.N > 0)
-        hipLaunchKernelGGL(k_build, dim3(grid_for(s.N)), dim3(kBlock), 0, st, s, cost, p->labels);
+        hipLaunchKernelGGL(k_build<false>, dim3(grid_for(s.N)), dim3(kBlock), 0, st, s, cost,
+                           p->labels);
+    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, s.slots, s.hdr, 3, nullptr);
+    return hip_ok(hipGetLastError()) ? GC_OK : GC_E_HIP;
+}
+
+GC_API int gc_coarse_problem(const gc_problem *p, int32_t block, gc_problem *coarse)
+{
+    if (!p || !coarse || block < 1) return GC_E_ARG;
+    int rc = gc_problem_check(p);
+    if (rc != GC_OK) return rc;
+    const int64_t b = block, b2 = b * b;
+    if (b2 * p->cap > INT32_MAX || b2 * p->penalty_h > INT32_MAX || b2 * p->penalty_v > INT32_MAX)
+        return GC_E_CAP_OVERFLOW;
+    gc_problem c;
+    c.width = (int32_t)((p->width + b - 1) / b);
+    c.height = (int32_t)((p->height + b - 1) / b);
+    c.labels = (int32_t)((p->labels + b - 1) / b);
+    c.cap = (int32_t)(b2 * p->cap);
+    c.penalty_h = (int32_t)(b2 * p->penalty_h);
+    c.penalty_v = (int32_t)(b2 * p->penalty_v);
+    c.inhibit_h = p->inhibit_h;
+    c.inhibit_v = p->inhibit_v;
+    if ((rc = gc_problem_check(&c)) != GC_OK) return rc;
+    *coarse = c;
+    return GC_OK;
+}
+
+GC_API int coarse_cost_volume(const gc_problem *p, const int32_t *cost, int32_t block,
+                              int32_t *coarse_cost, void *stream)
+{
+    gc_problem c;
+    int rc = gc_coarse_problem(p, block, &c);
+    if (rc != GC_OK) return rc;
+    if (!cost || !coarse_cost) return GC_E_ARG;
+    if (c.width == 0 || c.height == 0) return GC_OK;
+    if (c.height > 65535 || c.labels > 65535) return GC_E_SHAPE;
+    dim3 grid(grid_for(c.width), (unsigned)c.height, (unsigned)c.labels);
+    hipLaunchKernelGGL(k_coarse_cost, grid, dim3(kBlock), 0, (hipStream_t)stream, cost, p->width,
+                       p->height, p->labels, block, coarse_cost);
+    return hip_ok(hipGetLastError()) ? GC_OK : GC_E_HIP;
+}
+
+GC_API int graph_build_window(const gc_problem *p, const int32_t *cost,
+                              const int32_t *coarse_labels, int32_t block, void *ws,
+                              size_t ws_bytes, gc_graph *g_out, void *stream)
+{
+    if (block < 1 || !coarse_labels) return GC_E_ARG;
+    gc_problem c;
+    int rc = gc_coarse_problem(p, block, &c);
+    if (rc != GC_OK) return rc;
+    if ((rc = build_common(p, cost, ws, ws_bytes, g_out, block)) != GC_OK) return rc;
+    Graph s = view(g_out);
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, st, s.hdr, 0);
+    hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 0);
+    if (s.plane > 0)
+        hipLaunchKernelGGL(k_windows, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, coarse_labels,
+                           block, p->labels);
+    if (s.N > 0)
+        hipLaunchKernelGGL(k_build<true>, dim3(grid_for(s.N)), dim3(kBlock), 0, st, s, cost,
+                           p->labels);
+    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, s.slots, s.hdr, 3, nullptr);
     return hip_ok(hipGetLastError()) ? GC_OK : GC_E_HIP;
 }
 
 static int graph_check(const gc_graph *g)
 {
-    if (!g || !g->ws) return GC_E_ARG;
+    if (!g || !g->ws || g->window_block < 0) return GC_E_ARG;
     int rc = gc_problem_check(&g->p);
     if (rc != GC_OK) return rc;
     if (g->ws_bytes < gc_graph_footprint_bytes(&g->p)) return GC_E_WORKSPACE;
@@ -1025,11 +1255,18 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
     }
     Launcher L{st, (opt.flags & GC_OPT_TIME_KERNELS) != 0, {}};
     const unsigned grid = grid_for(s.N);
+    const bool win = g->window_block > 0;
     int status = GC_OK;
     for (;;) {
         // exact global relabelling: BFS distance to the deficit nodes
-        L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_mask, dim3(grid), dim3(kBlock), 0, st, s, 0); });
-        L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_seed, dim3(grid), dim3(kBlock), 0, st, s, 0); });
+        L.run(GC_K_OTHER, [&] {
+            if (win) hipLaunchKernelGGL(k_mask<true>, dim3(grid), dim3(kBlock), 0, st, s, 0);
+            else hipLaunchKernelGGL(k_mask<false>, dim3(grid), dim3(kBlock), 0, st, s, 0);
+        });
+        L.run(GC_K_OTHER, [&] {
+            if (win) hipLaunchKernelGGL(k_seed<true>, dim3(grid), dim3(kBlock), 0, st, s, 0);
+            else hipLaunchKernelGGL(k_seed<false>, dim3(grid), dim3(kBlock), 0, st, s, 0);
+        });
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
         if ((rc = relax_to_fixpoint(s, s.ht, 1, opt, L, &st_local.bfs_passes)) != GC_OK) return rc;
         st_local.global_relabels++;
@@ -1071,17 +1308,24 @@ GC_API int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *label
     Opts opt = resolve(nullptr);
     Launcher L{st, false, {}};
     int passes = 0;
+    const bool win = g->window_block > 0;
     if (s.N > 0) {
         const unsigned grid = grid_for(s.N);
-        hipLaunchKernelGGL(k_mask, dim3(grid), dim3(kBlock), 0, st, s, 1);
-        hipLaunchKernelGGL(k_seed, dim3(grid), dim3(kBlock), 0, st, s, 1);
+        if (win) {
+            hipLaunchKernelGGL(k_mask<true>, dim3(grid), dim3(kBlock), 0, st, s, 1);
+            hipLaunchKernelGGL(k_seed<true>, dim3(grid), dim3(kBlock), 0, st, s, 1);
+        } else {
+            hipLaunchKernelGGL(k_mask<false>, dim3(grid), dim3(kBlock), 0, st, s, 1);
+            hipLaunchKernelGGL(k_seed<false>, dim3(grid), dim3(kBlock), 0, st, s, 1);
+        }
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
         if ((rc = relax_to_fixpoint(s, s.aux, 0, opt, L, &passes)) != GC_OK) return rc;
     }
     hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(64), 0, st, result, s.hdr);
     hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 2);
     if (s.plane > 0) {
-        hipLaunchKernelGGL(k_labels, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
+        if (win) hipLaunchKernelGGL(k_labels<true>, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
+        else hipLaunchKernelGGL(k_labels<false>, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
         hipLaunchKernelGGL(k_energy, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, cost, labels,
                            p.width, p.height, p.labels, p.penalty_h, p.inhibit_h, p.penalty_v,
                            p.inhibit_v, s.slots);

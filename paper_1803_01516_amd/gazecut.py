@@ -24,7 +24,8 @@ class GcProblem(ctypes.Structure):
 
 
 class GcGraph(ctypes.Structure):
-    _fields_ = [("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t), ("p", GcProblem)]
+    _fields_ = [("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t), ("p", GcProblem),
+                ("window_block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class GcSolveOpts(ctypes.Structure):
@@ -55,7 +56,8 @@ class GcSolveStats(ctypes.Structure):
 
 
 EXPORTS = ("gc_status_str", "gc_last_hip_error", "gc_problem_check", "gc_graph_footprint_bytes",
-           "stereo_cost_volume", "graph_build", "maxflow_solve", "extract_labels")
+           "stereo_cost_volume", "graph_build", "maxflow_solve", "extract_labels",
+           "gc_coarse_problem", "coarse_cost_volume", "graph_build_window")
 
 _lib = None
 
@@ -98,6 +100,14 @@ def load(path: str = LIB_PATH):
     lib.maxflow_solve.restype = ctypes.c_int
     lib.extract_labels.argtypes = [ctypes.POINTER(GcGraph), P, P, P, P]
     lib.extract_labels.restype = ctypes.c_int
+    lib.gc_coarse_problem.argtypes = [ctypes.POINTER(GcProblem), ctypes.c_int32,
+                                      ctypes.POINTER(GcProblem)]
+    lib.gc_coarse_problem.restype = ctypes.c_int
+    lib.coarse_cost_volume.argtypes = [ctypes.POINTER(GcProblem), P, ctypes.c_int32, P, P]
+    lib.coarse_cost_volume.restype = ctypes.c_int
+    lib.graph_build_window.argtypes = [ctypes.POINTER(GcProblem), P, P, ctypes.c_int32, P,
+                                       ctypes.c_size_t, ctypes.POINTER(GcGraph), P]
+    lib.graph_build_window.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -194,3 +204,55 @@ def solve_pair(left, right, p: GcProblem, opts: GcSolveOpts | None = None, strea
     extract_labels(g, cost, labels, result, stream)
     r = result.cpu()
     return labels, cost, int(r[0]), int(r[1]), st
+
+
+# ---------------------------------------------------------------------------
+# Hierarchical approximation, level 1 (Sec. 4.5)
+# ---------------------------------------------------------------------------
+
+def coarse_problem(p: GcProblem, block: int) -> GcProblem:
+    c = GcProblem()
+    _check(load().gc_coarse_problem(ctypes.byref(p), int(block), ctypes.byref(c)), "gc_coarse_problem")
+    return c
+
+
+def coarse_cost_volume(p: GcProblem, cost, block: int, coarse_cost, stream=None):
+    _check(load().coarse_cost_volume(ctypes.byref(p), ctypes.c_void_p(cost.data_ptr()), int(block),
+                                     ctypes.c_void_p(coarse_cost.data_ptr()), _stream_ptr(stream)),
+           "coarse_cost_volume")
+
+
+def graph_build_window(p: GcProblem, cost, coarse_labels, block: int, ws, stream=None) -> Graph:
+    g = GcGraph()
+    _check(load().graph_build_window(ctypes.byref(p), ctypes.c_void_p(cost.data_ptr()),
+                                     ctypes.c_void_p(coarse_labels.data_ptr()), int(block),
+                                     ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                     ctypes.byref(g), _stream_ptr(stream)), "graph_build_window")
+    return Graph(g, ws)
+
+
+def approx_level1(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, stream=None,
+                  ws=None, ws_coarse=None):
+    """Delegate-point cut, then the exact cut inside the thin skin.  Returns
+    (labels, energy, flow, coarse labels, (coarse stats, fine stats))."""
+    import torch
+    dev = cost.device
+    c = coarse_problem(p, block)
+    ccost = torch.empty((c.labels, c.height, c.width), dtype=torch.int32, device=dev)
+    clab = torch.empty((c.height, c.width), dtype=torch.int32, device=dev)
+    cres = torch.zeros(2, dtype=torch.int64, device=dev)
+    if ws_coarse is None:
+        ws_coarse = alloc_workspace(c, dev)
+    coarse_cost_volume(p, cost, block, ccost, stream)
+    gcoarse = graph_build(c, ccost, ws_coarse, stream)
+    st_c = maxflow_solve(gcoarse, opts, stream)
+    extract_labels(gcoarse, ccost, clab, cres, stream)
+    if ws is None:
+        ws = alloc_workspace(p, dev)
+    labels = torch.empty((p.height, p.width), dtype=torch.int32, device=dev)
+    res = torch.zeros(2, dtype=torch.int64, device=dev)
+    gfine = graph_build_window(p, cost, clab, block, ws, stream)
+    st_f = maxflow_solve(gfine, opts, stream)
+    extract_labels(gfine, cost, labels, res, stream)
+    r = res.cpu()
+    return labels, int(r[0]), int(r[1]), clab, (st_c, st_f)

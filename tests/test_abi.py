@@ -33,7 +33,10 @@ def test_problem_validation_and_footprint():
     assert gc.problem_check(ok) == 0
     n = 384 * 288 * 15
     fp = gc.footprint_bytes(ok)
-    assert fp >= 46 * n and fp < 46 * n + 96 * 1024
+    sites = 384 * 288
+    tiles = (384 // 8) * (288 // 4) * ((15 + 3) // 4)     # stamp per 8x4x4 relaxation tile
+    base = 46 * n + 8 * sites + 4 * tiles
+    assert base <= fp < base + 64 * 1024
     assert gc.problem_check(gc.problem(4, 4, 0, 30, 1, 1023)) == -2      # labels < 1
     assert gc.problem_check(gc.problem(-1, 4, 4, 30, 1, 1023)) == -2
     assert gc.problem_check(gc.problem(4, 4, 4, 30, -1, 1023)) == -1     # eq. (1) needs >= 0
@@ -43,6 +46,20 @@ def test_problem_validation_and_footprint():
     assert gc.footprint_bytes(big) == 0
     assert gc.problem_check(gc.problem(0, 0, 1, 30, 1, 1023)) == 0      # empty is valid
     assert gc.load().gc_status_str(-5).decode().startswith("iteration cap")
+
+
+def test_coarse_problem_sizes():
+    p = gc.problem(384, 288, 16, 30, 1, 1023)
+    c = gc.coarse_problem(p, 3)
+    assert (c.width, c.height, c.labels, c.cap) == (128, 96, 6, 270)
+    assert (c.penalty_h, c.inhibit_h, c.penalty_v, c.inhibit_v) == (9, 1023, 9, 1023)
+    c = gc.coarse_problem(gc.problem(37, 19, 5, 20, 2, 7, 1, 0), 2)
+    assert (c.width, c.height, c.labels, c.cap, c.penalty_h, c.penalty_v, c.inhibit_v) == \
+        (19, 10, 3, 80, 8, 4, 0)
+    c1 = gc.coarse_problem(p, 1)
+    assert (c1.width, c1.height, c1.labels, c1.cap, c1.penalty_h) == (384, 288, 16, 30, 1)
+    with pytest.raises(gc.GazecutError):
+        gc.coarse_problem(p, 0)
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

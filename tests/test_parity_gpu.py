@@ -166,3 +166,43 @@ def test_repeat_solves_identical(torch_cuda, orc):
     for lab, e, f in outs[1:]:
         assert (lab == outs[0][0]).all() and e == outs[0][1] and f == outs[0][2]
     _check_against_oracle(orc, cost_np, outs[0][0], outs[0][1], outs[0][2], (1, 1023, 1, 1023))
+
+
+# ---------------------------------------------------------------------------
+# Hierarchical approximation, level 1 (Sec. 4.5)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("b", [1, 2, 3])
+@pytest.mark.parametrize("spec,seed", [(sg.TINY, (1, 0)), (sg.spec_like(sg.MID, 70, 33, 9), (9, 8)),
+                                       (sg.spec_like(sg.MID, 128, 96, 16), (5, 5))])
+def test_approx_level1_parity(torch_cuda, orc, b, spec, seed):
+    pr = sg.make_pair(spec, seed)
+    cost_np = orc.cost_volume(pr.left, pr.right, spec.m, spec.cap)
+    p = gc.problem(spec.w, spec.h, spec.m, spec.cap, 1, 1023)
+    cost = torch_cuda.from_numpy(cost_np).cuda()
+    cc = torch_cuda.empty((-(-spec.m // b), -(-spec.h // b), -(-spec.w // b)), dtype=torch_cuda.int32,
+                          device="cuda")
+    gc.coarse_cost_volume(p, cost, b, cc)
+    assert (cc.cpu().numpy() == orc.coarse_cost(cost_np, b)).all()
+    labels, energy, flow, clab, _ = gc.approx_level1(p, cost, b)
+    ref_lab, ref_e, ref_cl = orc.approx_level1(cost_np, b, 1, 1023)
+    assert (clab.cpu().numpy() == ref_cl).all()
+    assert energy == ref_e == flow
+    assert (labels.cpu().numpy() == ref_lab).all()
+    if b == 1:
+        ol, of, oe = orc.solve(cost_np, 1, 1023)
+        assert energy == oe and (labels.cpu().numpy() == ol).all()
+
+
+@pytest.mark.parametrize("b", [2, 3])
+def test_approx_level1_mid_full_size(torch_cuda, orc, b):
+    pr = sg.make_pair(sg.MID, (2, 0))
+    p = gc.problem(sg.MID.w, sg.MID.h, sg.MID.m, sg.MID.cap, 1, 1023)
+    cost_np = orc.cost_volume(pr.left, pr.right, sg.MID.m, sg.MID.cap)
+    cost = torch_cuda.from_numpy(cost_np).cuda()
+    labels, energy, flow, clab, _ = gc.approx_level1(p, cost, b)
+    ref_lab, ref_e, _ = orc.approx_level1(cost_np, b, 1, 1023)
+    assert energy == ref_e == flow
+    assert (labels.cpu().numpy() == ref_lab).all()
+    _, _, opt = orc.solve(cost_np, 1, 1023)
+    assert energy >= opt
