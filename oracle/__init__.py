@@ -92,6 +92,8 @@ def _load():
     lib.orc_approx_level1.restype = I
     lib.orc_brute_force_window.argtypes = [P, I, I, I, I, I, I, I, P, P, P, P]
     lib.orc_brute_force_window.restype = I
+    lib.orc_approx_level2.argtypes = [P, I, I, I, I, I, I, I, I, P, P, P]
+    lib.orc_approx_level2.restype = I
     _lib = lib
     return lib
 
@@ -304,3 +306,16 @@ def brute_force_window(cost: np.ndarray, lo: np.ndarray, hi: np.ndarray, pen_h: 
                                           _ptr(lo), _ptr(hi), _ptr(e), _ptr(lab)),
            "brute_force_window")
     return int(e[0]), lab
+
+
+def approx_level2(cost: np.ndarray, b: int, pen_h: int, inh_h: int, pen_v: int | None = None,
+                  inh_v: int | None = None):
+    """Level-2 approximation (Sec. 4.5).  Returns (labels, energy, coarse labels)."""
+    cost = np.ascontiguousarray(cost, dtype=np.int32)
+    m, h, w = cost.shape
+    lab = np.empty((h, w), dtype=np.int32)
+    cl = np.empty((-(-h // b), -(-w // b)), dtype=np.int32)
+    e = np.zeros(1, dtype=np.int64)
+    _check(_load().orc_approx_level2(_ptr(cost), w, h, m, *_params(pen_h, inh_h, pen_v, inh_v),
+                                     int(b), _ptr(lab), _ptr(e), _ptr(cl)), "approx_level2")
+    return lab, int(e[0]), cl

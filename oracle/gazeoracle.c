@@ -717,6 +717,209 @@ int orc_approx_level1(const int32_t *cost, int w, int h, int m, int pen_h, int i
     return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Hierarchical approximation, level 2 (Sec. 4.5).                           */
+/*                                                                          */
+/* The wave-front pass runs over the whole thin skin and the push-relabel   */
+/* loop cuts every b x b x b block separately.  Readings (the paper omits    */
+/* the details): the wave front is one pass down every column of the skin,  */
+/* from its top to its bottom, in which each free node hands the chain arc  */
+/* below it as much of its excess as the arc's residual allows; a block is   */
+/* b x b sites by b node levels (node v_k in level group (k-1)/b); each      */
+/* block's cut is its exact minimum cut with the arcs leaving the block      */
+/* unused, read off as the minimal source side; a site's label is the        */
+/* deepest source-side node of its column (the unbounded upward chain arcs   */
+/* put everything above it on the source side too).                         */
+/*                                                                          */
+/* State here is the skin with its terminals folded into node balances:     */
+/* bal[v] = capacity of arcs into v from forced-source nodes (and s) minus   */
+/* capacity of arcs from v to forced-sink nodes (and t); res[v][d] is the    */
+/* residual of the arc from v to its neighbour in direction d, kept only    */
+/* between two free nodes.                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* neighbour offsets (dk, dy, dx) of the 14 arcs of a node v_k */
+static const int NB[14][3] = {
+    {+1, 0, 0}, {-1, 0, 0},                      /* chain down / up          */
+    {0, 0, +1}, {0, 0, -1}, {0, +1, 0}, {0, -1, 0}, /* same level E W S N     */
+    {-1, 0, +1}, {+1, 0, +1}, {-1, 0, -1}, {+1, 0, -1}, /* E/W one level up/down */
+    {-1, +1, 0}, {+1, +1, 0}, {-1, -1, 0}, {+1, -1, 0}  /* S/N one level up/down */
+};
+
+/* Capacity of the arc from v_k (site x, y) to its neighbour in direction d
+ * (Sec. 3, Fig. 4): chain down g(k), chain up unbounded, same level h1,
+ * one level up (shallower) h2, one level down 0. */
+static int64_t arc_cap(const int32_t *cost, int w, int h, int x, int y, int k, int d,
+                       int pen_h, int inh_h, int pen_v, int inh_v)
+{
+    int dk = NB[d][0], dy = NB[d][1];
+    if (d == 0) return cost[((int64_t)k * h + y) * w + x];
+    if (d == 1) return ORC_INF;
+    int horiz = dy == 0;
+    if (dk == 0) return horiz ? pen_h : pen_v;
+    if (dk < 0) return horiz ? inh_h : inh_v;
+    return 0;
+}
+
+/* Tiny max-flow by shortest augmenting paths on a dense matrix. */
+static int64_t ek_maxflow(int n, int64_t *cap, int src, int snk, uint8_t *src_side)
+{
+    int64_t flow = 0;
+    int *prev = (int *)malloc(sizeof(int) * n), *q = (int *)malloc(sizeof(int) * n);
+    for (;;) {
+        for (int i = 0; i < n; i++) prev[i] = -1;
+        int qh = 0, qt = 0;
+        q[qt++] = src; prev[src] = src;
+        while (qh < qt && prev[snk] < 0) {
+            int u = q[qh++];
+            for (int v = 0; v < n; v++)
+                if (prev[v] < 0 && cap[(int64_t)u * n + v] > 0) { prev[v] = u; q[qt++] = v; }
+        }
+        if (prev[snk] < 0) break;
+        int64_t b = ORC_INF;
+        for (int v = snk; v != src; v = prev[v])
+            if (cap[(int64_t)prev[v] * n + v] < b) b = cap[(int64_t)prev[v] * n + v];
+        for (int v = snk; v != src; v = prev[v]) {
+            cap[(int64_t)prev[v] * n + v] -= b;
+            cap[(int64_t)v * n + prev[v]] += b;
+        }
+        flow += b;
+    }
+    /* minimal source side: reachable from src in the residual network */
+    for (int i = 0; i < n; i++) src_side[i] = prev[i] >= 0;
+    free(prev); free(q);
+    return flow;
+}
+
+int orc_approx_level2(const int32_t *cost, int w, int h, int m, int pen_h, int inh_h,
+                      int pen_v, int inh_v, int b, int32_t *labels, int64_t *energy,
+                      int32_t *coarse_labels)
+{
+    if (b < 1 || m < 2) return ORC_E_ARG;
+    int wc = (w + b - 1) / b, hc = (h + b - 1) / b, mc = (m + b - 1) / b;
+    size_t ns = (size_t)w * h, nn = ns * (size_t)(m - 1);
+    int32_t *cc = (int32_t *)malloc(((size_t)mc * wc * hc + 1) * sizeof(int32_t));
+    int32_t *cl = (int32_t *)malloc(((size_t)wc * hc + 1) * sizeof(int32_t));
+    int32_t *lo = (int32_t *)malloc((ns + 1) * sizeof(int32_t));
+    int32_t *hi = (int32_t *)malloc((ns + 1) * sizeof(int32_t));
+    int64_t *bal = (int64_t *)calloc(nn + 1, sizeof(int64_t));
+    int64_t *res = (int64_t *)calloc(nn * 14 + 1, sizeof(int64_t));
+    uint8_t *in_s = (uint8_t *)calloc(nn + 1, 1);
+    int rc = ORC_E_NOMEM;
+    if (!cc || !cl || !lo || !hi || !bal || !res || !in_s) goto done;
+    {
+        int64_t f, e;
+        rc = orc_coarse_cost(cost, w, h, m, b, cc);
+        if (rc == ORC_OK)
+            rc = orc_solve(cc, wc, hc, mc, b * b * pen_h, inh_h, b * b * pen_v, inh_v, 1, cl, &f, &e);
+        if (rc == ORC_OK) rc = orc_skin_windows(cl, w, h, m, b, lo, hi);
+        if (rc != ORC_OK) goto done;
+    }
+#define NODE(x, y, k) ((((size_t)(k) - 1) * h + (y)) * w + (x))
+#define FREE(x, y, k) ((k) > lo[(y) * w + (x)] && (k) <= hi[(y) * w + (x)])
+    /* folded skin: balances and free-to-free residuals */
+    for (int k = 1; k <= m - 1; k++)
+        for (int y = 0; y < h; y++)
+            for (int x = 0; x < w; x++) {
+                if (!FREE(x, y, k)) continue;
+                size_t v = NODE(x, y, k);
+                for (int d = 0; d < 14; d++) {
+                    int k2 = k + NB[d][0], y2 = y + NB[d][1], x2 = x + NB[d][2];
+                    if (x2 < 0 || x2 >= w || y2 < 0 || y2 >= h) continue;
+                    int lat = NB[d][1] != 0 || NB[d][2] != 0;
+                    if (lat && (k2 < 1 || k2 > m - 1)) continue;     /* no lateral arc to s or t */
+                    int64_t cout = arc_cap(cost, w, h, x, y, k, d, pen_h, inh_h, pen_v, inh_v);
+                    /* capacity of the arc back from the neighbour */
+                    int64_t cin;
+                    if (d == 0) cin = ORC_INF;
+                    else if (d == 1) cin = cost[((int64_t)(k - 1) * h + y) * w + x];
+                    else cin = arc_cap(cost, w, h, x2, y2, k2, d ^ ((d >= 2 && d <= 5) ? 1 : 0),
+                                       pen_h, inh_h, pen_v, inh_v);
+                    if (d >= 6) {
+                        /* opposite of a diagonal: one level the other way */
+                        int up = NB[d][0] < 0;
+                        int horiz = NB[d][1] == 0;
+                        cin = up ? 0 : (horiz ? inh_h : inh_v);
+                    }
+                    int src = k2 <= (k2 >= 1 && k2 <= m - 1 ? lo[y2 * w + x2] : 0) || k2 == 0;
+                    int snk = k2 == m || (k2 >= 1 && k2 <= m - 1 && k2 > hi[y2 * w + x2]);
+                    if (src) bal[v] += cin;
+                    else if (snk) bal[v] -= cout;
+                    else res[v * 14 + d] = cout;
+                }
+            }
+    /* wave front: one pass down every column of the skin */
+    for (int y = 0; y < h; y++)
+        for (int x = 0; x < w; x++)
+            for (int k = lo[y * w + x] + 1; k < hi[y * w + x]; k++) {
+                size_t v = NODE(x, y, k), u = NODE(x, y, k + 1);
+                int64_t d = bal[v] < res[v * 14 + 0] ? bal[v] : res[v * 14 + 0];
+                if (d <= 0) continue;
+                bal[v] -= d; bal[u] += d;
+                res[v * 14 + 0] -= d;
+                /* the reverse (upward) arc is unbounded either way */
+            }
+    /* every b x b x b block on its own */
+    {
+        int nbk = (m - 1 + b - 1) / b;
+        int cap_nodes = b * b * b + 2;
+        int64_t *C = (int64_t *)malloc(sizeof(int64_t) * cap_nodes * cap_nodes);
+        uint8_t *side = (uint8_t *)malloc(cap_nodes);
+        size_t *ids = (size_t *)malloc(sizeof(size_t) * cap_nodes);
+        int *kx = (int *)malloc(sizeof(int) * cap_nodes * 3);
+        if (!C || !side || !ids || !kx) { free(C); free(side); free(ids); free(kx); rc = ORC_E_NOMEM; goto done; }
+        for (int K = 0; K < nbk; K++)
+            for (int Y = 0; Y < hc; Y++)
+                for (int X = 0; X < wc; X++) {
+                    int n = 0;
+                    for (int k = K * b + 1; k <= K * b + b && k <= m - 1; k++)
+                        for (int y = Y * b; y < Y * b + b && y < h; y++)
+                            for (int x = X * b; x < X * b + b && x < w; x++)
+                                if (FREE(x, y, k)) {
+                                    ids[n] = NODE(x, y, k);
+                                    kx[3 * n] = k; kx[3 * n + 1] = y; kx[3 * n + 2] = x;
+                                    n++;
+                                }
+                    if (n == 0) continue;
+                    int N2 = n + 2, S = n, T = n + 1;
+                    memset(C, 0, sizeof(int64_t) * N2 * N2);
+                    for (int i = 0; i < n; i++) {
+                        size_t v = ids[i];
+                        if (bal[v] > 0) C[(int64_t)S * N2 + i] = bal[v];
+                        if (bal[v] < 0) C[(int64_t)i * N2 + T] = -bal[v];
+                        for (int d = 0; d < 14; d++) {
+                            int k2 = kx[3 * i] + NB[d][0], y2 = kx[3 * i + 1] + NB[d][1],
+                                x2 = kx[3 * i + 2] + NB[d][2];
+                            for (int j2 = 0; j2 < n; j2++)
+                                if (kx[3 * j2] == k2 && kx[3 * j2 + 1] == y2 && kx[3 * j2 + 2] == x2) {
+                                    int64_t r = d == 1 ? ORC_INF : res[v * 14 + d];
+                                    C[(int64_t)i * N2 + j2] += r;
+                                }
+                        }
+                    }
+                    ek_maxflow(N2, C, S, T, side);
+                    for (int i = 0; i < n; i++) in_s[ids[i]] = side[i];
+                }
+        free(C); free(side); free(ids); free(kx);
+    }
+    /* deepest source-side node of every column */
+    for (int y = 0; y < h; y++)
+        for (int x = 0; x < w; x++) {
+            int X = lo[y * w + x];
+            for (int k = lo[y * w + x] + 1; k <= hi[y * w + x]; k++)
+                if (in_s[NODE(x, y, k)]) X = k;
+            labels[y * w + x] = X;
+        }
+#undef NODE
+#undef FREE
+    *energy = orc_energy(cost, labels, w, h, m, pen_h, inh_h, pen_v, inh_v);
+    if (coarse_labels) memcpy(coarse_labels, cl, (size_t)wc * hc * sizeof(int32_t));
+    rc = ORC_OK;
+done:
+    free(cc); free(cl); free(lo); free(hi); free(bal); free(res); free(in_s);
+    return rc;
+}
+
 /* Brute force restricted to per-site windows (tiny grids only). */
 int orc_brute_force_window(const int32_t *cost, int w, int h, int m, int pen_h, int inh_h,
                            int pen_v, int inh_v, const int32_t *lo, const int32_t *hi,

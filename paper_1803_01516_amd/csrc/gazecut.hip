@@ -939,6 +939,195 @@ k_fold_slots(const Slot *slots, DevHeader *hdr, int what, int64_t *result)
 }
 
 // ---------------------------------------------------------------------------
+// Level-2 approximation (Sec. 4.5): wave-front pass over the skin, then every
+// b x b x b block cut on its own.
+// ---------------------------------------------------------------------------
+
+// Wave front: one pass down every column of the skin; each free node hands
+// the chain arc below it as much of its excess as the arc's residual allows.
+__global__ void __launch_bounds__(kBlock)
+k_wave(Graph s)
+{
+    int64_t site = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (site >= s.plane) return;
+    const int lo = s.wlo[site], hi = s.whi[site];
+    for (int k = lo + 1; k < hi; ++k) {
+        const int64_t n = (int64_t)(k - 1) * s.plane + site;
+        const int32_t e = s.ex[n], r = s.rd[n];
+        const int32_t d = e < r ? e : r;
+        if (d <= 0) continue;
+        s.ex[n] = e - d;
+        s.ex[n + s.plane] += d;
+        s.rd[n] = r - d;
+    }
+}
+
+constexpr int32_t kUpRes = 1 << 29;     // residual of an unbounded arc inside a block
+constexpr int kBlockLanes = 64;
+
+// Exact cut of one b x b x b block (b <= 4) with the arcs that leave the
+// block unused: one 64-lane workgroup, one lane per node, state in LDS.
+// Synchronous push-relabel with exact in-block BFS heights until no node
+// with excess reaches a deficit, then the block's minimal source side
+// (reachability from the remaining excess) goes to aux (0 = source side).
+__global__ void __launch_bounds__(kBlockLanes)
+k_block_cut(Graph s, int b, int max_outer)
+{
+    __shared__ int32_t e[kBlockLanes], hgt[kBlockLanes], ein[kBlockLanes];
+    __shared__ int32_t res[kBlockLanes][14];
+    __shared__ int s_part[kBlockLanes];
+    __shared__ int s_flag;
+    const int l = threadIdx.x;
+    const int nb = b * b * b;
+    const int lx = l % b, ly = (l / b) % b, lk = l / (b * b);
+    const int x = blockIdx.x * b + lx, y = blockIdx.y * b + ly, j = blockIdx.z * b + lk;
+    bool part = false;
+    int64_t n = 0;
+    if (l < nb && x < s.W && y < s.H && j < s.J) {
+        const int64_t site = (int64_t)y * s.W + x;
+        part = node_class(j + 1, s.wlo[site], s.whi[site]) == FREE;
+        n = (int64_t)j * s.plane + site;
+    }
+    // local index of the neighbour in direction d, or -1 outside the block
+    auto lnb = [&](int d) -> int {
+        const int nx = lx + dir_dx(d), ny = ly + dir_dy(d), nk = lk + dir_dj(d);
+        if (nx < 0 || nx >= b || ny < 0 || ny >= b || nk < 0 || nk >= b) return -1;
+        return (nk * b + ny) * b + nx;
+    };
+    e[l] = 0; ein[l] = 0; hgt[l] = kInf;
+    s_part[l] = part ? 1 : 0;
+#pragma unroll
+    for (int d = 0; d < 14; ++d) res[l][d] = 0;
+    __syncthreads();
+    if (part) {
+        int j_, y_, x_;
+        decode(s, n, j_, y_, x_);
+        const unsigned ex_mask = arc_exists(s, j_, y_, x_);
+        e[l] = s.ex[n];
+#pragma unroll
+        for (int d = 0; d < 14; ++d) {
+            if (!((ex_mask >> d) & 1u)) continue;
+            const int q = lnb(d);
+            if (q < 0 || !s_part[q]) continue;      // only arcs between free nodes of the block
+            res[l][d] = d == D_UP ? kUpRes : res_from_word(s, d, *word_ptr(s, n, d));
+        }
+    }
+    __syncthreads();
+    int outer = 0;
+    for (; outer < max_outer; ++outer) {
+        // exact in-block distance to a deficit
+        hgt[l] = (part && e[l] < 0) ? 1 : kInf;
+        __syncthreads();
+        for (int r = 0; r < nb; ++r) {
+            if (l == 0) s_flag = 0;
+            __syncthreads();
+            if (part && e[l] >= 0) {
+                int32_t best = hgt[l];
+#pragma unroll
+                for (int d = 0; d < 14; ++d) {
+                    const int q = lnb(d);
+                    if (q >= 0 && res[l][d] > 0) {
+                        const int32_t c = hgt[q] + 1;
+                        best = c < best ? c : best;
+                    }
+                }
+                if (best < hgt[l]) { hgt[l] = best; s_flag = 1; }
+            }
+            __syncthreads();
+            const int f = s_flag;
+            __syncthreads();
+            if (!f) break;
+        }
+        if (l == 0) s_flag = 0;
+        __syncthreads();
+        if (part && e[l] > 0 && hgt[l] < kInf) s_flag = 1;
+        __syncthreads();
+        const int any = s_flag;
+        __syncthreads();
+        if (!any) break;
+        for (int sweep = 0; sweep < 2 * nb; ++sweep) {
+            // push: heights are read-only, one writer per arc pair
+            if (part && e[l] > 0 && hgt[l] < kInf) {
+                int32_t ev = e[l];
+#pragma unroll
+                for (int d = 0; d < 14; ++d) {
+                    const int q = lnb(d);
+                    if (ev == 0 || q < 0) continue;
+                    const int32_t r = res[l][d];
+                    if (r > 0 && hgt[q] == hgt[l] - 1) {
+                        const int32_t dl = ev < r ? ev : r;
+                        res[l][d] = r - dl;
+                        const int od = d <= D_N ? (d ^ 1) : (d == D_EM ? D_WP : d == D_WP ? D_EM :
+                                       d == D_EP ? D_WM : d == D_WM ? D_EP : d == D_SM ? D_NP :
+                                       d == D_NP ? D_SM : d == D_SP ? D_NM : D_SP);
+                        atomicAdd(&res[q][od], dl);
+                        atomicAdd(&ein[q], dl);
+                        ev -= dl;
+                    }
+                }
+                e[l] = ev;
+            }
+            __syncthreads();
+            // relabel
+            if (part) {
+                e[l] += ein[l];
+                ein[l] = 0;
+            }
+            __syncthreads();
+            if (part && e[l] > 0 && hgt[l] < kInf) {
+                int32_t hmin = kInf;
+#pragma unroll
+                for (int d = 0; d < 14; ++d) {
+                    const int q = lnb(d);
+                    if (q >= 0 && res[l][d] > 0) hmin = hgt[q] < hmin ? hgt[q] : hmin;
+                }
+                const int32_t nh = hmin >= kInf ? kInf : hmin + 1;
+                if (nh > hgt[l]) hgt[l] = nh;
+            }
+            __syncthreads();
+        }
+    }
+    // minimal source side of the block: reachable from the remaining excess
+    hgt[l] = (part && e[l] > 0) ? 0 : kInf;
+    __syncthreads();
+    for (int r = 0; r < nb; ++r) {
+        if (l == 0) s_flag = 0;
+        __syncthreads();
+        if (part && hgt[l] != 0) {
+#pragma unroll
+            for (int d = 0; d < 14; ++d) {
+                const int q = lnb(d);
+                if (q < 0) continue;
+                const int od = d <= D_N ? (d ^ 1) : (d == D_EM ? D_WP : d == D_WP ? D_EM :
+                               d == D_EP ? D_WM : d == D_WM ? D_EP : d == D_SM ? D_NP :
+                               d == D_NP ? D_SM : d == D_SP ? D_NM : D_SP);
+                if (hgt[q] == 0 && res[q][od] > 0) { hgt[l] = 0; s_flag = 1; }
+            }
+        }
+        __syncthreads();
+        const int f = s_flag;
+        __syncthreads();
+        if (!f) break;
+    }
+    if (part) s.aux[n] = hgt[l] == 0 ? 0 : kInf;
+    if (l == 0 && outer >= max_outer) atomicOr(&s.hdr->prefix_err, 2);
+}
+
+// Label = deepest source-side node of the column (everything above it is on
+// the source side through the unbounded upward chain arcs).
+__global__ void __launch_bounds__(kBlock)
+k_labels_closure(Graph s, int32_t *__restrict__ labels)
+{
+    int64_t site = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (site >= s.plane) return;
+    const int lo = s.wlo[site], hi = s.whi[site];
+    int X = lo;
+    for (int k = lo + 1; k <= hi; ++k)
+        if (s.aux[(int64_t)(k - 1) * s.plane + site] == 0) X = k;
+    labels[site] = X;
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 
@@ -1294,6 +1483,45 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
     L.collect(&st_local);
     if (stats) *stats = st_local;
     return status;
+}
+
+__global__ void k_set_i64(int64_t *p, long long v)
+{
+    if (threadIdx.x == 0) *p = v;
+}
+
+GC_API int approx_level2_cut(gc_graph *skin, const int32_t *cost, int32_t *labels,
+                             int64_t *result, void *stream)
+{
+    int rc = graph_check(skin);
+    if (rc != GC_OK) return rc;
+    if (!cost || !labels || !result) return GC_E_ARG;
+    const int b = skin->window_block;
+    if (b < 1 || b > 4) return GC_E_ARG;
+    Graph s = view(skin);
+    hipStream_t st = (hipStream_t)stream;
+    const gc_problem &p = skin->p;
+    hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(64), 0, st, result, s.hdr);
+    hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 2);
+    if (s.N > 0) {
+        hipLaunchKernelGGL(k_wave, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s);
+        dim3 grid((unsigned)((s.W + b - 1) / b), (unsigned)((s.H + b - 1) / b),
+                  (unsigned)((s.J + b - 1) / b));
+        hipLaunchKernelGGL(k_block_cut, grid, dim3(kBlockLanes), 0, st, s, b, 64 + 8 * b * b * b);
+        hipLaunchKernelGGL(k_labels_closure, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
+    } else if (s.plane > 0) {
+        hipLaunchKernelGGL(k_labels<false>, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
+    }
+    if (s.plane > 0)
+        hipLaunchKernelGGL(k_energy, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, cost, labels,
+                           p.width, p.height, p.labels, p.penalty_h, p.inhibit_h, p.penalty_v,
+                           p.inhibit_v, s.slots);
+    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, s.slots, s.hdr, 2, result);
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, st, result + 1, -1LL);
+    if (!hip_ok(hipGetLastError())) return GC_E_HIP;
+    int32_t perr = 0;
+    if ((rc = read_i32(&s.hdr->prefix_err, &perr, st)) != GC_OK) return rc;
+    return (perr & 2) ? GC_E_NOT_CONVERGED : GC_OK;
 }
 
 GC_API int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *labels,

@@ -57,7 +57,7 @@ class GcSolveStats(ctypes.Structure):
 
 EXPORTS = ("gc_status_str", "gc_last_hip_error", "gc_problem_check", "gc_graph_footprint_bytes",
            "stereo_cost_volume", "graph_build", "maxflow_solve", "extract_labels",
-           "gc_coarse_problem", "coarse_cost_volume", "graph_build_window")
+           "gc_coarse_problem", "coarse_cost_volume", "graph_build_window", "approx_level2_cut")
 
 _lib = None
 
@@ -108,6 +108,8 @@ def load(path: str = LIB_PATH):
     lib.graph_build_window.argtypes = [ctypes.POINTER(GcProblem), P, P, ctypes.c_int32, P,
                                        ctypes.c_size_t, ctypes.POINTER(GcGraph), P]
     lib.graph_build_window.restype = ctypes.c_int
+    lib.approx_level2_cut.argtypes = [ctypes.POINTER(GcGraph), P, P, P, P]
+    lib.approx_level2_cut.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -231,10 +233,19 @@ def graph_build_window(p: GcProblem, cost, coarse_labels, block: int, ws, stream
     return Graph(g, ws)
 
 
+def approx_level2_cut(skin: Graph, cost, labels, result, stream=None):
+    _check(load().approx_level2_cut(ctypes.byref(skin.handle), ctypes.c_void_p(cost.data_ptr()),
+                                    ctypes.c_void_p(labels.data_ptr()),
+                                    ctypes.c_void_p(result.data_ptr()), _stream_ptr(stream)),
+           "approx_level2_cut")
+
+
 def approx_level1(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, stream=None,
-                  ws=None, ws_coarse=None):
-    """Delegate-point cut, then the exact cut inside the thin skin.  Returns
-    (labels, energy, flow, coarse labels, (coarse stats, fine stats))."""
+                  ws=None, ws_coarse=None, level: int = 1):
+    """Delegate-point cut, then the cut inside the thin skin: exact (level 1)
+    or block by block after a wave-front pass (level 2).  Returns (labels,
+    energy, flow, coarse labels, (coarse stats, fine stats)); level 2 has
+    flow -1 and no fine stats."""
     import torch
     dev = cost.device
     c = coarse_problem(p, block)
@@ -252,7 +263,16 @@ def approx_level1(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = Non
     labels = torch.empty((p.height, p.width), dtype=torch.int32, device=dev)
     res = torch.zeros(2, dtype=torch.int64, device=dev)
     gfine = graph_build_window(p, cost, clab, block, ws, stream)
-    st_f = maxflow_solve(gfine, opts, stream)
-    extract_labels(gfine, cost, labels, res, stream)
+    if level == 1:
+        st_f = maxflow_solve(gfine, opts, stream)
+        extract_labels(gfine, cost, labels, res, stream)
+    else:
+        st_f = None
+        approx_level2_cut(gfine, cost, labels, res, stream)
     r = res.cpu()
     return labels, int(r[0]), int(r[1]), clab, (st_c, st_f)
+
+
+def approx_level2(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, stream=None,
+                  ws=None, ws_coarse=None):
+    return approx_level1(p, cost, block, opts, stream, ws, ws_coarse, level=2)

@@ -80,3 +80,33 @@ def test_approximation_never_beats_exact(orc, b):
     # labels stay inside the skin of their delegate point
     lo, hi = orc.skin_windows(cl, spec.w, spec.h, spec.m, b)
     assert (lab >= lo).all() and (lab <= hi).all()
+
+
+@pytest.mark.parametrize("b", [1, 2, 3])
+def test_level2_is_a_labelling_in_the_skin(orc, b):
+    """Level 2 cuts blocks separately, so it is no better than the exact cut;
+    its labels stay inside the thin skin and its energy is recomputed from
+    the definition."""
+    spec = sg.spec_like(sg.MID, 96, 72, 16)
+    p = sg.make_pair(spec, (2, 9))
+    cost = orc.cost_volume(p.left, p.right, spec.m, spec.cap)
+    _, _, opt = orc.solve(cost, 1, 1023)
+    lab, e2, cl = orc.approx_level2(cost, b, 1, 1023)
+    assert e2 >= opt and e2 == orc.energy(cost, lab, 1, 1023)
+    lo, hi = orc.skin_windows(cl, spec.w, spec.h, spec.m, b)
+    assert (lab >= lo).all() and (lab <= hi).all()
+    # the first cut is the same as level 1's
+    _, _, cl1 = orc.approx_level1(cost, b, 1, 1023)
+    assert (cl == cl1).all()
+
+
+def test_level2_single_block_is_exact(orc):
+    """When one block covers the whole skin no arc is left unused, so the
+    block cut is the exact restricted cut: here 3x3 sites, 3 node levels
+    (m = 4) and b = 3 give a single block whose window is every label."""
+    rng = np.random.default_rng(11)
+    for _ in range(5):
+        cost = rng.integers(0, 20, (4, 3, 3)).astype(np.int32)
+        lab, e2, cl = orc.approx_level2(cost, 3, 1, 5)
+        emin, _, lo, _ = orc.brute_force(cost, 1, 5)
+        assert e2 == emin and (lab == lo).all()

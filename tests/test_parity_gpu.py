@@ -206,3 +206,29 @@ def test_approx_level1_mid_full_size(torch_cuda, orc, b):
     assert (labels.cpu().numpy() == ref_lab).all()
     _, _, opt = orc.solve(cost_np, 1, 1023)
     assert energy >= opt
+
+
+@pytest.mark.parametrize("b", [2, 3])
+@pytest.mark.parametrize("spec,seed", [(sg.TINY, (1, 0)), (sg.spec_like(sg.MID, 70, 33, 9), (9, 8)),
+                                       (sg.MID, (2, 0))])
+def test_approx_level2_parity(torch_cuda, orc, b, spec, seed):
+    pr = sg.make_pair(spec, seed)
+    cost_np = orc.cost_volume(pr.left, pr.right, spec.m, spec.cap)
+    p = gc.problem(spec.w, spec.h, spec.m, spec.cap, 1, 1023)
+    cost = torch_cuda.from_numpy(cost_np).cuda()
+    labels, energy, flow, clab, _ = gc.approx_level2(p, cost, b)
+    ref_lab, ref_e, ref_cl = orc.approx_level2(cost_np, b, 1, 1023)
+    assert (clab.cpu().numpy() == ref_cl).all()
+    assert energy == ref_e and flow == -1
+    assert (labels.cpu().numpy() == ref_lab).all()
+
+
+def test_approx_level2_single_block_exact(torch_cuda, orc):
+    rng = np.random.default_rng(11)
+    p = gc.problem(3, 3, 4, 30, 1, 5)
+    for _ in range(5):
+        cost_np = rng.integers(0, 20, (4, 3, 3)).astype(np.int32)
+        cost = torch_cuda.from_numpy(cost_np).cuda()
+        labels, energy, _, _, _ = gc.approx_level2(p, cost, 3)
+        emin, _, lo, _ = orc.brute_force(cost_np, 1, 5)
+        assert energy == emin and (labels.cpu().numpy() == lo).all()
