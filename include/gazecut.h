@@ -224,21 +224,22 @@ int graph_build_window(const gc_problem *p, const int32_t *cost, const int32_t *
                        int32_t block, void *ws, size_t ws_bytes, gc_graph *g_out, void *stream);
 
 /* Level-2 approximation (Sec. 4.5) on a thin-skin graph from
- * graph_build_window (block size b = skin->window_block, 1 <= b <= 4): the
+ * graph_build_window (block size b = skin->window_block, 1 <= b <= 3): the
  * wave-front pass covers the whole skin and the push-relabel loop cuts every
- * b x b x b block separately.  Readings (the paper omits the details): the
- * wave front is one pass down every column of the skin in which each free
- * node hands the chain arc below it as much of its excess as the arc allows;
- * a block is b x b sites by b node levels (node v_k in level group (k-1)/b);
- * each block is cut exactly with the arcs leaving it unused, read off as its
- * minimal source side; a site's label is the deepest source-side node of its
- * column.  Used instead of maxflow_solve + extract_labels on the skin.
+ * block separately.  Readings (the paper omits the details): the wave front
+ * is one pass down every column of the skin in which each free node hands
+ * the chain arc below it as much of its excess as the arc allows; a block is
+ * the b x b sites of one delegate point over the full depth of their skin,
+ * so only the arcs between delegate points go unused; each block is cut
+ * exactly, read off as its minimal source side; a site's label is the
+ * deepest source-side node of its column.  Used instead of maxflow_solve +
+ * extract_labels on the skin.
  * cost:   DEVICE int32 [labels][height][width], the full data term.
  * labels: DEVICE int32 [height][width], written.
  * result: DEVICE int64[2], written: result[0] = E(labels) from its
  *         definition, result[1] = -1 (no global cut value exists).
  * The skin's state is consumed.  Errors: GC_E_ARG (not a thin-skin graph or
- * b > 4), GC_E_NOT_CONVERGED, GC_E_HIP. */
+ * b > 3), GC_E_NOT_CONVERGED, GC_E_HIP. */
 int approx_level2_cut(gc_graph *skin, const int32_t *cost, int32_t *labels, int64_t *result,
                       void *stream);
 

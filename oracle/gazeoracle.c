@@ -721,15 +721,16 @@ int orc_approx_level1(const int32_t *cost, int w, int h, int m, int pen_h, int i
 /* Hierarchical approximation, level 2 (Sec. 4.5).                           */
 /*                                                                          */
 /* The wave-front pass runs over the whole thin skin and the push-relabel   */
-/* loop cuts every b x b x b block separately.  Readings (the paper omits    */
-/* the details): the wave front is one pass down every column of the skin,  */
-/* from its top to its bottom, in which each free node hands the chain arc  */
-/* below it as much of its excess as the arc's residual allows; a block is   */
-/* b x b sites by b node levels (node v_k in level group (k-1)/b); each      */
-/* block's cut is its exact minimum cut with the arcs leaving the block      */
-/* unused, read off as the minimal source side; a site's label is the        */
-/* deepest source-side node of its column (the unbounded upward chain arcs   */
-/* put everything above it on the source side too).                         */
+/* loop cuts every block separately.  Readings (the paper omits the         */
+/* details): the wave front is one pass down every column of the skin, from */
+/* its top to its bottom, in which each free node hands the chain arc below  */
+/* it as much of its excess as the arc's residual allows; a block is the     */
+/* b x b sites of one delegate point over the full depth of their skin (all */
+/* of them share one window), so only the arcs between delegate points go   */
+/* unused; each block's cut is its exact minimum cut read off as the         */
+/* minimal source side; a site's label is the deepest source-side node of   */
+/* its column.  Splitting the skin's depth into b-level blocks as well would */
+/* leave blocks in the middle of the skin without any sink.                  */
 /*                                                                          */
 /* State here is the skin with its terminals folded into node balances:     */
 /* bal[v] = capacity of arcs into v from forced-source nodes (and s) minus   */
@@ -859,47 +860,45 @@ int orc_approx_level2(const int32_t *cost, int w, int h, int m, int pen_h, int i
                 res[v * 14 + 0] -= d;
                 /* the reverse (upward) arc is unbounded either way */
             }
-    /* every b x b x b block on its own */
+    /* every block on its own */
     {
-        int nbk = (m - 1 + b - 1) / b;
-        int cap_nodes = b * b * b + 2;
+        int cap_nodes = b * b * (m - 1) + 2;
         int64_t *C = (int64_t *)malloc(sizeof(int64_t) * cap_nodes * cap_nodes);
         uint8_t *side = (uint8_t *)malloc(cap_nodes);
         size_t *ids = (size_t *)malloc(sizeof(size_t) * cap_nodes);
         int *kx = (int *)malloc(sizeof(int) * cap_nodes * 3);
         if (!C || !side || !ids || !kx) { free(C); free(side); free(ids); free(kx); rc = ORC_E_NOMEM; goto done; }
-        for (int K = 0; K < nbk; K++)
-            for (int Y = 0; Y < hc; Y++)
-                for (int X = 0; X < wc; X++) {
-                    int n = 0;
-                    for (int k = K * b + 1; k <= K * b + b && k <= m - 1; k++)
-                        for (int y = Y * b; y < Y * b + b && y < h; y++)
-                            for (int x = X * b; x < X * b + b && x < w; x++)
-                                if (FREE(x, y, k)) {
-                                    ids[n] = NODE(x, y, k);
-                                    kx[3 * n] = k; kx[3 * n + 1] = y; kx[3 * n + 2] = x;
-                                    n++;
-                                }
-                    if (n == 0) continue;
-                    int N2 = n + 2, S = n, T = n + 1;
-                    memset(C, 0, sizeof(int64_t) * N2 * N2);
-                    for (int i = 0; i < n; i++) {
-                        size_t v = ids[i];
-                        if (bal[v] > 0) C[(int64_t)S * N2 + i] = bal[v];
-                        if (bal[v] < 0) C[(int64_t)i * N2 + T] = -bal[v];
-                        for (int d = 0; d < 14; d++) {
-                            int k2 = kx[3 * i] + NB[d][0], y2 = kx[3 * i + 1] + NB[d][1],
-                                x2 = kx[3 * i + 2] + NB[d][2];
-                            for (int j2 = 0; j2 < n; j2++)
-                                if (kx[3 * j2] == k2 && kx[3 * j2 + 1] == y2 && kx[3 * j2 + 2] == x2) {
-                                    int64_t r = d == 1 ? ORC_INF : res[v * 14 + d];
-                                    C[(int64_t)i * N2 + j2] += r;
-                                }
-                        }
+        for (int Y = 0; Y < hc; Y++)
+            for (int X = 0; X < wc; X++) {
+                int n = 0;
+                for (int k = 1; k <= m - 1; k++)
+                    for (int y = Y * b; y < Y * b + b && y < h; y++)
+                        for (int x = X * b; x < X * b + b && x < w; x++)
+                            if (FREE(x, y, k)) {
+                                ids[n] = NODE(x, y, k);
+                                kx[3 * n] = k; kx[3 * n + 1] = y; kx[3 * n + 2] = x;
+                                n++;
+                            }
+                if (n == 0) continue;
+                int N2 = n + 2, S = n, T = n + 1;
+                memset(C, 0, sizeof(int64_t) * N2 * N2);
+                for (int i = 0; i < n; i++) {
+                    size_t v = ids[i];
+                    if (bal[v] > 0) C[(int64_t)S * N2 + i] = bal[v];
+                    if (bal[v] < 0) C[(int64_t)i * N2 + T] = -bal[v];
+                    for (int d = 0; d < 14; d++) {
+                        int k2 = kx[3 * i] + NB[d][0], y2 = kx[3 * i + 1] + NB[d][1],
+                            x2 = kx[3 * i + 2] + NB[d][2];
+                        for (int j2 = 0; j2 < n; j2++)
+                            if (kx[3 * j2] == k2 && kx[3 * j2 + 1] == y2 && kx[3 * j2 + 2] == x2) {
+                                int64_t r = d == 1 ? ORC_INF : res[v * 14 + d];
+                                C[(int64_t)i * N2 + j2] += r;
+                            }
                     }
-                    ek_maxflow(N2, C, S, T, side);
-                    for (int i = 0; i < n; i++) in_s[ids[i]] = side[i];
                 }
+                ek_maxflow(N2, C, S, T, side);
+                for (int i = 0; i < n; i++) in_s[ids[i]] = side[i];
+            }
         free(C); free(side); free(ids); free(kx);
     }
     /* deepest source-side node of every column */

@@ -940,7 +940,7 @@ k_fold_slots(const Slot *slots, DevHeader *hdr, int what, int64_t *result)
 
 // ---------------------------------------------------------------------------
 // Level-2 approximation (Sec. 4.5): wave-front pass over the skin, then every
-// b x b x b block cut on its own.
+// block (one delegate point's sites over the skin depth) cut on its own.
 // ---------------------------------------------------------------------------
 
 // Wave front: one pass down every column of the skin; each free node hands
@@ -963,10 +963,11 @@ k_wave(Graph s)
 }
 
 constexpr int32_t kUpRes = 1 << 29;     // residual of an unbounded arc inside a block
-constexpr int kBlockLanes = 64;
+constexpr int kBlockLanes = 128;        // b x b sites x up to 3b-1 skin levels, b <= 3
 
-// Exact cut of one b x b x b block (b <= 4) with the arcs that leave the
-// block unused: one 64-lane workgroup, one lane per node, state in LDS.
+// Exact cut of one block: the b x b sites of one delegate point over the
+// full depth of their skin (they share one window), with the arcs that leave
+// the block unused.  One 128-lane workgroup, one lane per node, state in LDS.
 // Synchronous push-relabel with exact in-block BFS heights until no node
 // with excess reaches a deficit, then the block's minimal source side
 // (reachability from the remaining excess) goes to aux (0 = source side).
@@ -978,20 +979,21 @@ k_block_cut(Graph s, int b, int max_outer)
     __shared__ int s_part[kBlockLanes];
     __shared__ int s_flag;
     const int l = threadIdx.x;
-    const int nb = b * b * b;
+    const int64_t site0 = (int64_t)(blockIdx.y * b) * s.W + blockIdx.x * b;
+    const int lo = s.wlo[site0], depth = s.whi[site0] - lo;     // free levels lo+1 .. hi
+    const int nb = b * b * depth;
     const int lx = l % b, ly = (l / b) % b, lk = l / (b * b);
-    const int x = blockIdx.x * b + lx, y = blockIdx.y * b + ly, j = blockIdx.z * b + lk;
+    const int x = blockIdx.x * b + lx, y = blockIdx.y * b + ly, j = lo + lk;   // node v_{lo+1+lk}
     bool part = false;
     int64_t n = 0;
-    if (l < nb && x < s.W && y < s.H && j < s.J) {
-        const int64_t site = (int64_t)y * s.W + x;
-        part = node_class(j + 1, s.wlo[site], s.whi[site]) == FREE;
-        n = (int64_t)j * s.plane + site;
+    if (l < nb && x < s.W && y < s.H) {
+        part = true;
+        n = (int64_t)j * s.plane + (int64_t)y * s.W + x;
     }
     // local index of the neighbour in direction d, or -1 outside the block
     auto lnb = [&](int d) -> int {
         const int nx = lx + dir_dx(d), ny = ly + dir_dy(d), nk = lk + dir_dj(d);
-        if (nx < 0 || nx >= b || ny < 0 || ny >= b || nk < 0 || nk >= b) return -1;
+        if (nx < 0 || nx >= b || ny < 0 || ny >= b || nk < 0 || nk >= depth) return -1;
         return (nk * b + ny) * b + nx;
     };
     e[l] = 0; ein[l] = 0; hgt[l] = kInf;
@@ -1497,7 +1499,7 @@ GC_API int approx_level2_cut(gc_graph *skin, const int32_t *cost, int32_t *label
     if (rc != GC_OK) return rc;
     if (!cost || !labels || !result) return GC_E_ARG;
     const int b = skin->window_block;
-    if (b < 1 || b > 4) return GC_E_ARG;
+    if (b < 1 || b > 3) return GC_E_ARG;
     Graph s = view(skin);
     hipStream_t st = (hipStream_t)stream;
     const gc_problem &p = skin->p;
@@ -1505,9 +1507,8 @@ GC_API int approx_level2_cut(gc_graph *skin, const int32_t *cost, int32_t *label
     hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 2);
     if (s.N > 0) {
         hipLaunchKernelGGL(k_wave, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s);
-        dim3 grid((unsigned)((s.W + b - 1) / b), (unsigned)((s.H + b - 1) / b),
-                  (unsigned)((s.J + b - 1) / b));
-        hipLaunchKernelGGL(k_block_cut, grid, dim3(kBlockLanes), 0, st, s, b, 64 + 8 * b * b * b);
+        dim3 grid((unsigned)((s.W + b - 1) / b), (unsigned)((s.H + b - 1) / b), 1);
+        hipLaunchKernelGGL(k_block_cut, grid, dim3(kBlockLanes), 0, st, s, b, 64 + 24 * b * b * b);
         hipLaunchKernelGGL(k_labels_closure, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
     } else if (s.plane > 0) {
         hipLaunchKernelGGL(k_labels<false>, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
