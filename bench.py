@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=3, help="pairs the oracle solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
+    ap.add_argument("--no-approx", action="store_true", help="skip the approximate variants")
     return ap.parse_args()
 
 
@@ -150,6 +151,42 @@ def main():
                 "bytes_per_launch": int(bytes_launch),
                 "device_ms_per_step": {k: round(v / args.steps, 3) for k, v in tot.items()}}
 
+    # the paper's approximate cuts (Sec. 4.5) on the same pairs, timed the same way
+    approx = {}
+    if not args.no_approx:
+        best_e = {}
+        for variant, level, b in (("level1_b2", 1, 2), ("level1_b3", 1, 3), ("level2_b3", 2, 3)):
+            c = gc.coarse_problem(p, b)
+            ws_c = gc.alloc_workspace(c, dev)
+            lat_a, gaps, errs, pcts = [], [], [], []
+            n_a = max(4, args.steps // 4)
+            for i in range(n_a + 2):
+                k = i % len(pairs)
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                gc.stereo_cost_volume(lefts[k], rights[k], p, cost, stream)
+                lab_a, e_a, _, _, _ = gc.approx_level1(p, cost, b, None, stream, ws=ws, ws_coarse=ws_c,
+                                                       level=level)
+                torch.cuda.synchronize()
+                if i >= 2:
+                    lat_a.append(time.perf_counter() - a)
+                    if k not in best_e:
+                        gc.stereo_cost_volume(lefts[k], rights[k], p, cost, stream)
+                        g = gc.graph_build(p, cost, ws, stream)
+                        gc.maxflow_solve(g, None, stream)
+                        gc.extract_labels(g, cost, labels, result, stream)
+                        best_e[k] = int(result.cpu()[0])
+                    gaps.append(e_a - best_e[k])
+                    er, pc = sg.eq2_error(pairs[k].gt, lab_a.cpu().numpy())
+                    errs.append(er)
+                    pcts.append(pc)
+            approx[variant] = {"ms_per_pair": round(1e3 * float(np.median(lat_a)), 3),
+                               "energy_gap_mean": round(float(np.mean(gaps)), 1),
+                               "energy_gap_rel": round(float(np.mean(gaps)) / float(np.mean(
+                                   [best_e[k] for k in best_e])), 6),
+                               "eq2_error_mean": round(float(np.mean(errs)), 1),
+                               "pct_exact_mean": round(float(np.mean(pcts)), 1)}
+
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
@@ -203,6 +240,7 @@ def main():
         "bfs_passes_per_pair": round(sum(s["bfs_passes"] for s in stats) / args.steps, 2),
         "energy_last": int(r[0]), "flow_last": int(r[1]),
         "eq2_error_last": err, "pct_exact_last": pct,
+        "approx": approx or None,
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
