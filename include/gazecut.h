@@ -100,6 +100,10 @@ typedef struct {
  * class in gc_solve_stats (adds a few microseconds per launch). */
 #define GC_OPT_TIME_KERNELS 1
 
+/* gc_solve_opts.flags, batched solves: replay the push-relabel sweeps of a
+ * round from a captured hipGraph (needs a non-null stream). */
+#define GC_OPT_BATCH_GRAPH 2
+
 /* Kernel classes of gc_solve_stats.kernel_ms / kernel_launches. */
 #define GC_K_PUSH 0           /* push sweep                                   */
 #define GC_K_RELABEL 1        /* relabel sweep (also merges inflow)           */
@@ -117,6 +121,9 @@ typedef struct {
     int32_t kernel_launches[GC_K_CLASSES];  /* with GC_OPT_TIME_KERNELS only */
     double kernel_ms[GC_K_CLASSES];         /* summed event time per class   */
 } gc_solve_stats;
+
+/* Largest number of graphs one batch holds at a time. */
+#define GC_BATCH_MAX_GRAPHS 256
 
 /* Human-readable name of a status code (static string). */
 const char *gc_status_str(int status);
@@ -242,6 +249,55 @@ int graph_build_window(const gc_problem *p, const int32_t *cost, const int32_t *
  * b > 3), GC_E_NOT_CONVERGED, GC_E_HIP. */
 int approx_level2_cut(gc_graph *skin, const int32_t *cost, int32_t *labels, int64_t *result,
                       void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched solve.  Many graphs of any sizes (full or thin-skin) are solved
+ * together: every kernel launch of a phase covers all member graphs, its
+ * blocks finding their graph in a device table.  A round runs, for every
+ * member, exactly the single-graph sequence: exact global relabel, then the
+ * termination test (finished members leave the batch), then
+ * `relabel_period` push-relabel sweeps.  Results are identical to
+ * maxflow_solve on each graph (the cut is canonical).  Graphs may join
+ * between rounds, which is how a serving loop admits new work while others
+ * are on the GPU.
+ * ---------------------------------------------------------------------- */
+
+/* Opaque host object of a batch (allocated by gc_batch_create). */
+typedef struct gc_batch gc_batch;
+
+/* Bytes of DEVICE memory a batch needs for its graph table (256-B aligned). */
+size_t gc_batch_footprint_bytes(void);
+
+/* Creates a batch over the caller's DEVICE table buffer; `o` fixes the
+ * relabel period, relaxation tile and GC_OPT_BATCH_GRAPH for all members.
+ * Errors: GC_E_ARG, GC_E_WORKSPACE. */
+int gc_batch_create(void *dev_table, size_t dev_bytes, const gc_solve_opts *o, gc_batch **out);
+
+/* Frees the host object (not the caller's memory). */
+int gc_batch_destroy(gc_batch *b);
+
+/* Number of graphs currently in the batch. */
+int gc_batch_members(const gc_batch *b);
+
+/* Adds a built graph (graph_build or graph_build_window), identified by
+ * `tag`.  Its workspace must stay untouched until it leaves the batch.
+ * Errors: GC_E_ARG (batch full), errors of an invalid graph. */
+int gc_batch_add(gc_batch *b, const gc_graph *g, int64_t tag);
+
+/* One round for every member on `stream`.  Members that finished leave the
+ * batch; their tags (and stats, if done_stats is not NULL) are written to
+ * done_tags[0 .. *n_done-1] (at most max_done of them; others stay for the
+ * next round).  A member leaves unfinished after max_sweeps sweeps, with
+ * stats.active_last > 0.  Blocks the host for the relabel read-backs; the
+ * sweeps are left running on the stream.  Errors: GC_E_ARG, GC_E_HIP. */
+int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solve_stats *done_stats,
+                   int32_t max_done, int32_t *n_done);
+
+/* Solves n graphs in one batch, refilling it as members finish.  stats
+ * (optional) receives n entries in input order.  Returns GC_E_NOT_CONVERGED
+ * if any graph hit max_sweeps.  extract_labels then reads each graph. */
+int maxflow_solve_batch(gc_graph *const *gs, int32_t n, void *dev_table, size_t dev_bytes,
+                        const gc_solve_opts *o, gc_solve_stats *stats, void *stream);
 
 #ifdef __cplusplus
 }

@@ -35,8 +35,10 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "gazecut.h"
@@ -105,6 +107,7 @@ struct Graph {
     int32_t W, H, J;
     int64_t plane, N;
     int32_t te, ts, ie, is;   // pair totals: 2*pen_h, 2*pen_v, inh_h, inh_v
+    int32_t win;              // thin-skin graph (levels outside per-site windows are inert)
 };
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -151,6 +154,7 @@ Graph view(const gc_graph *g)
     s.stamps = (int32_t *)b;
     s.te = 2 * p.penalty_h; s.ts = 2 * p.penalty_v;
     s.ie = p.inhibit_h; s.is = p.inhibit_v;
+    s.win = g->window_block > 0 ? 1 : 0;
     return s;
 }
 
@@ -189,7 +193,51 @@ __device__ inline T block_sum(T v)
     return t;
 }
 
-__device__ inline Slot &my_slot(Slot *slots) { return slots[blockIdx.x & (kSlots - 1)]; }
+__device__ inline Slot &my_slot(Slot *slots, int64_t lb) { return slots[lb & (kSlots - 1)]; }
+
+// Kernel sources.  A solver kernel runs either on one graph (passed by value,
+// one block per 256 nodes or per tile) or on a batch: a device table of
+// graphs with prefix offsets of their blocks, where a block finds its graph
+// by binary search.  Blocks past the batch total exit at once, so a launch
+// may use an upper-bound grid.
+constexpr int kMaxBatch = GC_BATCH_MAX_GRAPHS;
+struct BatchDev {
+    int32_t ng;
+    int32_t pad[63];
+    int32_t node_off[kMaxBatch + 1];    // node blocks (256 nodes each)
+    int32_t tile_off[kMaxBatch + 1];    // relaxation tiles
+    int32_t pad2[2];
+    Graph graphs[kMaxBatch];
+    int32_t gathered[kMaxBatch][16];    // per-graph flags / counters read back by the host
+};
+struct Batch {
+    const BatchDev *T;
+};
+
+__device__ inline bool locate(const Graph &in, int, Graph &s, int64_t &lb)
+{
+    s = in;
+    lb = blockIdx.x;
+    return true;
+}
+
+__device__ inline bool locate(const Batch &b, int which, Graph &s, int64_t &lb)
+{
+    const BatchDev *T = b.T;
+    const int32_t *off = which ? T->tile_off : T->node_off;
+    const int ng = T->ng;
+    const int bid = blockIdx.x;
+    if (ng <= 0 || bid >= off[ng]) return false;
+    int lo = 0, hi = ng - 1;                 // largest g with off[g] <= bid
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    s = T->graphs[lo];
+    lb = bid - off[lo];
+    return true;
+}
 
 // Node counts stay below 2^29 (checked on the host), so 32-bit division is exact.
 __device__ inline void decode(const Graph &s, int64_t n, int &j, int &y, int &x)
@@ -463,8 +511,8 @@ k_build(Graph s, const int32_t *__restrict__ cost, int m)
     __syncthreads();
     c0 = block_sum(c0);
     if (threadIdx.x == 0) {
-        if (tsum) atomicAdd((unsigned long long *)&my_slot(s.slots).tcap, (unsigned long long)tsum);
-        if (c0) atomicAdd((unsigned long long *)&my_slot(s.slots).c0, (unsigned long long)c0);
+        if (tsum) atomicAdd((unsigned long long *)&my_slot(s.slots, blockIdx.x).tcap, (unsigned long long)tsum);
+        if (c0) atomicAdd((unsigned long long *)&my_slot(s.slots, blockIdx.x).c0, (unsigned long long)c0);
     }
 }
 
@@ -510,10 +558,14 @@ k_coarse_cost(const int32_t *__restrict__ cost, int W, int H, int m, int b,
 // Push sweep.  All 14 stored words and neighbour heights of an active node
 // are loaded up front (one round of memory latency); pushes then run in
 // registers and write the new words directly.
+template <class Src>
 __global__ void __launch_bounds__(kBlock)
-k_push(Graph s)
+k_push(Src src)
 {
-    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    Graph s;
+    int64_t lb;
+    if (!locate(src, 0, s, lb)) return;
+    int64_t n = lb * kBlock + threadIdx.x;
     int cnt = 0;
     if (n < s.N) {
         int32_t e = s.ex[n];
@@ -545,15 +597,19 @@ k_push(Graph s)
         }
     }
     cnt = block_sum(cnt);
-    if (threadIdx.x == 0 && cnt) atomicAdd(&my_slot(s.slots).pushes, (unsigned long long)cnt);
+    if (threadIdx.x == 0 && cnt) atomicAdd(&my_slot(s.slots, lb).pushes, (unsigned long long)cnt);
 }
 
 // Relabel sweep: merges the inflow of the push sweep, then lifts every
 // active node to one above its lowest residual neighbour.
+template <class Src>
 __global__ void __launch_bounds__(kBlock)
-k_relabel(Graph s)
+k_relabel(Src src)
 {
-    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    Graph s;
+    int64_t lb;
+    if (!locate(src, 0, s, lb)) return;
+    int64_t n = lb * kBlock + threadIdx.x;
     if (n >= s.N) return;
     int32_t in = s.ein[n];
     int32_t e = s.ex[n];
@@ -592,15 +648,18 @@ __device__ inline bool is_frozen(const Graph &s, int j, int y, int x)
 // mode 0: out-arc mask (distance to deficits); mode 1: in-arc mask
 // (reachability from excess).  Forced nodes of a thin-skin graph get no
 // arcs, so relaxation never gives them a finite value.
-template <bool kWindow>
+template <class Src>
 __global__ void __launch_bounds__(kBlock)
-k_mask(Graph s, int mode)
+k_mask(Src src, int mode)
 {
-    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    Graph s;
+    int64_t lb;
+    if (!locate(src, 0, s, lb)) return;
+    int64_t n = lb * kBlock + threadIdx.x;
     if (n >= s.N) return;
     int j, y, x;
     decode(s, n, j, y, x);
-    if (kWindow && is_frozen(s, j, y, x)) { s.mask[n] = 0; return; }
+    if (s.win && is_frozen(s, j, y, x)) { s.mask[n] = 0; return; }
     unsigned mk = 0;
 #pragma unroll
     for (int d = 0; d < 14; ++d) {
@@ -612,14 +671,17 @@ k_mask(Graph s, int mode)
 
 // Seeds: mode 0 -> ht = 1 at deficit nodes, INF elsewhere;
 //        mode 1 -> aux = 0 at excess nodes, INF elsewhere.
-template <bool kWindow>
+template <class Src>
 __global__ void __launch_bounds__(kBlock)
-k_seed(Graph s, int mode)
+k_seed(Src src, int mode)
 {
-    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    Graph s;
+    int64_t lb;
+    if (!locate(src, 0, s, lb)) return;
+    int64_t n = lb * kBlock + threadIdx.x;
     if (n >= s.N) return;
     int32_t e = s.ex[n];
-    if (kWindow) {
+    if (s.win) {
         int j, y, x;
         decode(s, n, j, y, x);
         if (is_frozen(s, j, y, x)) e = 0;          // inert: never a seed
@@ -642,11 +704,19 @@ k_seed(Graph s, int mode)
 // the next round (neighbours of a changed node whose mask points back at
 // it); rounds stop when it is empty.  flags[p % kMaxFlags] <- 1 if any
 // value changed; pass p returns at once when pass p-1 changed nothing.
-template <int TW, int TH, int TJ>
+template <int TW, int TH, int TJ, class Src>
 __global__ void __launch_bounds__(kBlock)
-k_relax(Graph s, int32_t *__restrict__ val, int step, int max_rounds, int32_t *flags, int pass,
-        int32_t *__restrict__ stamps, int ntx, int nty, int ntz)
+k_relax(Src src, int mode, int max_rounds, int pass)
 {
+    Graph s;
+    int64_t lb;
+    if (!locate(src, 1, s, lb)) return;
+    // mode 0: BFS distance to the deficits in ht; mode 1: reachability in aux
+    int32_t *__restrict__ val = mode == 0 ? s.ht : s.aux;
+    const int step = mode == 0 ? 1 : 0;
+    int32_t *flags = s.hdr->flags;
+    int32_t *__restrict__ stamps = s.stamps;
+    const int ntx = (s.W + TW - 1) / TW, nty = (s.H + TH - 1) / TH, ntz = (s.J + TJ - 1) / TJ;
     constexpr int HW = TW + 2, HH = TH + 2, HJ = TJ + 2;
     constexpr int NH = HW * HH * HJ, NI = TW * TH * TJ;
     static_assert(NI % kBlock == 0 && NI / kBlock <= 32, "tile must hold 1..32 nodes per thread");
@@ -657,8 +727,8 @@ k_relax(Graph s, int32_t *__restrict__ val, int step, int max_rounds, int32_t *f
     __shared__ int s_flag;
     const int tid = threadIdx.x;
     if (pass > 1 && flags[(pass - 1) % kMaxFlags] == 0) return;     // converged already
-    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
-    const int tile = (bz * nty + by) * ntx + bx;
+    const int tile = (int)lb;
+    const int bx = tile % ntx, by = (tile / ntx) % nty, bz = tile / (ntx * nty);
     // Neighbouring tiles may rewrite their stamps during this pass, so one
     // thread decides for the whole block.
     __shared__ int s_run, s_full;
@@ -802,14 +872,18 @@ k_relax(Graph s, int32_t *__restrict__ val, int step, int max_rounds, int32_t *f
     }
 }
 
+template <class Src>
 __global__ void __launch_bounds__(kBlock)
-k_count_active(Graph s)
+k_count_active(Src src)
 {
-    int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    Graph s;
+    int64_t lb;
+    if (!locate(src, 0, s, lb)) return;
+    int64_t n = lb * kBlock + threadIdx.x;
     int a = 0;
     if (n < s.N) a = (s.ex[n] > 0 && s.ht[n] < kInf) ? 1 : 0;
     a = block_sum(a);
-    if (threadIdx.x == 0 && a) atomicAdd(&my_slot(s.slots).active, a);
+    if (threadIdx.x == 0 && a) atomicAdd(&my_slot(s.slots, lb).active, a);
 }
 
 __global__ void k_zero_header(DevHeader *h, int what)
@@ -840,13 +914,12 @@ __global__ void k_zero_result(int64_t *r, DevHeader *h)
 // Labels from the reachability values: X = source-side nodes in the column,
 // which must form the prefix v_1..v_X.  In a thin-skin graph the levels at
 // or above the window's top are source side by construction.
-template <bool kWindow>
 __global__ void __launch_bounds__(kBlock)
 k_labels(Graph s, int32_t *__restrict__ labels)
 {
     int64_t site = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (site >= s.plane) return;
-    const int lo = kWindow ? s.wlo[site] : 0, hi = kWindow ? s.whi[site] : s.J;
+    const int lo = s.win ? s.wlo[site] : 0, hi = s.win ? s.whi[site] : s.J;
     int X = lo;
     bool gap = false, bad = false;
     for (int j = lo; j < hi; ++j) {
@@ -884,8 +957,8 @@ k_energy(const int32_t *__restrict__ cost, const int32_t *__restrict__ labels, i
     __syncthreads();
     tcap = block_sum(tcap);
     if (threadIdx.x == 0) {
-        atomicAdd((unsigned long long *)&my_slot(slots).e0, (unsigned long long)e);
-        atomicAdd((unsigned long long *)&my_slot(slots).e1, (unsigned long long)tcap);
+        atomicAdd((unsigned long long *)&my_slot(slots, blockIdx.x).e0, (unsigned long long)e);
+        atomicAdd((unsigned long long *)&my_slot(slots, blockIdx.x).e1, (unsigned long long)tcap);
     }
 }
 
@@ -898,7 +971,7 @@ k_deficit(Graph s)
     if (n < s.N) { int32_t e = s.ex[n]; d = e < 0 ? -(long long)e : 0; }
     d = block_sum(d);
     if (threadIdx.x == 0 && d)
-        atomicAdd((unsigned long long *)&my_slot(s.slots).e1, (unsigned long long)(-d));
+        atomicAdd((unsigned long long *)&my_slot(s.slots, blockIdx.x).e1, (unsigned long long)(-d));
 }
 
 // Clears slot fields: what 0 = everything, 1 = active, 2 = energy/flow.
@@ -935,6 +1008,44 @@ k_fold_slots(const Slot *slots, DevHeader *hdr, int what, int64_t *result)
         __syncthreads();
         long long c = block_sum(sl.c0);
         if (threadIdx.x == 0) { hdr->tcap = t; hdr->c0 = c; }
+    }
+}
+
+// Per-graph bookkeeping of a batch, one block per member graph.
+// what 0: clear change flags of passes first .. first+count-1;
+// what 1: clear the active counters.
+__global__ void __launch_bounds__(kSlots)
+k_batch_zero(const BatchDev *T, int what, int first, int count)
+{
+    const Graph &s = T->graphs[blockIdx.x];
+    const int t = threadIdx.x;
+    if (what == 0) {
+        if (t < count) s.hdr->flags[(first + t) % kMaxFlags] = 0;
+    } else {
+        s.slots[t].active = 0;
+    }
+}
+
+// what 0: copy the change flags; what 1: fold active nodes and pushes.
+__global__ void __launch_bounds__(kSlots)
+k_batch_gather(BatchDev *T, int what)
+{
+    const int g = blockIdx.x;
+    const Graph &s = T->graphs[g];
+    const int t = threadIdx.x;
+    if (what == 0) {
+        if (t < kMaxFlags) T->gathered[g][t] = s.hdr->flags[t];
+        return;
+    }
+    const int a = block_sum(s.slots[t].active);
+    __syncthreads();
+    const unsigned long long pu = block_sum(s.slots[t].pushes);
+    if (t == 0) {
+        s.hdr->active = a;
+        s.hdr->pushes = pu;
+        T->gathered[g][0] = a;
+        T->gathered[g][1] = (int32_t)(pu & 0x7fffffffULL);
+        T->gathered[g][2] = (int32_t)(pu >> 31);
     }
 }
 
@@ -1152,7 +1263,8 @@ Opts resolve(const gc_solve_opts *o)
     return r;
 }
 
-typedef void (*RelaxFn)(Graph, int32_t *, int, int, int32_t *, int, int32_t *, int, int, int);
+template <class Src>
+using RelaxFn = void (*)(Src, int, int, int);
 
 // Tile shapes compiled for the relaxation pass (x, y, depth layers).
 #define GC_RELAX_SHAPES(X)                                                        \
@@ -1160,19 +1272,25 @@ typedef void (*RelaxFn)(Graph, int32_t *, int, int, int32_t *, int, int32_t *, i
     X(16, 16, 8) X(32, 8, 8) X(32, 16, 8) X(64, 8, 8) X(16, 16, 4) X(32, 16, 4)   \
     X(32, 32, 4) X(64, 16, 4) X(8, 8, 32) X(16, 8, 32) X(16, 16, 32)
 
-RelaxFn relax_kernel(int tw, int th, int tj)
+template <class Src>
+RelaxFn<Src> relax_kernel(int tw, int th, int tj)
 {
     if (tw < kMinTileW || th < kMinTileH || tj < kMinTileJ) return nullptr;
 #define GC_RELAX_CASE(a, b, c) \
-    if (tw == a && th == b && tj == c) return k_relax<a, b, c>;
+    if (tw == a && th == b && tj == c) return k_relax<a, b, c, Src>;
     GC_RELAX_SHAPES(GC_RELAX_CASE)
 #undef GC_RELAX_CASE
     return nullptr;
 }
 
+int64_t relax_tiles(const Graph &s, const Opts &o)
+{
+    return (int64_t)((s.W + o.tw - 1) / o.tw) * ((s.H + o.th - 1) / o.th) * ((s.J + o.tj - 1) / o.tj);
+}
+
 int check_opts(const Opts &o)
 {
-    if (!relax_kernel(o.tw, o.th, o.tj)) return GC_E_ARG;
+    if (!relax_kernel<Graph>(o.tw, o.th, o.tj)) return GC_E_ARG;
     return GC_OK;
 }
 
@@ -1224,22 +1342,20 @@ struct Launcher {
 // Runs relaxation passes until a pass changes nothing.  Passes are issued in
 // growing batches with one flag read-back per batch; a pass that follows a
 // pass without change returns at once, so over-issuing is cheap.
-int relax_to_fixpoint(const Graph &s, int32_t *val, int step, const Opts &o,
-                      Launcher &L, int *passes_out)
+int relax_to_fixpoint(const Graph &s, int mode, const Opts &o, Launcher &L, int *passes_out)
 {
-    const int ntx = (s.W + o.tw - 1) / o.tw, nty = (s.H + o.th - 1) / o.th,
-              ntz = (s.J + o.tj - 1) / o.tj;
-    dim3 grid((unsigned)ntx, (unsigned)nty, (unsigned)ntz);
-    RelaxFn fn = relax_kernel(o.tw, o.th, o.tj);
+    const int64_t tiles = relax_tiles(s, o);
+    RelaxFn<Graph> fn = relax_kernel<Graph>(o.tw, o.th, o.tj);
     if (!fn) return GC_E_ARG;
+    if (tiles <= 0) return GC_OK;
     const int max_passes = 1 << 22;
     int passes = 0, batch = 2;
     for (;;) {
         hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, L.st, s.hdr, passes + 1, batch);
         for (int b = 1; b <= batch; ++b)
             L.run(GC_K_RELAX, [&] {
-                hipLaunchKernelGGL(fn, grid, dim3(kBlock), 0, L.st, s, val, step, o.local_iters,
-                                   s.hdr->flags, passes + b, s.stamps, ntx, nty, ntz);
+                hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(kBlock), 0, L.st, s, mode,
+                                   o.local_iters, passes + b);
             });
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
         int32_t flags[kMaxFlags];
@@ -1446,23 +1562,16 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
     }
     Launcher L{st, (opt.flags & GC_OPT_TIME_KERNELS) != 0, {}};
     const unsigned grid = grid_for(s.N);
-    const bool win = g->window_block > 0;
     int status = GC_OK;
     for (;;) {
         // exact global relabelling: BFS distance to the deficit nodes
-        L.run(GC_K_OTHER, [&] {
-            if (win) hipLaunchKernelGGL(k_mask<true>, dim3(grid), dim3(kBlock), 0, st, s, 0);
-            else hipLaunchKernelGGL(k_mask<false>, dim3(grid), dim3(kBlock), 0, st, s, 0);
-        });
-        L.run(GC_K_OTHER, [&] {
-            if (win) hipLaunchKernelGGL(k_seed<true>, dim3(grid), dim3(kBlock), 0, st, s, 0);
-            else hipLaunchKernelGGL(k_seed<false>, dim3(grid), dim3(kBlock), 0, st, s, 0);
-        });
+        L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_mask<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 0); });
+        L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_seed<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 0); });
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
-        if ((rc = relax_to_fixpoint(s, s.ht, 1, opt, L, &st_local.bfs_passes)) != GC_OK) return rc;
+        if ((rc = relax_to_fixpoint(s, 0, opt, L, &st_local.bfs_passes)) != GC_OK) return rc;
         st_local.global_relabels++;
         hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 1);
-        L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_count_active, dim3(grid), dim3(kBlock), 0, st, s); });
+        L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_count_active<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
         hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, s.slots, s.hdr, 0, nullptr);
         int32_t active = 0;
         if ((rc = read_i32(&s.hdr->active, &active, st)) != GC_OK) return rc;
@@ -1470,8 +1579,8 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
         if (active == 0) break;
         if (st_local.sweeps >= opt.max_sweeps) { status = GC_E_NOT_CONVERGED; break; }
         for (int i = 0; i < opt.period; ++i) {
-            L.run(GC_K_PUSH, [&] { hipLaunchKernelGGL(k_push, dim3(grid), dim3(kBlock), 0, st, s); });
-            L.run(GC_K_RELABEL, [&] { hipLaunchKernelGGL(k_relabel, dim3(grid), dim3(kBlock), 0, st, s); });
+            L.run(GC_K_PUSH, [&] { hipLaunchKernelGGL(k_push<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
+            L.run(GC_K_RELABEL, [&] { hipLaunchKernelGGL(k_relabel<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
             st_local.sweeps++;
         }
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
@@ -1511,7 +1620,7 @@ GC_API int approx_level2_cut(gc_graph *skin, const int32_t *cost, int32_t *label
         hipLaunchKernelGGL(k_block_cut, grid, dim3(kBlockLanes), 0, st, s, b, 64 + 24 * b * b * b);
         hipLaunchKernelGGL(k_labels_closure, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
     } else if (s.plane > 0) {
-        hipLaunchKernelGGL(k_labels<false>, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
+        hipLaunchKernelGGL(k_labels, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
     }
     if (s.plane > 0)
         hipLaunchKernelGGL(k_energy, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, cost, labels,
@@ -1523,6 +1632,265 @@ GC_API int approx_level2_cut(gc_graph *skin, const int32_t *cost, int32_t *label
     int32_t perr = 0;
     if ((rc = read_i32(&s.hdr->prefix_err, &perr, st)) != GC_OK) return rc;
     return (perr & 2) ? GC_E_NOT_CONVERGED : GC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched solve: one launch per phase covers every member graph.
+// ---------------------------------------------------------------------------
+
+struct gc_batch {
+    struct Member {
+        gc_graph g;
+        Graph s;
+        int64_t tag;
+        gc_solve_stats st;
+        int64_t blocks, tiles;
+    };
+    BatchDev *dev = nullptr;
+    Opts opt{};
+    std::vector<Member> mem;
+    std::vector<char> host;            // staging copy of the table prefix
+    bool dirty = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t exec_blocks = -1;
+    hipStream_t exec_stream = nullptr;
+};
+
+namespace {
+
+int batch_upload(gc_batch *b, hipStream_t st)
+{
+    if (!b->dirty) return GC_OK;
+    BatchDev *h = (BatchDev *)b->host.data();
+    const int ng = (int)b->mem.size();
+    h->ng = ng;
+    h->node_off[0] = 0;
+    h->tile_off[0] = 0;
+    for (int g = 0; g < ng; ++g) {
+        h->graphs[g] = b->mem[g].s;
+        h->node_off[g + 1] = h->node_off[g] + (int32_t)b->mem[g].blocks;
+        h->tile_off[g + 1] = h->tile_off[g] + (int32_t)b->mem[g].tiles;
+    }
+    const size_t bytes = offsetof(BatchDev, graphs) + (size_t)ng * sizeof(Graph);
+    if (!hip_ok(hipMemcpyAsync(b->dev, h, bytes, hipMemcpyHostToDevice, st))) return GC_E_HIP;
+    // the staging copy must outlive the transfer
+    if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
+    b->dirty = false;
+    return GC_OK;
+}
+
+void batch_drop_graph(gc_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->exec_blocks = -1;
+}
+
+void launch_sweeps(gc_batch *b, hipStream_t st, int64_t grid)
+{
+    Batch B{b->dev};
+    for (int i = 0; i < b->opt.period; ++i) {
+        hipLaunchKernelGGL(k_push<Batch>, dim3((unsigned)grid), dim3(kBlock), 0, st, B);
+        hipLaunchKernelGGL(k_relabel<Batch>, dim3((unsigned)grid), dim3(kBlock), 0, st, B);
+    }
+}
+
+}  // namespace
+
+GC_API size_t gc_batch_footprint_bytes(void) { return align256(sizeof(BatchDev)); }
+
+GC_API int gc_batch_create(void *dev_table, size_t dev_bytes, const gc_solve_opts *o,
+                           gc_batch **out)
+{
+    if (!dev_table || !out || ((uintptr_t)dev_table & 255) != 0) return GC_E_ARG;
+    if (dev_bytes < gc_batch_footprint_bytes()) return GC_E_WORKSPACE;
+    Opts opt = resolve(o);
+    int rc = check_opts(opt);
+    if (rc != GC_OK) return rc;
+    gc_batch *b = new (std::nothrow) gc_batch();
+    if (!b) return GC_E_ARG;
+    b->dev = (BatchDev *)dev_table;
+    b->opt = opt;
+    b->host.assign(sizeof(BatchDev), 0);
+    *out = b;
+    return GC_OK;
+}
+
+GC_API int gc_batch_destroy(gc_batch *b)
+{
+    if (!b) return GC_E_ARG;
+    batch_drop_graph(b);
+    delete b;
+    return GC_OK;
+}
+
+GC_API int gc_batch_members(const gc_batch *b) { return b ? (int)b->mem.size() : 0; }
+
+GC_API int gc_batch_add(gc_batch *b, const gc_graph *g, int64_t tag)
+{
+    if (!b) return GC_E_ARG;
+    int rc = graph_check(g);
+    if (rc != GC_OK) return rc;
+    if ((int)b->mem.size() >= kMaxBatch) return GC_E_ARG;
+    gc_batch::Member m;
+    m.g = *g;
+    m.s = view(g);
+    m.tag = tag;
+    memset(&m.st, 0, sizeof(m.st));
+    m.blocks = (int64_t)grid_for(m.s.N);
+    m.tiles = relax_tiles(m.s, b->opt);
+    if (m.s.N == 0) m.blocks = m.tiles = 0;
+    b->mem.push_back(m);
+    b->dirty = true;
+    return GC_OK;
+}
+
+GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solve_stats *done_stats,
+                          int32_t max_done, int32_t *n_done)
+{
+    if (!b || !n_done || (max_done > 0 && !done_tags)) return GC_E_ARG;
+    *n_done = 0;
+    hipStream_t st = (hipStream_t)stream;
+    int rc;
+    // empty graphs are finished at once
+    for (size_t i = 0; i < b->mem.size();) {
+        if (b->mem[i].s.N == 0 && *n_done < max_done) {
+            done_tags[*n_done] = b->mem[i].tag;
+            if (done_stats) done_stats[*n_done] = b->mem[i].st;
+            ++*n_done;
+            b->mem.erase(b->mem.begin() + i);
+            b->dirty = true;
+        } else {
+            ++i;
+        }
+    }
+    if (b->mem.empty()) return GC_OK;
+    if ((rc = batch_upload(b, st)) != GC_OK) return rc;
+    const int ng = (int)b->mem.size();
+    const BatchDev *h = (const BatchDev *)b->host.data();
+    const int64_t nblk = h->node_off[ng], ntile = h->tile_off[ng];
+    Batch B{b->dev};
+    const Opts &o = b->opt;
+
+    // exact global relabelling of every member
+    hipLaunchKernelGGL(k_mask<Batch>, dim3((unsigned)nblk), dim3(kBlock), 0, st, B, 0);
+    hipLaunchKernelGGL(k_seed<Batch>, dim3((unsigned)nblk), dim3(kBlock), 0, st, B, 0);
+    RelaxFn<Batch> fn = relax_kernel<Batch>(o.tw, o.th, o.tj);
+    std::vector<int32_t> gathered((size_t)ng * 16);
+    std::vector<char> conv(ng, 0);
+    int passes = 0, batch = 2, n_conv = 0;
+    while (n_conv < ng) {
+        hipLaunchKernelGGL(k_batch_zero, dim3(ng), dim3(kSlots), 0, st, b->dev, 0, passes + 1, batch);
+        for (int q = 1; q <= batch; ++q)
+            hipLaunchKernelGGL(fn, dim3((unsigned)ntile), dim3(kBlock), 0, st, B, 0, o.local_iters,
+                               passes + q);
+        hipLaunchKernelGGL(k_batch_gather, dim3(ng), dim3(kSlots), 0, st, b->dev, 0);
+        if (!hip_ok(hipGetLastError())) return GC_E_HIP;
+        if (!hip_ok(hipMemcpyAsync(gathered.data(), b->dev->gathered, gathered.size() * 4,
+                                   hipMemcpyDeviceToHost, st)))
+            return GC_E_HIP;
+        if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
+        for (int g = 0; g < ng; ++g) {
+            if (conv[g]) continue;
+            for (int q = 1; q <= batch; ++q) {
+                b->mem[g].st.bfs_passes++;
+                if (!gathered[(size_t)g * 16 + (passes + q) % kMaxFlags]) { conv[g] = 1; ++n_conv; break; }
+            }
+        }
+        passes += batch;
+        if (passes >= (1 << 22)) return GC_E_NOT_CONVERGED;
+        batch = batch * 2 > 8 ? 8 : batch * 2;
+    }
+    // termination test
+    hipLaunchKernelGGL(k_batch_zero, dim3(ng), dim3(kSlots), 0, st, b->dev, 1, 0, 0);
+    hipLaunchKernelGGL(k_count_active<Batch>, dim3((unsigned)nblk), dim3(kBlock), 0, st, B);
+    hipLaunchKernelGGL(k_batch_gather, dim3(ng), dim3(kSlots), 0, st, b->dev, 1);
+    if (!hip_ok(hipGetLastError())) return GC_E_HIP;
+    if (!hip_ok(hipMemcpyAsync(gathered.data(), b->dev->gathered, gathered.size() * 4,
+                               hipMemcpyDeviceToHost, st)))
+        return GC_E_HIP;
+    if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
+    std::vector<gc_batch::Member> keep;
+    keep.reserve(b->mem.size());
+    for (int g = 0; g < ng; ++g) {
+        gc_batch::Member &m = b->mem[g];
+        const int32_t *gv = &gathered[(size_t)g * 16];
+        m.st.global_relabels++;
+        m.st.active_last = gv[0];
+        m.st.pushes = (int64_t)(uint32_t)gv[1] | ((int64_t)(uint32_t)gv[2] << 31);
+        const bool finished = gv[0] == 0 || m.st.sweeps >= o.max_sweeps;
+        if (finished && *n_done < max_done) {
+            done_tags[*n_done] = m.tag;
+            if (done_stats) done_stats[*n_done] = m.st;
+            ++*n_done;
+            b->dirty = true;
+        } else {
+            keep.push_back(m);
+        }
+    }
+    b->mem.swap(keep);
+    if (b->mem.empty()) return GC_OK;
+    // push-relabel sweeps of the members still running
+    if ((rc = batch_upload(b, st)) != GC_OK) return rc;
+    const int64_t grid = ((const BatchDev *)b->host.data())->node_off[b->mem.size()];
+    const bool use_graph = st != nullptr && (o.flags & GC_OPT_BATCH_GRAPH) != 0;
+    if (use_graph) {
+        int64_t cap = 1;
+        while (cap < grid) cap <<= 1;                 // upper-bound grid: fewer captures
+        if (b->exec_blocks != cap || b->exec_stream != st) {
+            batch_drop_graph(b);
+            if (!hip_ok(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal))) return GC_E_HIP;
+            launch_sweeps(b, st, cap);
+            if (!hip_ok(hipStreamEndCapture(st, &b->graph))) return GC_E_HIP;
+            if (!hip_ok(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0))) return GC_E_HIP;
+            b->exec_blocks = cap;
+            b->exec_stream = st;
+        }
+        if (!hip_ok(hipGraphLaunch(b->exec, st))) return GC_E_HIP;
+    } else {
+        launch_sweeps(b, st, grid);
+    }
+    if (!hip_ok(hipGetLastError())) return GC_E_HIP;
+    for (auto &m : b->mem) m.st.sweeps += o.period;
+    return GC_OK;
+}
+
+GC_API int maxflow_solve_batch(gc_graph *const *gs, int32_t n, void *dev_table, size_t dev_bytes,
+                               const gc_solve_opts *o, gc_solve_stats *stats, void *stream)
+{
+    if (n < 0 || (n > 0 && !gs)) return GC_E_ARG;
+    for (int i = 0; i < n; ++i) {
+        int rc = graph_check(gs[i]);
+        if (rc != GC_OK) return rc;
+    }
+    gc_batch *b = nullptr;
+    int rc = gc_batch_create(dev_table, dev_bytes, o, &b);
+    if (rc != GC_OK) return rc;
+    int next = 0, done = 0;
+    std::vector<int64_t> tags(kMaxBatch);
+    std::vector<gc_solve_stats> sts(kMaxBatch);
+    int status = GC_OK;
+    while (done < n) {
+        while (next < n && gc_batch_members(b) < kMaxBatch) {
+            if ((rc = gc_batch_add(b, gs[next], next)) != GC_OK) { gc_batch_destroy(b); return rc; }
+            ++next;
+        }
+        int32_t nd = 0;
+        if ((rc = gc_batch_round(b, stream, tags.data(), sts.data(), kMaxBatch, &nd)) != GC_OK) {
+            gc_batch_destroy(b);
+            return rc;
+        }
+        for (int i = 0; i < nd; ++i) {
+            if (stats) stats[tags[i]] = sts[i];
+            if (sts[i].active_last != 0) status = GC_E_NOT_CONVERGED;
+        }
+        done += nd;
+    }
+    gc_batch_destroy(b);
+    return status;
 }
 
 GC_API int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *labels,
@@ -1537,24 +1905,17 @@ GC_API int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *label
     Opts opt = resolve(nullptr);
     Launcher L{st, false, {}};
     int passes = 0;
-    const bool win = g->window_block > 0;
     if (s.N > 0) {
         const unsigned grid = grid_for(s.N);
-        if (win) {
-            hipLaunchKernelGGL(k_mask<true>, dim3(grid), dim3(kBlock), 0, st, s, 1);
-            hipLaunchKernelGGL(k_seed<true>, dim3(grid), dim3(kBlock), 0, st, s, 1);
-        } else {
-            hipLaunchKernelGGL(k_mask<false>, dim3(grid), dim3(kBlock), 0, st, s, 1);
-            hipLaunchKernelGGL(k_seed<false>, dim3(grid), dim3(kBlock), 0, st, s, 1);
-        }
+        hipLaunchKernelGGL(k_mask<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 1);
+        hipLaunchKernelGGL(k_seed<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 1);
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
-        if ((rc = relax_to_fixpoint(s, s.aux, 0, opt, L, &passes)) != GC_OK) return rc;
+        if ((rc = relax_to_fixpoint(s, 1, opt, L, &passes)) != GC_OK) return rc;
     }
     hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(64), 0, st, result, s.hdr);
     hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 2);
     if (s.plane > 0) {
-        if (win) hipLaunchKernelGGL(k_labels<true>, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
-        else hipLaunchKernelGGL(k_labels<false>, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
+        hipLaunchKernelGGL(k_labels, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
         hipLaunchKernelGGL(k_energy, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, cost, labels,
                            p.width, p.height, p.labels, p.penalty_h, p.inhibit_h, p.penalty_v,
                            p.inhibit_v, s.slots);

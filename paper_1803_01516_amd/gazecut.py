@@ -36,6 +36,8 @@ class GcSolveOpts(ctypes.Structure):
 
 
 GC_OPT_TIME_KERNELS = 1
+GC_OPT_BATCH_GRAPH = 2
+GC_BATCH_MAX_GRAPHS = 256
 KERNEL_CLASSES = ("push", "relabel", "relax", "other")
 
 
@@ -57,7 +59,9 @@ class GcSolveStats(ctypes.Structure):
 
 EXPORTS = ("gc_status_str", "gc_last_hip_error", "gc_problem_check", "gc_graph_footprint_bytes",
            "stereo_cost_volume", "graph_build", "maxflow_solve", "extract_labels",
-           "gc_coarse_problem", "coarse_cost_volume", "graph_build_window", "approx_level2_cut")
+           "gc_coarse_problem", "coarse_cost_volume", "graph_build_window", "approx_level2_cut",
+           "gc_batch_footprint_bytes", "gc_batch_create", "gc_batch_destroy", "gc_batch_members",
+           "gc_batch_add", "gc_batch_round", "maxflow_solve_batch")
 
 _lib = None
 
@@ -110,6 +114,23 @@ def load(path: str = LIB_PATH):
     lib.graph_build_window.restype = ctypes.c_int
     lib.approx_level2_cut.argtypes = [ctypes.POINTER(GcGraph), P, P, P, P]
     lib.approx_level2_cut.restype = ctypes.c_int
+    lib.gc_batch_footprint_bytes.argtypes = []
+    lib.gc_batch_footprint_bytes.restype = ctypes.c_size_t
+    lib.gc_batch_create.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(GcSolveOpts), ctypes.POINTER(P)]
+    lib.gc_batch_create.restype = ctypes.c_int
+    lib.gc_batch_destroy.argtypes = [P]
+    lib.gc_batch_destroy.restype = ctypes.c_int
+    lib.gc_batch_members.argtypes = [P]
+    lib.gc_batch_members.restype = ctypes.c_int
+    lib.gc_batch_add.argtypes = [P, ctypes.POINTER(GcGraph), ctypes.c_int64]
+    lib.gc_batch_add.restype = ctypes.c_int
+    lib.gc_batch_round.argtypes = [P, P, P, ctypes.POINTER(GcSolveStats), ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_int32)]
+    lib.gc_batch_round.restype = ctypes.c_int
+    lib.maxflow_solve_batch.argtypes = [ctypes.POINTER(ctypes.POINTER(GcGraph)), ctypes.c_int32, P,
+                                        ctypes.c_size_t, ctypes.POINTER(GcSolveOpts),
+                                        ctypes.POINTER(GcSolveStats), P]
+    lib.maxflow_solve_batch.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -276,3 +297,74 @@ def approx_level1(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = Non
 def approx_level2(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, stream=None,
                   ws=None, ws_coarse=None):
     return approx_level1(p, cost, block, opts, stream, ws, ws_coarse, level=2)
+
+
+# ---------------------------------------------------------------------------
+# Batched solve
+# ---------------------------------------------------------------------------
+
+def batch_footprint_bytes() -> int:
+    return int(load().gc_batch_footprint_bytes())
+
+
+class Batch:
+    """Host handle of a gc_batch over a caller-owned device table."""
+
+    def __init__(self, table_ptr: int, table_bytes: int, opts: GcSolveOpts | None = None,
+                 table_owner=None):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        self._owner = table_owner            # keeps the device table alive
+        self._graphs = {}                    # tag -> Graph (keeps workspaces alive)
+        _check(self._lib.gc_batch_create(ctypes.c_void_p(table_ptr), ctypes.c_size_t(table_bytes),
+                                         ctypes.byref(opts) if opts is not None else None,
+                                         ctypes.byref(self._h)), "gc_batch_create")
+
+    @classmethod
+    def on_device(cls, opts: GcSolveOpts | None = None, device="cuda"):
+        import torch
+        t = torch.empty(batch_footprint_bytes(), dtype=torch.uint8, device=device)
+        return cls(t.data_ptr(), t.numel(), opts, table_owner=t)
+
+    def close(self):
+        if self._h:
+            self._lib.gc_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        self.close()
+
+    def __len__(self):
+        return int(self._lib.gc_batch_members(self._h))
+
+    def add(self, graph: Graph, tag: int):
+        _check(self._lib.gc_batch_add(self._h, ctypes.byref(graph.handle), int(tag)), "gc_batch_add")
+        self._graphs[int(tag)] = graph
+
+    def round(self, stream=None, max_done: int = GC_BATCH_MAX_GRAPHS):
+        """One round; returns [(tag, GcSolveStats)] of the members that finished."""
+        tags = (ctypes.c_int64 * max_done)()
+        sts = (GcSolveStats * max_done)()
+        nd = ctypes.c_int32()
+        _check(self._lib.gc_batch_round(self._h, _stream_ptr(stream), tags, sts, max_done,
+                                        ctypes.byref(nd)), "gc_batch_round")
+        out = []
+        for i in range(nd.value):
+            self._graphs.pop(int(tags[i]), None)
+            out.append((int(tags[i]), sts[i]))
+        return out
+
+
+def maxflow_solve_batch(graphs, opts: GcSolveOpts | None = None, stream=None, table=None):
+    """Solves a list of built graphs together; returns their stats in order."""
+    import torch
+    n = len(graphs)
+    arr = (ctypes.POINTER(GcGraph) * max(1, n))(*[ctypes.pointer(g.handle) for g in graphs])
+    if table is None:
+        table = torch.empty(batch_footprint_bytes(), dtype=torch.uint8, device="cuda")
+    sts = (GcSolveStats * max(1, n))()
+    _check(load().maxflow_solve_batch(arr, n, ctypes.c_void_p(table.data_ptr()),
+                                      ctypes.c_size_t(table.numel()),
+                                      ctypes.byref(opts) if opts is not None else None, sts,
+                                      _stream_ptr(stream)), "maxflow_solve_batch")
+    return [sts[i] for i in range(n)]

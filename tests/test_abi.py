@@ -70,3 +70,21 @@ def test_binding_fails_loudly_without_library(tmp_path):
             gc.load(str(tmp_path / "missing.so"))
         finally:
             gc._lib = gc._lib_backup
+
+
+def test_batch_host_object_without_gpu():
+    """gc_batch_create/add/members/destroy only touch host memory."""
+    fp = gc.batch_footprint_bytes()
+    assert fp > 0 and fp % 256 == 0
+    fake_table = 1 << 20                       # aligned, never dereferenced on the host
+    b = gc.Batch(fake_table, fp)
+    assert len(b) == 0
+    p = gc.problem(16, 8, 4, 20, 1, 1023)
+    g = gc.GcGraph(ws=1 << 24, ws_bytes=gc.footprint_bytes(p), p=p)
+    b.add(gc.Graph(g, None), 7)
+    assert len(b) == 1
+    with pytest.raises(gc.GazecutError):
+        gc.Batch(fake_table, fp - 1)
+    with pytest.raises(gc.GazecutError):
+        gc.Batch(fake_table + 4, fp)
+    b.close()

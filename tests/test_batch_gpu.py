@@ -1,0 +1,108 @@
+"""GPU tests of the batched solve: graphs of mixed sizes and kinds solved in
+one batch (one launch per phase over all members) give the same canonical
+cut, energy and flow as one solve per graph and as the oracle."""
+import numpy as np
+import pytest
+
+from paper_1803_01516_amd import gazecut as gc
+from paper_1803_01516_amd import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gc.load()
+    return torch
+
+
+def _cases(orc):
+    """(name, cost volume, penalty, inhibit, thin-skin block or 0)."""
+    out = []
+    for name, spec, seed, lam in [("tiny-a", sg.TINY, (1, 0), 1), ("tiny-b", sg.TINY, (1, 1), 2),
+                                  ("ragged", sg.spec_like(sg.TINY, 37, 19, 5), (9, 9), 1),
+                                  ("ragged2", sg.spec_like(sg.MID, 70, 33, 9), (9, 8), 1),
+                                  ("mid", sg.MID, (2, 0), 1)]:
+        pr = sg.make_pair(spec, seed)
+        out.append((name, orc.cost_volume(pr.left, pr.right, spec.m, spec.cap), lam, 1023, 0))
+    rng = np.random.default_rng(5)
+    out.append(("m2", rng.integers(0, 31, (2, 9, 20)).astype(np.int32), 1, 1023, 0))
+    pr = sg.make_pair(sg.spec_like(sg.MID, 128, 96, 16), (5, 5))
+    out.append(("skin-b2", orc.cost_volume(pr.left, pr.right, 16, 30), 1, 1023, 2))
+    out.append(("empty", np.zeros((8, 0, 0), np.int32), 1, 1023, 0))
+    return out
+
+
+def _build(torch, orc, name, cost_np, pen, inh, block):
+    m, h, w = cost_np.shape
+    p = gc.problem(w, h, m, 30, pen, inh)
+    cost = torch.from_numpy(np.ascontiguousarray(cost_np)).cuda() if cost_np.size else \
+        torch.empty(1, dtype=torch.int32, device="cuda")
+    ws = torch.empty(max(256, gc.footprint_bytes(p)), dtype=torch.uint8, device="cuda")
+    if block:
+        _, _, _, clab, _ = gc.approx_level1(p, cost, block)          # its delegate cut
+        g = gc.graph_build_window(p, cost, clab, block, ws)
+        ref = orc.solve_window(cost_np, *orc.skin_windows(clab.cpu().numpy(), w, h, m, block), pen, inh)
+    else:
+        g = gc.graph_build(p, cost, ws)
+        ref = orc.solve(cost_np, pen, inh) if cost_np.size else (np.zeros((0, 0), np.int32), 0, 0)
+    return p, cost, g, ref
+
+
+def _read(torch, g, cost, p):
+    lab = torch.empty((max(1, p.height), max(1, p.width)), dtype=torch.int32, device="cuda")
+    res = torch.zeros(2, dtype=torch.int64, device="cuda")
+    gc.extract_labels(g, cost, lab, res)
+    r = res.cpu().tolist()
+    return lab.cpu().numpy()[:p.height, :p.width], r[0], r[1]
+
+
+def _check(ref, got):
+    ol, of, oe = ref
+    lab, e, f = got
+    assert e == oe and f == of
+    assert (lab == ol).all()
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_matches_oracle(torch_cuda, orc, use_graph):
+    torch = torch_cuda
+    stream = torch.cuda.Stream() if use_graph else None
+    opts = gc.GcSolveOpts(flags=gc.GC_OPT_BATCH_GRAPH if use_graph else 0)
+    built = []
+    ctx = torch.cuda.stream(stream) if stream is not None else torch.cuda.stream(torch.cuda.current_stream())
+    with ctx:
+        for c in _cases(orc):
+            built.append(_build(torch, orc, *c))
+        stats = gc.maxflow_solve_batch([b[2] for b in built], opts, stream=stream)
+        for (p, cost, g, ref), st in zip(built, stats):
+            assert st.active_last == 0
+            _check(ref, _read(torch, g, cost, p))
+    torch.cuda.synchronize()
+
+
+def test_batch_rounds_with_members_joining(torch_cuda, orc):
+    """Graphs join between rounds while others are still being solved."""
+    torch = torch_cuda
+    cases = _cases(orc)
+    built = [_build(torch, orc, *c) for c in cases]
+    b = gc.Batch.on_device(gc.GcSolveOpts(relabel_period=16))
+    pending = list(range(len(built)))
+    done = {}
+    b.add(built[pending.pop(0)][2], 0)
+    rounds = 0
+    while len(done) < len(built):
+        if pending:
+            i = pending.pop(0)
+            b.add(built[i][2], i)
+        for tag, st in b.round():
+            assert st.active_last == 0
+            done[tag] = st
+        rounds += 1
+        assert rounds < 10000
+    for i, (p, cost, g, ref) in enumerate(built):
+        _check(ref, _read(torch, g, cost, p))
+    b.close()
