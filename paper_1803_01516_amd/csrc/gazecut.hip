@@ -102,6 +102,8 @@ struct Graph {
     uint16_t *mask;
     int32_t *stamps;          // per relaxation tile: last pass that changed it
     int32_t *wlo, *whi;       // per-site label window of a thin-skin graph
+    uint8_t *bact;            // per 256-node block: holds an active node
+    uint8_t *binf;            // per 256-node block: received inflow in the last push sweep
     DevHeader *hdr;
     Slot *slots;
     int32_t W, H, J;
@@ -151,6 +153,8 @@ Graph view(const gc_graph *g)
     s.mask = (uint16_t *)b; b += align256((size_t)s.N * 2);
     s.wlo = (int32_t *)b; b += align256((size_t)s.plane * 4);
     s.whi = (int32_t *)b; b += align256((size_t)s.plane * 4);
+    s.bact = (uint8_t *)b; b += align256((size_t)(s.N + kBlock - 1) / kBlock);
+    s.binf = (uint8_t *)b; b += align256((size_t)(s.N + kBlock - 1) / kBlock);
     s.stamps = (int32_t *)b;
     s.te = 2 * p.penalty_h; s.ts = 2 * p.penalty_v;
     s.ie = p.inhibit_h; s.is = p.inhibit_v;
@@ -565,6 +569,7 @@ k_push(Src src)
     Graph s;
     int64_t lb;
     if (!locate(src, 0, s, lb)) return;
+    if (!s.bact[lb]) return;                  // no active node in this block
     int64_t n = lb * kBlock + threadIdx.x;
     int cnt = 0;
     if (n < s.N) {
@@ -588,7 +593,9 @@ k_push(Src src)
                 if (e > 0 && r > 0 && hv[d] == h - 1) {
                     const int32_t delta = e < r ? e : r;
                     *word_ptr(s, n, d) = word_is_forward(d) ? w[d] - delta : w[d] + delta;
-                    atomicAdd(&s.ein[nbr(s, n, d)], delta);
+                    const int64_t v = nbr(s, n, d);
+                    atomicAdd(&s.ein[v], delta);
+                    s.binf[v / kBlock] = 1;
                     e -= delta;
                     ++cnt;
                 }
@@ -609,34 +616,44 @@ k_relabel(Src src)
     Graph s;
     int64_t lb;
     if (!locate(src, 0, s, lb)) return;
+    if (!s.bact[lb] && !s.binf[lb]) return;   // nothing arrived, nothing to lift
     int64_t n = lb * kBlock + threadIdx.x;
-    if (n >= s.N) return;
-    int32_t in = s.ein[n];
-    int32_t e = s.ex[n];
-    if (in != 0) {
-        e += in;
-        s.ex[n] = e;
-        s.ein[n] = 0;
-    }
-    const int32_t h = s.ht[n];
-    if (e <= 0 || h >= kInf) return;
-    int j, y, x;
-    decode(s, n, j, y, x);
-    const unsigned ex_mask = arc_exists(s, j, y, x);
-    int32_t w[14], hv[14];
+    bool active = false;
+    if (n < s.N) {
+        int32_t in = s.ein[n];
+        int32_t e = s.ex[n];
+        if (in != 0) {
+            e += in;
+            s.ex[n] = e;
+            s.ein[n] = 0;
+        }
+        const int32_t h = s.ht[n];
+        if (e > 0 && h < kInf) {
+            int j, y, x;
+            decode(s, n, j, y, x);
+            const unsigned ex_mask = arc_exists(s, j, y, x);
+            int32_t w[14], hv[14];
 #pragma unroll
-    for (int d = 0; d < 14; ++d) {
-        const bool ok = (ex_mask >> d) & 1u;
-        w[d] = ok ? *word_ptr(s, n, d) : 0;
-        hv[d] = ok ? s.ht[nbr(s, n, d)] : kInf;
-    }
-    int32_t hmin = kInf;
+            for (int d = 0; d < 14; ++d) {
+                const bool ok = (ex_mask >> d) & 1u;
+                w[d] = ok ? *word_ptr(s, n, d) : 0;
+                hv[d] = ok ? s.ht[nbr(s, n, d)] : kInf;
+            }
+            int32_t hmin = kInf;
 #pragma unroll
-    for (int d = 0; d < 14; ++d)
-        if (((ex_mask >> d) & 1u) && res_from_word(s, d, w[d]) > 0)
-            hmin = hv[d] < hmin ? hv[d] : hmin;
-    const int32_t nh = hmin >= kInf ? kInf : hmin + 1;
-    if (nh > h) s.ht[n] = nh;
+            for (int d = 0; d < 14; ++d)
+                if (((ex_mask >> d) & 1u) && res_from_word(s, d, w[d]) > 0)
+                    hmin = hv[d] < hmin ? hv[d] : hmin;
+            const int32_t nh = hmin >= kInf ? kInf : hmin + 1;
+            if (nh > h) s.ht[n] = nh;
+            active = nh < kInf;
+        }
+    }
+    const int any = block_sum(active ? 1 : 0);
+    if (threadIdx.x == 0) {
+        s.bact[lb] = any > 0;
+        s.binf[lb] = 0;
+    }
 }
 
 __device__ inline bool is_frozen(const Graph &s, int j, int y, int x)
@@ -883,7 +900,11 @@ k_count_active(Src src)
     int a = 0;
     if (n < s.N) a = (s.ex[n] > 0 && s.ht[n] < kInf) ? 1 : 0;
     a = block_sum(a);
-    if (threadIdx.x == 0 && a) atomicAdd(&my_slot(s.slots, lb).active, a);
+    if (threadIdx.x == 0) {
+        if (a) atomicAdd(&my_slot(s.slots, lb).active, a);
+        s.bact[lb] = a > 0;                   // block flags of the sweeps that follow
+        s.binf[lb] = 0;
+    }
 }
 
 __global__ void k_zero_header(DevHeader *h, int what)
@@ -1426,8 +1447,10 @@ GC_API size_t gc_graph_footprint_bytes(const gc_problem *p)
     if (gc_problem_check(p) != GC_OK) return 0;
     size_t n = (size_t)node_count(p);
     const size_t sites = (size_t)p->width * p->height;
+    const size_t blocks = (n + kBlock - 1) / kBlock;
     return align256(sizeof(DevHeader)) + align256(kSlots * sizeof(Slot)) + 11 * align256(n * 4) +
-           align256(n * 2) + 2 * align256(sites * 4) + align256(max_tiles(p) * 4);
+           align256(n * 2) + 2 * align256(sites * 4) + 2 * align256(blocks) +
+           align256(max_tiles(p) * 4);
 }
 
 GC_API int stereo_cost_volume(const uint8_t *left, const uint8_t *right, const gc_problem *p,

@@ -1,0 +1,306 @@
+"""Runtime above the C ABI: autotuner, batched workload runner and the
+continuous-batching serving loop.
+
+Orchestration only: every step of the path (cost volume, graph build,
+max-flow, cut read-out) runs in the HIP library through ``gazecut``; the
+batch engine that schedules graphs round by round is native (``gc_batch_*``).
+PyTorch provides device memory and streams.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import gazecut as gc
+from . import scenegen as sg
+
+
+# ---------------------------------------------------------------------------
+# Items of work
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Item:
+    """One stereo pair resident on the device, with its graph workspace."""
+    tag: int
+    spec: sg.SceneSpec
+    left: object                 # uint8 [h][w] device tensor
+    right: object
+    p: gc.GcProblem
+    cost: object = None          # int32 [m][h][w]
+    ws: object = None            # uint8 workspace
+    graph: gc.Graph | None = None
+    labels: object = None
+    result: object = None        # int64 [2]
+    energy: int = 0
+    flow: int = 0
+    stats: dict = field(default_factory=dict)
+    t_done: float = 0.0
+
+    @property
+    def footprint(self) -> int:
+        return gc.footprint_bytes(self.p) + 4 * self.p.labels * self.p.height * self.p.width
+
+
+def make_item(tag, spec: sg.SceneSpec, pair: sg.Pair, lam=1, device="cuda") -> Item:
+    import torch
+    p = gc.problem(spec.w, spec.h, spec.m, spec.cap, lam, spec.inhibit)
+    return Item(tag, spec, torch.from_numpy(pair.left).to(device),
+                torch.from_numpy(pair.right).to(device), p)
+
+
+def prepare(item: Item, stream=None):
+    """Allocates device buffers, computes the cost volume and builds the graph."""
+    import torch
+    dev = item.left.device
+    p = item.p
+    if item.cost is None:
+        item.cost = torch.empty((p.labels, p.height, p.width), dtype=torch.int32, device=dev)
+        item.ws = torch.empty(gc.footprint_bytes(p), dtype=torch.uint8, device=dev)
+        item.labels = torch.empty((p.height, p.width), dtype=torch.int32, device=dev)
+        item.result = torch.zeros(2, dtype=torch.int64, device=dev)
+    gc.stereo_cost_volume(item.left, item.right, p, item.cost, stream)
+    item.graph = gc.graph_build(p, item.cost, item.ws, stream)
+
+
+def finish(item: Item, stream=None):
+    gc.extract_labels(item.graph, item.cost, item.labels, item.result, stream)
+    r = item.result.cpu().tolist()
+    item.energy, item.flow = int(r[0]), int(r[1])
+
+
+def release(item: Item):
+    item.cost = item.ws = item.graph = None
+
+
+# ---------------------------------------------------------------------------
+# Autotuner: relaxation tile shape and global-relabel period
+# ---------------------------------------------------------------------------
+
+TILE_CANDIDATES = ((8, 8, 16), (16, 8, 16), (8, 8, 32), (16, 16, 8))
+PERIOD_CANDIDATES = (32, 64, 128)
+
+
+def autotune(items, tiles=TILE_CANDIDATES, periods=PERIOD_CANDIDATES, stream=None,
+             use_graph=False):
+    """Times one batched solve of `items` per (tile, period) candidate and
+    returns (best options, [(tile, period, seconds)]).  The items' graphs are
+    rebuilt in place before every trial, so the trials solve the same graphs."""
+    import torch
+    flags = gc.GC_OPT_BATCH_GRAPH if use_graph else 0
+    table = torch.empty(gc.batch_footprint_bytes(), dtype=torch.uint8, device="cuda")
+    trials = []
+    for tile in tiles:
+        for period in periods:
+            opts = gc.GcSolveOpts(relabel_period=period, tile_w=tile[0], tile_h=tile[1],
+                                  tile_j=tile[2], flags=flags)
+            for it in items:
+                prepare(it, stream)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            gc.maxflow_solve_batch([it.graph for it in items], opts, stream, table)
+            torch.cuda.synchronize()
+            trials.append((tile, period, time.perf_counter() - t))
+    tile, period, _ = min(trials, key=lambda r: r[2])
+    best = gc.GcSolveOpts(relabel_period=period, tile_w=tile[0], tile_h=tile[1], tile_j=tile[2],
+                          flags=flags)
+    return best, trials
+
+
+# ---------------------------------------------------------------------------
+# Batched workload: many uneven pairs, batched vs one pair per launch
+# ---------------------------------------------------------------------------
+
+def batch_mix(n=64, shapes=sg.BATCH_SHAPES, seed=4, base=sg.MID):
+    """n seeded pairs, shapes drawn uniformly from `shapes` (W, H, labels),
+    generated with the slanted-plane settings of `base`."""
+    rng = np.random.default_rng([seed, n])
+    picks = rng.integers(0, len(shapes), n)
+    out = []
+    for i, k in enumerate(picks):
+        w, h, m = shapes[int(k)]
+        spec = sg.spec_like(base, w, h, m)
+        out.append((spec, sg.make_pair(spec, (seed, i))))
+    return out
+
+
+def run_one_per_launch(items, opts=None, stream=None):
+    """Solves the items one after another; returns per-item completion times
+    (seconds from the start) and the total."""
+    import torch
+    for it in items:
+        prepare(it, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for it in items:
+        st = gc.maxflow_solve(it.graph, opts, stream)
+        finish(it, stream)
+        it.t_done = time.perf_counter() - t0
+        it.stats = st.as_dict()
+    torch.cuda.synchronize()
+    return [it.t_done for it in items], time.perf_counter() - t0
+
+
+def run_batched(items, opts=None, stream=None):
+    """Solves all items in one batch; each item's labels are read as soon as
+    it leaves the batch.  Returns completion times and the total."""
+    import torch
+    for it in items:
+        prepare(it, stream)
+    torch.cuda.synchronize()
+    b = gc.Batch.on_device(opts)
+    by_tag = {it.tag: it for it in items}
+    t0 = time.perf_counter()
+    pending = list(items)
+    done = 0
+    while done < len(items):
+        while pending and len(b) < gc.GC_BATCH_MAX_GRAPHS:
+            it = pending.pop(0)
+            b.add(it.graph, it.tag)
+        for tag, st in b.round(stream):
+            it = by_tag[tag]
+            finish(it, stream)
+            it.t_done = time.perf_counter() - t0
+            it.stats = st.as_dict()
+            done += 1
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    b.close()
+    return [it.t_done for it in items], total
+
+
+# ---------------------------------------------------------------------------
+# Serving: continuous batching with admission by device-memory footprint
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float               # seconds after the start of the stream
+    shape: tuple
+    pool_index: int
+    item: Item | None = None
+    t_admit: float = 0.0
+    t_done: float = 0.0
+
+
+def poisson_requests(n, rate, shapes=sg.SERVE_SHAPES, pool_per_shape=2, seed=5):
+    """n requests with exponential inter-arrival times at `rate` per second,
+    shapes drawn uniformly; each request names a pair of a small seeded pool
+    per shape (generating a fresh scene per request would cost more than the
+    solve at these rates)."""
+    rng = np.random.default_rng([seed, n])
+    gaps = rng.exponential(1.0 / rate, n)
+    arrivals = np.cumsum(gaps)
+    picks = rng.integers(0, len(shapes), n)
+    pools = rng.integers(0, pool_per_shape, n)
+    return [Request(i, float(arrivals[i]), tuple(shapes[int(picks[i])]), int(pools[i]))
+            for i in range(n)]
+
+
+class Server:
+    """Continuous batching over the native batch engine.
+
+    Requests are admitted in arrival order while the bytes of live graph
+    workspaces and cost volumes stay within `budget_bytes` and the batch has
+    room; an admitted request's cost volume and graph are built on the
+    serving stream and the graph joins the running batch at the next round,
+    so its work overlaps with the requests already on the GPU.  Finished
+    graphs leave the batch, their labels are read and their memory is freed.
+    """
+
+    def __init__(self, budget_bytes, opts=None, stream=None, lam=1, device="cuda"):
+        self.budget = int(budget_bytes)
+        self.opts = opts
+        self.stream = stream
+        self.lam = lam
+        self.device = device
+        self.batch = gc.Batch.on_device(opts, device)
+        self.used = 0
+        self.live = {}
+        self.rounds = 0
+        self.peak_used = 0
+        self.peak_members = 0
+
+    def fits(self, item: Item) -> bool:
+        return self.used + item.footprint <= self.budget and len(self.batch) < gc.GC_BATCH_MAX_GRAPHS
+
+    def admit(self, req: Request, item: Item, now: float):
+        prepare(item, self.stream)
+        self.batch.add(item.graph, req.rid)
+        self.used += item.footprint
+        self.peak_used = max(self.peak_used, self.used)
+        self.live[req.rid] = req
+        req.item = item
+        req.t_admit = now
+        self.peak_members = max(self.peak_members, len(self.batch))
+
+    def step(self, clock):
+        """One batch round; returns the requests that completed."""
+        out = []
+        for tag, st in self.batch.round(self.stream):
+            req = self.live.pop(tag)
+            finish(req.item, self.stream)
+            req.item.stats = st.as_dict()
+            req.t_done = clock()
+            self.used -= req.item.footprint
+            release(req.item)
+            out.append(req)
+        self.rounds += 1
+        return out
+
+
+def serve(requests, pools, budget_bytes, opts=None, stream=None, lam=1, keep_labels=False,
+          max_wall_s=None):
+    """Runs the request stream in real time.  `pools[shape][i]` is the
+    (spec, pair) a request names.  Returns (completed requests, wall seconds,
+    server).  With keep_labels the label tensors are copied to the host."""
+    import torch
+    srv = Server(budget_bytes, opts, stream, lam)
+    queue = list(requests)
+    qi = 0
+    done = []
+    t0 = time.perf_counter()
+
+    def clock():
+        return time.perf_counter() - t0
+
+    while len(done) < len(queue):
+        now = clock()
+        if max_wall_s is not None and now > max_wall_s:
+            break
+        while qi < len(queue) and queue[qi].arrival <= now:
+            req = queue[qi]
+            spec, pair = pools[req.shape][req.pool_index]
+            item = make_item(req.rid, spec, pair, lam)
+            if item.footprint > budget_bytes:
+                raise ValueError(f"request {req.rid} needs {item.footprint} B, budget {budget_bytes}")
+            if not srv.fits(item):
+                break                               # head of line waits for memory
+            srv.admit(req, item, now)
+            qi += 1
+        if len(srv.batch) == 0:
+            if qi < len(queue):
+                time.sleep(max(0.0, min(0.001, queue[qi].arrival - clock())))
+            continue
+        for req in srv.step(clock):
+            if keep_labels:
+                req.item.labels = req.item.labels.cpu().numpy()
+            else:
+                req.item.labels = None
+            done.append(req)
+    torch.cuda.synchronize()
+    return done, clock(), srv
+
+
+def latency_summary(done):
+    lat = np.array([r.t_done - r.arrival for r in done]) * 1e3
+    wait = np.array([r.t_admit - r.arrival for r in done]) * 1e3
+    if lat.size == 0:
+        return {}
+    return {"p50_ms": round(float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "mean_ms": round(float(lat.mean()), 2),
+            "admission_wait_p99_ms": round(float(np.percentile(wait, 99)), 2)}

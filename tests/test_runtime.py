@@ -1,0 +1,101 @@
+"""Runtime: request streams, the batched workload runner, the autotuner and
+the continuous-batching server.  GPU tests show that every request's result
+is the same alone and in the mix (bit-exact: the cut is canonical)."""
+import numpy as np
+import pytest
+
+from paper_1803_01516_amd import gazecut as gc
+from paper_1803_01516_amd import runtime as rt
+from paper_1803_01516_amd import scenegen as sg
+
+SMALL_SHAPES = ((64, 48, 8), (96, 72, 16), (37, 19, 5))
+
+
+def test_poisson_requests_are_seeded_and_ordered():
+    a = rt.poisson_requests(500, 200.0, SMALL_SHAPES, seed=5)
+    b = rt.poisson_requests(500, 200.0, SMALL_SHAPES, seed=5)
+    assert [(r.arrival, r.shape, r.pool_index) for r in a] == [(r.arrival, r.shape, r.pool_index) for r in b]
+    arr = np.array([r.arrival for r in a])
+    assert (np.diff(arr) > 0).all()
+    rate = len(arr) / arr[-1]
+    assert 150 < rate < 260                     # 200 req/s within sampling noise
+    assert {r.shape for r in a} == set(SMALL_SHAPES)
+
+
+def test_batch_mix_is_seeded():
+    a = rt.batch_mix(6, SMALL_SHAPES, seed=3)
+    b = rt.batch_mix(6, SMALL_SHAPES, seed=3)
+    for (sa, pa), (sb, pb) in zip(a, b):
+        assert sa == sb and (pa.left == pb.left).all()
+
+
+def _pools(shapes, per=2, seed=8):
+    return {s: [(sg.spec_like(sg.MID, *s), sg.make_pair(sg.spec_like(sg.MID, *s), (seed, k, i)))
+                for i in range(per)] for k, s in enumerate(shapes)}
+
+
+def _alone(spec, pair, lam=1):
+    import torch
+    p = gc.problem(spec.w, spec.h, spec.m, spec.cap, lam, spec.inhibit)
+    lab, cost, e, f, st = gc.solve_pair(torch.from_numpy(pair.left).cuda(),
+                                       torch.from_numpy(pair.right).cuda(), p)
+    return lab.cpu().numpy(), e, f
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("budget_mb", [4096, 6])
+def test_serving_results_same_alone_and_in_mix(budget_mb):
+    """Requests arriving at 2000/s overlap on the GPU (or, with a 6 MB budget,
+    wait for memory); each result equals the same pair solved alone."""
+    import torch
+    pools = _pools(SMALL_SHAPES)
+    reqs = rt.poisson_requests(24, 2000.0, SMALL_SHAPES, pool_per_shape=2, seed=6)
+    stream = torch.cuda.Stream()
+    opts = gc.GcSolveOpts(flags=gc.GC_OPT_BATCH_GRAPH)
+    with torch.cuda.stream(stream):
+        done, wall, srv = rt.serve(reqs, pools, budget_mb << 20, opts, stream, keep_labels=True)
+    assert len(done) == len(reqs)
+    assert srv.used == 0
+    if budget_mb > 100:
+        assert srv.peak_members > 1                 # requests overlapped
+    assert srv.peak_used <= budget_mb << 20
+    cache = {}
+    for r in done:
+        key = (r.shape, r.pool_index)
+        if key not in cache:
+            cache[key] = _alone(*pools[r.shape][r.pool_index])
+        lab, e, f = cache[key]
+        assert r.item.energy == e and r.item.flow == f
+        assert (r.item.labels == lab).all()
+        assert r.t_done >= r.t_admit >= r.arrival - 1e-3
+
+
+@pytest.mark.gpu
+def test_batched_runner_matches_one_per_launch_and_oracle(orc):
+    import torch
+    mix = rt.batch_mix(8, SMALL_SHAPES, seed=7)
+    a = [rt.make_item(i, s, p) for i, (s, p) in enumerate(mix)]
+    b = [rt.make_item(i, s, p) for i, (s, p) in enumerate(mix)]
+    ta, tot_a = rt.run_one_per_launch(a)
+    tb, tot_b = rt.run_batched(b, gc.GcSolveOpts(relabel_period=32))
+    for x, y, (spec, pair) in zip(a, b, mix):
+        assert x.energy == y.energy == x.flow == y.flow
+        assert (x.labels.cpu() == y.labels.cpu()).all()
+    spec, pair = mix[0]
+    cost = orc.cost_volume(pair.left, pair.right, spec.m, spec.cap)
+    lab, f, e = orc.solve(cost, 1, 1023)
+    assert a[0].energy == e and (a[0].labels.cpu().numpy() == lab).all()
+    torch.cuda.synchronize()
+
+
+@pytest.mark.gpu
+def test_autotune_picks_a_candidate():
+    mix = rt.batch_mix(3, SMALL_SHAPES, seed=9)
+    items = [rt.make_item(i, s, p) for i, (s, p) in enumerate(mix)]
+    best, trials = rt.autotune(items, tiles=((8, 8, 16), (16, 8, 16)), periods=(16, 64))
+    assert len(trials) == 4
+    assert (best.tile_w, best.tile_h, best.tile_j) in {(8, 8, 16), (16, 8, 16)}
+    assert best.relabel_period in (16, 64)
+    for it in items:                      # the last trial left solved graphs
+        rt.finish(it)
+        assert it.energy == it.flow
