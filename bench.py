@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-approx", action="store_true", help="skip the approximate variants")
+    ap.add_argument("--batch-pairs", type=int, default=64, help="pairs of the uneven batch (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=60, help="requests of the serving stream (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     return ap.parse_args()
 
 
@@ -64,6 +68,85 @@ def algorithmic_bytes(kind: str, nodes: int, active_mean: float) -> float:
     if kind == "relabel":
         return 12.0 * nodes + 116.0 * active_mean
     return 0.0
+
+
+def _pct(xs, q):
+    return round(float(np.percentile(np.array(xs) * 1e3, q)), 2)
+
+
+def bench_batch(args, gc, sg, torch):
+    """Uneven batch: pairs drawn uniformly from 320x240x16, 384x288x16,
+    450x375x64 and 640x480x64, solved one pair per launch and in one batch
+    (autotuned tile and relabel period, sweeps replayed from a hipGraph).
+    Latency of a pair = its completion time from the start of the run."""
+    from paper_1803_01516_amd import runtime as rt
+    stream = torch.cuda.Stream()
+    mix = rt.batch_mix(args.batch_pairs, sg.BATCH_SHAPES, seed=4)
+    with torch.cuda.stream(stream):
+        # autotune on one pair of every shape class
+        seen, tune = set(), []
+        for i, (spec, pair) in enumerate(mix):
+            key = (spec.w, spec.h, spec.m)
+            if key not in seen:
+                seen.add(key)
+                tune.append(rt.make_item(i, spec, pair))
+        t = time.perf_counter()
+        best, trials = rt.autotune(tune, stream=stream, use_graph=True)
+        tune_s = time.perf_counter() - t
+        for it in tune:
+            rt.release(it)
+        one = [rt.make_item(i, spec, pair) for i, (spec, pair) in enumerate(mix)]
+        t_one, tot_one = rt.run_one_per_launch(one, None, stream)
+        ref = [(it.energy, it.flow, it.labels.cpu()) for it in one]
+        for it in one:
+            rt.release(it)
+        del one
+        torch.cuda.empty_cache()
+        bat = [rt.make_item(i, spec, pair) for i, (spec, pair) in enumerate(mix)]
+        t_bat, tot_bat = rt.run_batched(bat, best, stream)
+        same = all(it.energy == r[0] and it.flow == r[1] and bool((it.labels.cpu() == r[2]).all())
+                   for it, r in zip(bat, ref))
+        nodes = sum(it.p.width * it.p.height * (it.p.labels - 1) for it in bat)
+        for it in bat:
+            rt.release(it)
+        del bat
+        torch.cuda.empty_cache()
+    n = len(mix)
+    return {"workload": f"{n} seeded pairs uniform over 320x240x16, 384x288x16, 450x375x64, "
+                        "640x480x64 (6-10 slanted planes, sigma 3, cap 30, penalty 1, inhibit 1023)",
+            "nodes_total": nodes,
+            "batched": {"pairs_per_s": round(n / tot_bat, 2), "total_s": round(tot_bat, 3),
+                        "p50_ms": _pct(t_bat, 50), "p99_ms": _pct(t_bat, 99)},
+            "one_per_launch": {"pairs_per_s": round(n / tot_one, 2), "total_s": round(tot_one, 3),
+                               "p50_ms": _pct(t_one, 50), "p99_ms": _pct(t_one, 99)},
+            "speedup": round(tot_one / tot_bat, 3),
+            "autotuned": {"tile": [best.tile_w, best.tile_h, best.tile_j],
+                          "relabel_period": best.relabel_period, "tuning_s": round(tune_s, 2),
+                          "candidates": len(trials)},
+            "identical_results": same}
+
+
+def bench_serving(args, gc, sg, torch):
+    """Poisson request stream over 384x288x16, 640x480x64 and 1280x720x128
+    pairs, served by continuous batching with admission by workspace
+    footprint.  Latency = completion - arrival."""
+    from paper_1803_01516_amd import runtime as rt
+    stream = torch.cuda.Stream()
+    pools = {s: [(sg.spec_like(sg.MID, *s), sg.make_pair(sg.spec_like(sg.MID, *s), (5, k, i)))
+                 for i in range(2)] for k, s in enumerate(sg.SERVE_SHAPES)}
+    reqs = rt.poisson_requests(args.serve_requests, args.serve_rate, sg.SERVE_SHAPES, 2, seed=5)
+    opts = gc.GcSolveOpts(flags=gc.GC_OPT_BATCH_GRAPH)
+    with torch.cuda.stream(stream):
+        done, wall, srv = rt.serve(reqs, pools, int(args.serve_budget_gb * 1e9), opts, stream)
+    torch.cuda.empty_cache()
+    out = {"workload": f"{len(reqs)} Poisson requests at {args.serve_rate:g}/s, uniform over "
+                       "384x288x16, 640x480x64, 1280x720x128",
+           "completed": len(done), "wall_s": round(wall, 3),
+           "pairs_per_s": round(len(done) / wall, 2), "rounds": srv.rounds,
+           "peak_members": srv.peak_members, "peak_gb": round(srv.peak_used / 1e9, 2),
+           "budget_gb": args.serve_budget_gb}
+    out.update(rt.latency_summary(done))
+    return out
 
 
 def main():
@@ -187,6 +270,9 @@ def main():
                                "eq2_error_mean": round(float(np.mean(errs)), 1),
                                "pct_exact_mean": round(float(np.mean(pcts)), 1)}
 
+    batch = bench_batch(args, gc, sg, torch) if args.batch_pairs > 0 else None
+    serving = bench_serving(args, gc, sg, torch) if args.serve_requests > 0 else None
+
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
@@ -241,6 +327,8 @@ def main():
         "energy_last": int(r[0]), "flow_last": int(r[1]),
         "eq2_error_last": err, "pct_exact_last": pct,
         "approx": approx or None,
+        "batch": batch,
+        "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,

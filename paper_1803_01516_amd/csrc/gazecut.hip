@@ -202,9 +202,9 @@ __device__ inline Slot &my_slot(Slot *slots, int64_t lb) { return slots[lb & (kS
 // Kernel sources.  A solver kernel runs either on one graph (passed by value,
 // one block per 256 nodes or per tile) or on a batch: a device table of
 // graphs with prefix offsets of their blocks, where a block finds its graph
-// by binary search.  Blocks past the batch total exit at once, so a launch
-// may use an upper-bound grid.
+// by binary search.
 constexpr int kMaxBatch = GC_BATCH_MAX_GRAPHS;
+constexpr int64_t kMaxGrid = 32768;     // blocks of a batch launch (each walks many items)
 struct BatchDev {
     int32_t ng;
     int32_t pad[63];
@@ -218,29 +218,35 @@ struct Batch {
     const BatchDev *T;
 };
 
-__device__ inline bool locate(const Graph &in, int, Graph &s, int64_t &lb)
+// Runs f(graph, local block) for the blocks of a launch.  One graph: the
+// grid covers its blocks exactly.  A batch: the grid is capped and every
+// block walks the (graph, block) list with a stride of the grid size, with a
+// barrier between items so LDS can be reused.
+template <class F>
+__device__ inline void for_blocks(const Graph &s, int, F &&f)
 {
-    s = in;
-    lb = blockIdx.x;
-    return true;
+    f(s, (int64_t)blockIdx.x);
 }
 
-__device__ inline bool locate(const Batch &b, int which, Graph &s, int64_t &lb)
+template <class F>
+__device__ inline void for_blocks(const Batch &b, int which, F &&f)
 {
     const BatchDev *T = b.T;
     const int32_t *off = which ? T->tile_off : T->node_off;
     const int ng = T->ng;
-    const int bid = blockIdx.x;
-    if (ng <= 0 || bid >= off[ng]) return false;
-    int lo = 0, hi = ng - 1;                 // largest g with off[g] <= bid
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= bid) lo = mid;
-        else hi = mid - 1;
+    if (ng <= 0) return;
+    const int64_t total = off[ng];
+    for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        int lo = 0, hi = ng - 1;                 // largest g with off[g] <= vb
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= vb) lo = mid;
+            else hi = mid - 1;
+        }
+        const Graph s = T->graphs[lo];
+        f(s, vb - off[lo]);
+        __syncthreads();
     }
-    s = T->graphs[lo];
-    lb = bid - off[lo];
-    return true;
 }
 
 // Node counts stay below 2^29 (checked on the host), so 32-bit division is exact.
@@ -566,9 +572,7 @@ template <class Src>
 __global__ void __launch_bounds__(kBlock)
 k_push(Src src)
 {
-    Graph s;
-    int64_t lb;
-    if (!locate(src, 0, s, lb)) return;
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
     if (!s.bact[lb]) return;                  // no active node in this block
     int64_t n = lb * kBlock + threadIdx.x;
     int cnt = 0;
@@ -605,6 +609,7 @@ k_push(Src src)
     }
     cnt = block_sum(cnt);
     if (threadIdx.x == 0 && cnt) atomicAdd(&my_slot(s.slots, lb).pushes, (unsigned long long)cnt);
+    });
 }
 
 // Relabel sweep: merges the inflow of the push sweep, then lifts every
@@ -613,9 +618,7 @@ template <class Src>
 __global__ void __launch_bounds__(kBlock)
 k_relabel(Src src)
 {
-    Graph s;
-    int64_t lb;
-    if (!locate(src, 0, s, lb)) return;
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
     if (!s.bact[lb] && !s.binf[lb]) return;   // nothing arrived, nothing to lift
     int64_t n = lb * kBlock + threadIdx.x;
     bool active = false;
@@ -654,6 +657,7 @@ k_relabel(Src src)
         s.bact[lb] = any > 0;
         s.binf[lb] = 0;
     }
+    });
 }
 
 __device__ inline bool is_frozen(const Graph &s, int j, int y, int x)
@@ -669,9 +673,7 @@ template <class Src>
 __global__ void __launch_bounds__(kBlock)
 k_mask(Src src, int mode)
 {
-    Graph s;
-    int64_t lb;
-    if (!locate(src, 0, s, lb)) return;
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
     int64_t n = lb * kBlock + threadIdx.x;
     if (n >= s.N) return;
     int j, y, x;
@@ -684,6 +686,7 @@ k_mask(Src src, int mode)
         mk |= (r > 0 ? 1u : 0u) << d;
     }
     s.mask[n] = (uint16_t)mk;
+    });
 }
 
 // Seeds: mode 0 -> ht = 1 at deficit nodes, INF elsewhere;
@@ -692,9 +695,7 @@ template <class Src>
 __global__ void __launch_bounds__(kBlock)
 k_seed(Src src, int mode)
 {
-    Graph s;
-    int64_t lb;
-    if (!locate(src, 0, s, lb)) return;
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
     int64_t n = lb * kBlock + threadIdx.x;
     if (n >= s.N) return;
     int32_t e = s.ex[n];
@@ -705,6 +706,7 @@ k_seed(Src src, int mode)
     }
     if (mode == 0) s.ht[n] = e < 0 ? 1 : kInf;
     else s.aux[n] = e > 0 ? 0 : kInf;
+    });
 }
 
 // One tiled min-plus relaxation pass: val(u) = min(val(u), val(w) + step)
@@ -725,15 +727,6 @@ template <int TW, int TH, int TJ, class Src>
 __global__ void __launch_bounds__(kBlock)
 k_relax(Src src, int mode, int max_rounds, int pass)
 {
-    Graph s;
-    int64_t lb;
-    if (!locate(src, 1, s, lb)) return;
-    // mode 0: BFS distance to the deficits in ht; mode 1: reachability in aux
-    int32_t *__restrict__ val = mode == 0 ? s.ht : s.aux;
-    const int step = mode == 0 ? 1 : 0;
-    int32_t *flags = s.hdr->flags;
-    int32_t *__restrict__ stamps = s.stamps;
-    const int ntx = (s.W + TW - 1) / TW, nty = (s.H + TH - 1) / TH, ntz = (s.J + TJ - 1) / TJ;
     constexpr int HW = TW + 2, HH = TH + 2, HJ = TJ + 2;
     constexpr int NH = HW * HH * HJ, NI = TW * TH * TJ;
     static_assert(NI % kBlock == 0 && NI / kBlock <= 32, "tile must hold 1..32 nodes per thread");
@@ -742,13 +735,20 @@ k_relax(Src src, int mode, int max_rounds, int pass)
     __shared__ uint16_t smk[NI];
     __shared__ uint32_t dirty[2][kBlock];
     __shared__ int s_flag;
+    __shared__ int s_run, s_full;
+    for_blocks(src, 1, [&](const Graph &s, int64_t lb) {
+    // mode 0: BFS distance to the deficits in ht; mode 1: reachability in aux
+    int32_t *__restrict__ val = mode == 0 ? s.ht : s.aux;
+    const int step = mode == 0 ? 1 : 0;
+    int32_t *flags = s.hdr->flags;
+    int32_t *__restrict__ stamps = s.stamps;
+    const int ntx = (s.W + TW - 1) / TW, nty = (s.H + TH - 1) / TH, ntz = (s.J + TJ - 1) / TJ;
     const int tid = threadIdx.x;
     if (pass > 1 && flags[(pass - 1) % kMaxFlags] == 0) return;     // converged already
     const int tile = (int)lb;
     const int bx = tile % ntx, by = (tile / ntx) % nty, bz = tile / (ntx * nty);
     // Neighbouring tiles may rewrite their stamps during this pass, so one
     // thread decides for the whole block.
-    __shared__ int s_run, s_full;
     if (tid == 0) {
         int run = pass == 1, full_ = pass == 1;
         if (pass > 1) {
@@ -887,15 +887,14 @@ k_relax(Src src, int mode, int max_rounds, int pass)
             stamps[tile] = 0;
         }
     }
+    });
 }
 
 template <class Src>
 __global__ void __launch_bounds__(kBlock)
 k_count_active(Src src)
 {
-    Graph s;
-    int64_t lb;
-    if (!locate(src, 0, s, lb)) return;
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
     int64_t n = lb * kBlock + threadIdx.x;
     int a = 0;
     if (n < s.N) a = (s.ex[n] > 0 && s.ht[n] < kInf) ? 1 : 0;
@@ -905,6 +904,7 @@ k_count_active(Src src)
         s.bact[lb] = a > 0;                   // block flags of the sweeps that follow
         s.binf[lb] = 0;
     }
+    });
 }
 
 __global__ void k_zero_header(DevHeader *h, int what)
@@ -1797,10 +1797,12 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
     const int64_t nblk = h->node_off[ng], ntile = h->tile_off[ng];
     Batch B{b->dev};
     const Opts &o = b->opt;
+    const unsigned gnode = (unsigned)(nblk < kMaxGrid ? nblk : kMaxGrid);
+    const unsigned gtile = (unsigned)(ntile < kMaxGrid ? ntile : kMaxGrid);
 
     // exact global relabelling of every member
-    hipLaunchKernelGGL(k_mask<Batch>, dim3((unsigned)nblk), dim3(kBlock), 0, st, B, 0);
-    hipLaunchKernelGGL(k_seed<Batch>, dim3((unsigned)nblk), dim3(kBlock), 0, st, B, 0);
+    hipLaunchKernelGGL(k_mask<Batch>, dim3(gnode), dim3(kBlock), 0, st, B, 0);
+    hipLaunchKernelGGL(k_seed<Batch>, dim3(gnode), dim3(kBlock), 0, st, B, 0);
     RelaxFn<Batch> fn = relax_kernel<Batch>(o.tw, o.th, o.tj);
     std::vector<int32_t> gathered((size_t)ng * 16);
     std::vector<char> conv(ng, 0);
@@ -1808,8 +1810,7 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
     while (n_conv < ng) {
         hipLaunchKernelGGL(k_batch_zero, dim3(ng), dim3(kSlots), 0, st, b->dev, 0, passes + 1, batch);
         for (int q = 1; q <= batch; ++q)
-            hipLaunchKernelGGL(fn, dim3((unsigned)ntile), dim3(kBlock), 0, st, B, 0, o.local_iters,
-                               passes + q);
+            hipLaunchKernelGGL(fn, dim3(gtile), dim3(kBlock), 0, st, B, 0, o.local_iters, passes + q);
         hipLaunchKernelGGL(k_batch_gather, dim3(ng), dim3(kSlots), 0, st, b->dev, 0);
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
         if (!hip_ok(hipMemcpyAsync(gathered.data(), b->dev->gathered, gathered.size() * 4,
@@ -1829,7 +1830,7 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
     }
     // termination test
     hipLaunchKernelGGL(k_batch_zero, dim3(ng), dim3(kSlots), 0, st, b->dev, 1, 0, 0);
-    hipLaunchKernelGGL(k_count_active<Batch>, dim3((unsigned)nblk), dim3(kBlock), 0, st, B);
+    hipLaunchKernelGGL(k_count_active<Batch>, dim3(gnode), dim3(kBlock), 0, st, B);
     hipLaunchKernelGGL(k_batch_gather, dim3(ng), dim3(kSlots), 0, st, b->dev, 1);
     if (!hip_ok(hipGetLastError())) return GC_E_HIP;
     if (!hip_ok(hipMemcpyAsync(gathered.data(), b->dev->gathered, gathered.size() * 4,
@@ -1862,7 +1863,7 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
     const bool use_graph = st != nullptr && (o.flags & GC_OPT_BATCH_GRAPH) != 0;
     if (use_graph) {
         int64_t cap = 1;
-        while (cap < grid) cap <<= 1;                 // upper-bound grid: fewer captures
+        while (cap < grid && cap < kMaxGrid) cap <<= 1;   // upper-bound grid: fewer captures
         if (b->exec_blocks != cap || b->exec_stream != st) {
             batch_drop_graph(b);
             if (!hip_ok(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal))) return GC_E_HIP;
@@ -1874,7 +1875,7 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
         }
         if (!hip_ok(hipGraphLaunch(b->exec, st))) return GC_E_HIP;
     } else {
-        launch_sweeps(b, st, grid);
+        launch_sweeps(b, st, grid < kMaxGrid ? grid : kMaxGrid);
     }
     if (!hip_ok(hipGetLastError())) return GC_E_HIP;
     for (auto &m : b->mem) m.st.sweeps += o.period;

@@ -106,3 +106,28 @@ def test_batch_rounds_with_members_joining(torch_cuda, orc):
     for i, (p, cost, g, ref) in enumerate(built):
         _check(ref, _read(torch, g, cost, p))
     b.close()
+
+
+def test_batch_larger_than_one_launch_grid(torch_cuda):
+    """Two 450x375x64 graphs hold more node blocks than a batch launch has
+    workgroups, so every workgroup walks several (graph, block) items; the
+    cuts equal the single-graph solves."""
+    torch = torch_cuda
+    items = []
+    for seed in [(3, 0), (3, 1)]:
+        pr = sg.make_pair(sg.LARGE, seed)
+        p = gc.problem(sg.LARGE.w, sg.LARGE.h, sg.LARGE.m, sg.LARGE.cap, 1, 1023)
+        L = torch.from_numpy(pr.left).cuda()
+        R = torch.from_numpy(pr.right).cuda()
+        lab, cost, e, f, _ = gc.solve_pair(L, R, p)
+        ws = gc.alloc_workspace(p)
+        g = gc.graph_build(p, cost, ws)
+        items.append((p, cost, g, (lab.cpu().numpy(), f, e)))
+    assert sum(-(-sg.LARGE.w * sg.LARGE.h * (sg.LARGE.m - 1) // 256) for _ in items) > 32768
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        gc.maxflow_solve_batch([it[2] for it in items], gc.GcSolveOpts(flags=gc.GC_OPT_BATCH_GRAPH),
+                               stream=stream)
+        for p, cost, g, ref in items:
+            _check(ref, _read(torch, g, cost, p))
+    torch.cuda.synchronize()
