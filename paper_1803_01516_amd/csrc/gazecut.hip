@@ -201,10 +201,17 @@ __device__ inline Slot &my_slot(Slot *slots, int64_t lb) { return slots[lb & (kS
 
 // Kernel sources.  A solver kernel runs either on one graph (passed by value,
 // one block per 256 nodes or per tile) or on a batch: a device table of
-// graphs with prefix offsets of their blocks, where a block finds its graph
-// by binary search.
+// graphs with prefix offsets of their blocks.
 constexpr int kMaxBatch = GC_BATCH_MAX_GRAPHS;
-constexpr int64_t kMaxGrid = 32768;     // blocks of a batch launch (each walks many items)
+constexpr unsigned kGridX = 65535;      // x extent of a batch launch's 2-D grid
+
+// 2-D grid holding `blocks` workgroups (x fastest).
+inline dim3 batch_grid(int64_t blocks)
+{
+    if (blocks <= 0) blocks = 1;
+    if (blocks <= kGridX) return dim3((unsigned)blocks, 1, 1);
+    return dim3(kGridX, (unsigned)((blocks + kGridX - 1) / kGridX), 1);
+}
 struct BatchDev {
     int32_t ng;
     int32_t pad[63];
@@ -218,10 +225,10 @@ struct Batch {
     const BatchDev *T;
 };
 
-// Runs f(graph, local block) for the blocks of a launch.  One graph: the
-// grid covers its blocks exactly.  A batch: the grid is capped and every
-// block walks the (graph, block) list with a stride of the grid size, with a
-// barrier between items so LDS can be reused.
+// Runs f(graph, local block) for the block of a launch.  One graph: the
+// grid covers its blocks exactly.  A batch: the 2-D grid (x fastest) covers
+// the total of all member graphs' blocks; a block finds its graph by binary
+// search over the prefix offsets and blocks past the total exit.
 template <class F>
 __device__ inline void for_blocks(const Graph &s, int, F &&f)
 {
@@ -234,19 +241,15 @@ __device__ inline void for_blocks(const Batch &b, int which, F &&f)
     const BatchDev *T = b.T;
     const int32_t *off = which ? T->tile_off : T->node_off;
     const int ng = T->ng;
-    if (ng <= 0) return;
-    const int64_t total = off[ng];
-    for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
-        int lo = 0, hi = ng - 1;                 // largest g with off[g] <= vb
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (off[mid] <= vb) lo = mid;
-            else hi = mid - 1;
-        }
-        const Graph s = T->graphs[lo];
-        f(s, vb - off[lo]);
-        __syncthreads();
+    const int64_t vb = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (ng <= 0 || vb >= off[ng]) return;
+    int lo = 0, hi = ng - 1;                     // largest g with off[g] <= vb
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= vb) lo = mid;
+        else hi = mid - 1;
     }
+    f(T->graphs[lo], vb - off[lo]);
 }
 
 // Node counts stay below 2^29 (checked on the host), so 32-bit division is exact.
@@ -1712,12 +1715,13 @@ void batch_drop_graph(gc_batch *b)
     b->exec_blocks = -1;
 }
 
-void launch_sweeps(gc_batch *b, hipStream_t st, int64_t grid)
+void launch_sweeps(gc_batch *b, hipStream_t st, int64_t blocks)
 {
     Batch B{b->dev};
+    const dim3 grid = batch_grid(blocks);
     for (int i = 0; i < b->opt.period; ++i) {
-        hipLaunchKernelGGL(k_push<Batch>, dim3((unsigned)grid), dim3(kBlock), 0, st, B);
-        hipLaunchKernelGGL(k_relabel<Batch>, dim3((unsigned)grid), dim3(kBlock), 0, st, B);
+        hipLaunchKernelGGL(k_push<Batch>, grid, dim3(kBlock), 0, st, B);
+        hipLaunchKernelGGL(k_relabel<Batch>, grid, dim3(kBlock), 0, st, B);
     }
 }
 
@@ -1797,12 +1801,11 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
     const int64_t nblk = h->node_off[ng], ntile = h->tile_off[ng];
     Batch B{b->dev};
     const Opts &o = b->opt;
-    const unsigned gnode = (unsigned)(nblk < kMaxGrid ? nblk : kMaxGrid);
-    const unsigned gtile = (unsigned)(ntile < kMaxGrid ? ntile : kMaxGrid);
+    const dim3 gnode = batch_grid(nblk), gtile = batch_grid(ntile);
 
     // exact global relabelling of every member
-    hipLaunchKernelGGL(k_mask<Batch>, dim3(gnode), dim3(kBlock), 0, st, B, 0);
-    hipLaunchKernelGGL(k_seed<Batch>, dim3(gnode), dim3(kBlock), 0, st, B, 0);
+    hipLaunchKernelGGL(k_mask<Batch>, gnode, dim3(kBlock), 0, st, B, 0);
+    hipLaunchKernelGGL(k_seed<Batch>, gnode, dim3(kBlock), 0, st, B, 0);
     RelaxFn<Batch> fn = relax_kernel<Batch>(o.tw, o.th, o.tj);
     std::vector<int32_t> gathered((size_t)ng * 16);
     std::vector<char> conv(ng, 0);
@@ -1810,7 +1813,7 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
     while (n_conv < ng) {
         hipLaunchKernelGGL(k_batch_zero, dim3(ng), dim3(kSlots), 0, st, b->dev, 0, passes + 1, batch);
         for (int q = 1; q <= batch; ++q)
-            hipLaunchKernelGGL(fn, dim3(gtile), dim3(kBlock), 0, st, B, 0, o.local_iters, passes + q);
+            hipLaunchKernelGGL(fn, gtile, dim3(kBlock), 0, st, B, 0, o.local_iters, passes + q);
         hipLaunchKernelGGL(k_batch_gather, dim3(ng), dim3(kSlots), 0, st, b->dev, 0);
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
         if (!hip_ok(hipMemcpyAsync(gathered.data(), b->dev->gathered, gathered.size() * 4,
@@ -1830,7 +1833,7 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
     }
     // termination test
     hipLaunchKernelGGL(k_batch_zero, dim3(ng), dim3(kSlots), 0, st, b->dev, 1, 0, 0);
-    hipLaunchKernelGGL(k_count_active<Batch>, dim3(gnode), dim3(kBlock), 0, st, B);
+    hipLaunchKernelGGL(k_count_active<Batch>, gnode, dim3(kBlock), 0, st, B);
     hipLaunchKernelGGL(k_batch_gather, dim3(ng), dim3(kSlots), 0, st, b->dev, 1);
     if (!hip_ok(hipGetLastError())) return GC_E_HIP;
     if (!hip_ok(hipMemcpyAsync(gathered.data(), b->dev->gathered, gathered.size() * 4,
@@ -1863,7 +1866,7 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
     const bool use_graph = st != nullptr && (o.flags & GC_OPT_BATCH_GRAPH) != 0;
     if (use_graph) {
         int64_t cap = 1;
-        while (cap < grid && cap < kMaxGrid) cap <<= 1;   // upper-bound grid: fewer captures
+        while (cap < grid) cap <<= 1;                 // upper-bound grid: fewer captures
         if (b->exec_blocks != cap || b->exec_stream != st) {
             batch_drop_graph(b);
             if (!hip_ok(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal))) return GC_E_HIP;
@@ -1875,7 +1878,7 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
         }
         if (!hip_ok(hipGraphLaunch(b->exec, st))) return GC_E_HIP;
     } else {
-        launch_sweeps(b, st, grid < kMaxGrid ? grid : kMaxGrid);
+        launch_sweeps(b, st, grid);
     }
     if (!hip_ok(hipGetLastError())) return GC_E_HIP;
     for (auto &m : b->mem) m.st.sweeps += o.period;
