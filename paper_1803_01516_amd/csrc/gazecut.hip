@@ -221,14 +221,16 @@ struct BatchDev {
     Graph graphs[kMaxBatch];
     int32_t gathered[kMaxBatch][16];    // per-graph flags / counters read back by the host
 };
+// A launch over the members g0 .. g1-1 of a batch table.
 struct Batch {
     const BatchDev *T;
+    int g0, g1;
 };
 
 // Runs f(graph, local block) for the block of a launch.  One graph: the
 // grid covers its blocks exactly.  A batch: the 2-D grid (x fastest) covers
-// the total of all member graphs' blocks; a block finds its graph by binary
-// search over the prefix offsets and blocks past the total exit.
+// the total of the launch's member graphs' blocks; a block finds its graph by
+// binary search over the prefix offsets and blocks past the total exit.
 template <class F>
 __device__ inline void for_blocks(const Graph &s, int, F &&f)
 {
@@ -240,16 +242,20 @@ __device__ inline void for_blocks(const Batch &b, int which, F &&f)
 {
     const BatchDev *T = b.T;
     const int32_t *off = which ? T->tile_off : T->node_off;
-    const int ng = T->ng;
-    const int64_t vb = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    if (ng <= 0 || vb >= off[ng]) return;
-    int lo = 0, hi = ng - 1;                     // largest g with off[g] <= vb
+    if (b.g1 <= b.g0) return;
+    const int64_t vb = off[b.g0] + (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    if (vb >= off[b.g1]) return;
+    int lo = b.g0, hi = b.g1 - 1;                // largest g with off[g] <= vb
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (off[mid] <= vb) lo = mid;
         else hi = mid - 1;
     }
-    f(T->graphs[lo], vb - off[lo]);
+    // a private copy: through a reference into the table every field would be
+    // reloaded after each store the kernel makes (the compiler cannot rule
+    // out that the store aliases the table)
+    const Graph g = T->graphs[lo];
+    f(g, vb - off[lo]);
 }
 
 // Node counts stay below 2^29 (checked on the host), so 32-bit division is exact.
@@ -659,6 +665,100 @@ k_relabel(Src src)
     if (threadIdx.x == 0) {
         s.bact[lb] = any > 0;
         s.binf[lb] = 0;
+    }
+    });
+}
+
+// Fused sweep: one kernel per push-relabel step.  Every node of a block
+// that holds an active node or received inflow merges its inflow, relabels
+// to one above its lowest residual neighbour when no neighbour is lower, and
+// pushes along residual arcs to lower neighbours.  Neighbour heights are
+// read while they change; a stale height is never above the current one
+// (heights only grow between global relabels), and the two nodes of an arc
+// pair move flow in opposite directions, so with atomic updates of the pair
+// word every residual stays within [0, pair total] whatever the order.  The
+// labelling may lose validity between global relabels; only the exact global
+// relabel decides termination, so the final state is the same max preflow.
+template <class Src>
+__global__ void __launch_bounds__(kBlock)
+k_sweep(Src src)
+{
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
+    __shared__ int s_go;
+    if (threadIdx.x == 0) {
+        const bool inflow = s.binf[lb] != 0;
+        if (inflow) s.binf[lb] = 0;               // cleared before the inflow is merged
+        s_go = inflow || s.bact[lb];
+    }
+    __syncthreads();
+    if (!s_go) return;
+    const int64_t n = lb * kBlock + threadIdx.x;
+    bool active = false;
+    int cnt = 0;
+    if (n < s.N) {
+        int32_t e = s.ex[n];
+        const int32_t e0 = e;
+        if (s.ein[n] != 0) e += atomicExch(&s.ein[n], 0);
+        int32_t h = s.ht[n];
+        if (e > 0 && h < kInf) {
+            int j, y, x;
+            decode(s, n, j, y, x);
+            const unsigned ex_mask = arc_exists(s, j, y, x);
+            int32_t r[14], hv[14];
+#pragma unroll
+            for (int d = 0; d < 14; ++d) {
+                const bool ok = (ex_mask >> d) & 1u;
+                r[d] = ok ? res_from_word(s, d, *word_ptr(s, n, d)) : 0;
+                hv[d] = ok ? s.ht[nbr(s, n, d)] : kInf;
+            }
+            int32_t hmin = kInf;
+#pragma unroll
+            for (int d = 0; d < 14; ++d)
+                if (r[d] > 0) hmin = hv[d] < hmin ? hv[d] : hmin;
+            if (hmin >= h) {                       // no lower neighbour: relabel
+                h = hmin >= kInf ? kInf : hmin + 1;
+                s.ht[n] = h;
+            }
+#pragma unroll
+            for (int d = 0; d < 14; ++d) {
+                if (e > 0 && r[d] > 0 && hv[d] < h) {
+                    const int32_t delta = e < r[d] ? e : r[d];
+                    atomicAdd(word_ptr(s, n, d), word_is_forward(d) ? -delta : delta);
+                    const int64_t v = nbr(s, n, d);
+                    atomicAdd(&s.ein[v], delta);
+                    s.binf[v / kBlock] = 1;
+                    e -= delta;
+                    ++cnt;
+                }
+            }
+            active = e > 0 && h < kInf;
+        }
+        if (e != e0) s.ex[n] = e;
+    }
+    const int any = block_sum(active ? 1 : 0);
+    cnt = block_sum(cnt);
+    if (threadIdx.x == 0) {
+        s.bact[lb] = any > 0;
+        if (cnt) atomicAdd(&my_slot(s.slots, lb).pushes, (unsigned long long)cnt);
+    }
+    });
+}
+
+// Merges the inflow left by the last fused sweep into the excess.  Every
+// block is visited: a block's inflow flag is cleared and set by different
+// workgroups of one sweep without ordering, so it may read 0 while inflow is
+// pending.
+template <class Src>
+__global__ void __launch_bounds__(kBlock)
+k_merge(Src src)
+{
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
+    const int64_t n = lb * kBlock + threadIdx.x;
+    if (n >= s.N) return;
+    const int32_t in = s.ein[n];
+    if (in != 0) {
+        s.ex[n] += in;
+        s.ein[n] = 0;
     }
     });
 }
@@ -1078,23 +1178,45 @@ k_batch_gather(BatchDev *T, int what)
 // block (one delegate point's sites over the skin depth) cut on its own.
 // ---------------------------------------------------------------------------
 
-// Wave front: one pass down every column of the skin; each free node hands
-// the chain arc below it as much of its excess as the arc's residual allows.
+// Wave front (Sec. 4.4): one pass along every column, from the source end
+// towards the sink end over the free levels; each node hands the chain arc
+// towards the sink as much of its excess (its own plus what the pass brought
+// from below) as the arc's residual allows.  Heights are ignored, so a
+// global relabel must follow before any push sweep.  One thread per site;
+// the grid covers the sites with the node blocks of the source (a graph or a
+// batch), blocks past the plane exit.
+template <class Src>
 __global__ void __launch_bounds__(kBlock)
-k_wave(Graph s)
+k_wave(Src src)
 {
-    int64_t site = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (site >= s.plane) return;
-    const int lo = s.wlo[site], hi = s.whi[site];
-    for (int k = lo + 1; k < hi; ++k) {
-        const int64_t n = (int64_t)(k - 1) * s.plane + site;
-        const int32_t e = s.ex[n], r = s.rd[n];
-        const int32_t d = e < r ? e : r;
-        if (d <= 0) continue;
-        s.ex[n] = e - d;
-        s.ex[n + s.plane] += d;
-        s.rd[n] = r - d;
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
+    if (lb * kBlock >= s.plane) return;             // whole block past the plane
+    const int64_t site = lb * kBlock + threadIdx.x;
+    int cnt = 0;
+    if (site < s.plane) {
+        const int lo = s.win ? s.wlo[site] : 0, hi = s.win ? s.whi[site] : s.J;
+        int32_t carry = 0;
+        for (int k = lo + 1; k <= hi; ++k) {
+            const int64_t n = (int64_t)(k - 1) * s.plane + site;
+            const int32_t e0 = s.ex[n];
+            int32_t e = e0 + carry;
+            carry = 0;
+            if (k < hi && e > 0) {
+                const int32_t r = s.rd[n];
+                const int32_t d = e < r ? e : r;
+                if (d > 0) {
+                    s.rd[n] = r - d;
+                    e -= d;
+                    carry = d;
+                    ++cnt;
+                }
+            }
+            if (e != e0) s.ex[n] = e;
+        }
     }
+    cnt = block_sum(cnt);
+    if (threadIdx.x == 0 && cnt) atomicAdd(&my_slot(s.slots, lb).pushes, (unsigned long long)cnt);
+    });
 }
 
 constexpr int32_t kUpRes = 1 << 29;     // residual of an unbounded arc inside a block
@@ -1310,6 +1432,14 @@ RelaxFn<Src> relax_kernel(int tw, int th, int tj)
 int64_t relax_tiles(const Graph &s, const Opts &o)
 {
     return (int64_t)((s.W + o.tw - 1) / o.tw) * ((s.H + o.th - 1) / o.th) * ((s.J + o.tj - 1) / o.tj);
+}
+
+// The optional wave-front pass: before the first global relabel, or before
+// every one.
+inline bool wave_in_round(const Opts &o, int round)
+{
+    if (o.flags & GC_OPT_WAVE_ALL) return true;
+    return round == 0 && (o.flags & GC_OPT_WAVE_FIRST) != 0;
 }
 
 int check_opts(const Opts &o)
@@ -1589,8 +1719,11 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
     Launcher L{st, (opt.flags & GC_OPT_TIME_KERNELS) != 0, {}};
     const unsigned grid = grid_for(s.N);
     int status = GC_OK;
-    for (;;) {
-        // exact global relabelling: BFS distance to the deficit nodes
+    for (int round = 0;; ++round) {
+        // wave-front pass along the columns, then exact global relabelling:
+        // BFS distance to the deficit nodes
+        if (wave_in_round(opt, round))
+            L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_wave<Graph>, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s); });
         L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_mask<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 0); });
         L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_seed<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 0); });
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
@@ -1605,10 +1738,16 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
         if (active == 0) break;
         if (st_local.sweeps >= opt.max_sweeps) { status = GC_E_NOT_CONVERGED; break; }
         for (int i = 0; i < opt.period; ++i) {
-            L.run(GC_K_PUSH, [&] { hipLaunchKernelGGL(k_push<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
-            L.run(GC_K_RELABEL, [&] { hipLaunchKernelGGL(k_relabel<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
+            if (opt.flags & GC_OPT_FUSED_SWEEP) {
+                L.run(GC_K_PUSH, [&] { hipLaunchKernelGGL(k_sweep<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
+            } else {
+                L.run(GC_K_PUSH, [&] { hipLaunchKernelGGL(k_push<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
+                L.run(GC_K_RELABEL, [&] { hipLaunchKernelGGL(k_relabel<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
+            }
             st_local.sweeps++;
         }
+        if (opt.flags & GC_OPT_FUSED_SWEEP)
+            L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_merge<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
     }
     unsigned long long pushes = 0;
@@ -1641,7 +1780,7 @@ GC_API int approx_level2_cut(gc_graph *skin, const int32_t *cost, int32_t *label
     hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(64), 0, st, result, s.hdr);
     hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 2);
     if (s.N > 0) {
-        hipLaunchKernelGGL(k_wave, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s);
+        hipLaunchKernelGGL(k_wave<Graph>, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s);
         dim3 grid((unsigned)((s.W + b - 1) / b), (unsigned)((s.H + b - 1) / b), 1);
         hipLaunchKernelGGL(k_block_cut, grid, dim3(kBlockLanes), 0, st, s, b, 64 + 24 * b * b * b);
         hipLaunchKernelGGL(k_labels_closure, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
@@ -1679,7 +1818,7 @@ struct gc_batch {
     bool dirty = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    int64_t exec_blocks = -1;
+    std::vector<int64_t> exec_key;     // group bounds and grids the graph was captured for
     hipStream_t exec_stream = nullptr;
 };
 
@@ -1712,16 +1851,51 @@ void batch_drop_graph(gc_batch *b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
-    b->exec_blocks = -1;
+    b->exec_key.clear();
 }
 
-void launch_sweeps(gc_batch *b, hipStream_t st, int64_t blocks)
+// Sweeps touch 40 B per node (excess, height, inflow, seven pair words).  The
+// members are split into consecutive groups whose sweep state fits in this
+// many bytes, and each group runs its whole period of sweeps before the next
+// starts, so a group of small graphs keeps its state in the 256 MB Infinity
+// Cache instead of streaming every member from HBM on every sweep.  A
+// member larger than the budget forms a group of its own.
+constexpr size_t kSweepBytesPerNode = 40;
+constexpr size_t kSweepGroupBytes = size_t(192) << 20;
+
+void sweep_groups(const gc_batch *b, std::vector<int> &bounds)
 {
-    Batch B{b->dev};
-    const dim3 grid = batch_grid(blocks);
-    for (int i = 0; i < b->opt.period; ++i) {
-        hipLaunchKernelGGL(k_push<Batch>, grid, dim3(kBlock), 0, st, B);
-        hipLaunchKernelGGL(k_relabel<Batch>, grid, dim3(kBlock), 0, st, B);
+    const int ng = (int)b->mem.size();
+    bounds.assign(1, 0);
+    size_t acc = 0;
+    for (int g = 0; g < ng; ++g) {
+        const size_t by = (size_t)b->mem[g].s.N * kSweepBytesPerNode;
+        if (g > bounds.back() && acc + by > kSweepGroupBytes) {
+            bounds.push_back(g);
+            acc = 0;
+        }
+        acc += by;
+    }
+    bounds.push_back(ng);
+}
+
+// One period of sweeps, group after group; grids[k] workgroups for group k.
+void launch_sweeps(gc_batch *b, hipStream_t st, const std::vector<int> &bounds,
+                   const std::vector<int64_t> &grids)
+{
+    const bool fused = (b->opt.flags & GC_OPT_FUSED_SWEEP) != 0;
+    for (size_t k = 0; k + 1 < bounds.size(); ++k) {
+        const Batch B{b->dev, bounds[k], bounds[k + 1]};
+        const dim3 grid = batch_grid(grids[k]);
+        for (int i = 0; i < b->opt.period; ++i) {
+            if (fused) {
+                hipLaunchKernelGGL(k_sweep<Batch>, grid, dim3(kBlock), 0, st, B);
+            } else {
+                hipLaunchKernelGGL(k_push<Batch>, grid, dim3(kBlock), 0, st, B);
+                hipLaunchKernelGGL(k_relabel<Batch>, grid, dim3(kBlock), 0, st, B);
+            }
+        }
+        if (fused) hipLaunchKernelGGL(k_merge<Batch>, grid, dim3(kBlock), 0, st, B);
     }
 }
 
@@ -1799,11 +1973,24 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
     const int ng = (int)b->mem.size();
     const BatchDev *h = (const BatchDev *)b->host.data();
     const int64_t nblk = h->node_off[ng], ntile = h->tile_off[ng];
-    Batch B{b->dev};
+    const Batch B{b->dev, 0, ng};
     const Opts &o = b->opt;
     const dim3 gnode = batch_grid(nblk), gtile = batch_grid(ntile);
 
-    // exact global relabelling of every member
+    // wave-front pass for the members in their first round (or for all),
+    // then exact global relabelling of every member
+    for (int g0 = 0; g0 < ng;) {
+        int g1 = g0;
+        while (g1 < ng && wave_in_round(o, b->mem[g1].st.global_relabels)) ++g1;
+        if (g1 > g0) {
+            const Batch W{b->dev, g0, g1};
+            hipLaunchKernelGGL(k_wave<Batch>, batch_grid(h->node_off[g1] - h->node_off[g0]),
+                               dim3(kBlock), 0, st, W);
+            g0 = g1;
+        } else {
+            ++g0;
+        }
+    }
     hipLaunchKernelGGL(k_mask<Batch>, gnode, dim3(kBlock), 0, st, B, 0);
     hipLaunchKernelGGL(k_seed<Batch>, gnode, dim3(kBlock), 0, st, B, 0);
     RelaxFn<Batch> fn = relax_kernel<Batch>(o.tw, o.th, o.tj);
@@ -1860,25 +2047,37 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
     }
     b->mem.swap(keep);
     if (b->mem.empty()) return GC_OK;
-    // push-relabel sweeps of the members still running
+    // push-relabel sweeps of the members still running, group by group
     if ((rc = batch_upload(b, st)) != GC_OK) return rc;
-    const int64_t grid = ((const BatchDev *)b->host.data())->node_off[b->mem.size()];
+    const BatchDev *hk = (const BatchDev *)b->host.data();
+    std::vector<int> bounds;
+    sweep_groups(b, bounds);
+    std::vector<int64_t> grids(bounds.size() - 1);
+    for (size_t k = 0; k + 1 < bounds.size(); ++k)
+        grids[k] = hk->node_off[bounds[k + 1]] - hk->node_off[bounds[k]];
     const bool use_graph = st != nullptr && (o.flags & GC_OPT_BATCH_GRAPH) != 0;
     if (use_graph) {
-        int64_t cap = 1;
-        while (cap < grid) cap <<= 1;                 // upper-bound grid: fewer captures
-        if (b->exec_blocks != cap || b->exec_stream != st) {
+        std::vector<int64_t> key;
+        for (size_t k = 0; k + 1 < bounds.size(); ++k) {
+            int64_t cap = 1;
+            while (cap < grids[k]) cap <<= 1;         // upper-bound grids: fewer captures
+            grids[k] = cap;
+            key.push_back(bounds[k]);
+            key.push_back(cap);
+        }
+        key.push_back(bounds.back());
+        if (b->exec_key != key || b->exec_stream != st) {
             batch_drop_graph(b);
             if (!hip_ok(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal))) return GC_E_HIP;
-            launch_sweeps(b, st, cap);
+            launch_sweeps(b, st, bounds, grids);
             if (!hip_ok(hipStreamEndCapture(st, &b->graph))) return GC_E_HIP;
             if (!hip_ok(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0))) return GC_E_HIP;
-            b->exec_blocks = cap;
+            b->exec_key = key;
             b->exec_stream = st;
         }
         if (!hip_ok(hipGraphLaunch(b->exec, st))) return GC_E_HIP;
     } else {
-        launch_sweeps(b, st, grid);
+        launch_sweeps(b, st, bounds, grids);
     }
     if (!hip_ok(hipGetLastError())) return GC_E_HIP;
     for (auto &m : b->mem) m.st.sweeps += o.period;
