@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=60, help="requests of the serving stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run 5 plain 256 MiB device copies (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -121,8 +123,9 @@ def bench_batch(args, gc, sg, torch):
                                "p50_ms": _pct(t_one, 50), "p99_ms": _pct(t_one, 99)},
             "speedup": round(tot_one / tot_bat, 3),
             "autotuned": {"tile": [best.tile_w, best.tile_h, best.tile_j],
-                          "relabel_period": best.relabel_period, "tuning_s": round(tune_s, 2),
-                          "candidates": len(trials)},
+                          "relabel_period": best.relabel_period,
+                          "fused_sweep": bool(best.flags & gc.GC_OPT_FUSED_SWEEP),
+                          "tuning_s": round(tune_s, 2), "candidates": len(trials)},
             "identical_results": same}
 
 
@@ -270,6 +273,18 @@ def main():
                                "eq2_error_mean": round(float(np.mean(errs)), 1),
                                "pct_exact_mean": round(float(np.mean(pcts)), 1)}
 
+    calib = None
+    if args.copy_calibration:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
+        # calibrates the counters that give the solve kernels' HBM traffic
+        src = torch.ones(64 << 20, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        calib = {"copy_bytes": src.numel() * 4, "copies": 5}
+        del src, dst
+
     batch = bench_batch(args, gc, sg, torch) if args.batch_pairs > 0 else None
     serving = bench_serving(args, gc, sg, torch) if args.serve_requests > 0 else None
 
@@ -327,6 +342,7 @@ def main():
         "energy_last": int(r[0]), "flow_last": int(r[1]),
         "eq2_error_last": err, "pct_exact_last": pct,
         "approx": approx or None,
+        "copy_calibration": calib,
         "batch": batch,
         "serving": serving,
         "roofline": roof,

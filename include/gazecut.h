@@ -104,13 +104,11 @@ typedef struct {
  * round from a captured hipGraph (needs a non-null stream). */
 #define GC_OPT_BATCH_GRAPH 2
 
-/* gc_solve_opts.flags: the wave-front pass of Sec. 4.4 (each column hands its
- * excess along the data chain towards the sink as far as the chain's
- * residuals allow, in one pass per column).  WAVE_FIRST runs it before the
- * first global relabel, WAVE_ALL before every global relabel; by default it
- * does not run.  Labels, energy and flow do not depend on the choice. */
+/* gc_solve_opts.flags: run the wave-front pass of Sec. 4.4 once before the
+ * first global relabel (each column hands its excess along the data chain
+ * towards the sink as far as the chain's residuals allow, in one pass per
+ * column).  Off by default.  Labels, energy and flow do not depend on it. */
 #define GC_OPT_WAVE_FIRST 4
-#define GC_OPT_WAVE_ALL 8
 
 /* gc_solve_opts.flags: one fused push-relabel kernel per sweep instead of a
  * push kernel and a relabel kernel (same final result). */

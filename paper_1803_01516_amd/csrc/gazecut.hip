@@ -736,6 +736,7 @@ k_sweep(Src src)
         if (e != e0) s.ex[n] = e;
     }
     const int any = block_sum(active ? 1 : 0);
+    __syncthreads();
     cnt = block_sum(cnt);
     if (threadIdx.x == 0) {
         s.bact[lb] = any > 0;
@@ -1103,7 +1104,9 @@ __global__ void __launch_bounds__(kSlots)
 k_zero_slots(Slot *slots, int what)
 {
     Slot &sl = slots[threadIdx.x];
-    if (what == 0) { sl.pushes = 0; sl.active = 0; sl.e0 = 0; sl.e1 = 0; sl.tcap = 0; sl.c0 = 0; }
+    if (what == 0) {
+        sl.pushes = 0; sl.active = 0; sl.e0 = 0; sl.e1 = 0; sl.tcap = 0; sl.c0 = 0;
+    }
     else if (what == 1) sl.active = 0;
     else { sl.e0 = 0; sl.e1 = 0; }
 }
@@ -1434,11 +1437,10 @@ int64_t relax_tiles(const Graph &s, const Opts &o)
     return (int64_t)((s.W + o.tw - 1) / o.tw) * ((s.H + o.th - 1) / o.th) * ((s.J + o.tj - 1) / o.tj);
 }
 
-// The optional wave-front pass: before the first global relabel, or before
-// every one.
+// The optional wave-front pass runs once, before the first global relabel
+// (heights are all zero then, so ignoring them loses nothing).
 inline bool wave_in_round(const Opts &o, int round)
 {
-    if (o.flags & GC_OPT_WAVE_ALL) return true;
     return round == 0 && (o.flags & GC_OPT_WAVE_FIRST) != 0;
 }
 
@@ -1718,6 +1720,7 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
     }
     Launcher L{st, (opt.flags & GC_OPT_TIME_KERNELS) != 0, {}};
     const unsigned grid = grid_for(s.N);
+    const bool fused = (opt.flags & GC_OPT_FUSED_SWEEP) != 0;
     int status = GC_OK;
     for (int round = 0;; ++round) {
         // wave-front pass along the columns, then exact global relabelling:
@@ -1738,7 +1741,7 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
         if (active == 0) break;
         if (st_local.sweeps >= opt.max_sweeps) { status = GC_E_NOT_CONVERGED; break; }
         for (int i = 0; i < opt.period; ++i) {
-            if (opt.flags & GC_OPT_FUSED_SWEEP) {
+            if (fused) {
                 L.run(GC_K_PUSH, [&] { hipLaunchKernelGGL(k_sweep<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
             } else {
                 L.run(GC_K_PUSH, [&] { hipLaunchKernelGGL(k_push<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
@@ -1746,7 +1749,7 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
             }
             st_local.sweeps++;
         }
-        if (opt.flags & GC_OPT_FUSED_SWEEP)
+        if (fused)
             L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_merge<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
     }

@@ -38,7 +38,6 @@ class GcSolveOpts(ctypes.Structure):
 GC_OPT_TIME_KERNELS = 1
 GC_OPT_BATCH_GRAPH = 2
 GC_OPT_WAVE_FIRST = 4
-GC_OPT_WAVE_ALL = 8
 GC_OPT_FUSED_SWEEP = 16
 GC_BATCH_MAX_GRAPHS = 256
 KERNEL_CLASSES = ("push", "relabel", "relax", "other")

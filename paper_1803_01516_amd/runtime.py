@@ -81,31 +81,34 @@ def release(item: Item):
 
 TILE_CANDIDATES = ((8, 8, 16), (16, 8, 16), (8, 8, 32), (16, 16, 8))
 PERIOD_CANDIDATES = (32, 64, 128)
+SWEEP_CANDIDATES = (0, gc.GC_OPT_FUSED_SWEEP)      # push + relabel kernels, or the fused one
 
 
-def autotune(items, tiles=TILE_CANDIDATES, periods=PERIOD_CANDIDATES, stream=None,
-             use_graph=False):
-    """Times one batched solve of `items` per (tile, period) candidate and
-    returns (best options, [(tile, period, seconds)]).  The items' graphs are
-    rebuilt in place before every trial, so the trials solve the same graphs."""
+def autotune(items, tiles=TILE_CANDIDATES, periods=PERIOD_CANDIDATES, sweeps=SWEEP_CANDIDATES,
+             stream=None, use_graph=False):
+    """Times one batched solve of `items` per (tile, period, sweep kind)
+    candidate and returns (best options, [(tile, period, sweep flags,
+    seconds)]).  The items' graphs are rebuilt in place before every trial,
+    so the trials solve the same graphs."""
     import torch
-    flags = gc.GC_OPT_BATCH_GRAPH if use_graph else 0
+    base = gc.GC_OPT_BATCH_GRAPH if use_graph else 0
     table = torch.empty(gc.batch_footprint_bytes(), dtype=torch.uint8, device="cuda")
     trials = []
     for tile in tiles:
         for period in periods:
-            opts = gc.GcSolveOpts(relabel_period=period, tile_w=tile[0], tile_h=tile[1],
-                                  tile_j=tile[2], flags=flags)
-            for it in items:
-                prepare(it, stream)
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            gc.maxflow_solve_batch([it.graph for it in items], opts, stream, table)
-            torch.cuda.synchronize()
-            trials.append((tile, period, time.perf_counter() - t))
-    tile, period, _ = min(trials, key=lambda r: r[2])
+            for sw in sweeps:
+                opts = gc.GcSolveOpts(relabel_period=period, tile_w=tile[0], tile_h=tile[1],
+                                      tile_j=tile[2], flags=base | sw)
+                for it in items:
+                    prepare(it, stream)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                gc.maxflow_solve_batch([it.graph for it in items], opts, stream, table)
+                torch.cuda.synchronize()
+                trials.append((tile, period, sw, time.perf_counter() - t))
+    tile, period, sw, _ = min(trials, key=lambda r: r[3])
     best = gc.GcSolveOpts(relabel_period=period, tile_w=tile[0], tile_h=tile[1], tile_j=tile[2],
-                          flags=flags)
+                          flags=base | sw)
     return best, trials
 
 

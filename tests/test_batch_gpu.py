@@ -109,9 +109,10 @@ def test_batch_rounds_with_members_joining(torch_cuda, orc):
 
 
 def test_batch_larger_than_one_launch_grid(torch_cuda):
-    """Two 450x375x64 graphs hold more node blocks than a batch launch has
-    workgroups, so every workgroup walks several (graph, block) items; the
-    cuts equal the single-graph solves."""
+    """Two 450x375x64 graphs hold more node blocks than one grid row has
+    workgroups (65535), so the launch grid gets a second dimension, and each
+    graph's sweep state exceeds the cache-sized group budget, so the sweeps
+    run in two groups; the cuts equal the single-graph solves."""
     torch = torch_cuda
     items = []
     for seed in [(3, 0), (3, 1)]:
@@ -123,11 +124,41 @@ def test_batch_larger_than_one_launch_grid(torch_cuda):
         ws = gc.alloc_workspace(p)
         g = gc.graph_build(p, cost, ws)
         items.append((p, cost, g, (lab.cpu().numpy(), f, e)))
-    assert sum(-(-sg.LARGE.w * sg.LARGE.h * (sg.LARGE.m - 1) // 256) for _ in items) > 32768
+    assert sum(-(-sg.LARGE.w * sg.LARGE.h * (sg.LARGE.m - 1) // 256) for _ in items) > 65535
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         gc.maxflow_solve_batch([it[2] for it in items], gc.GcSolveOpts(flags=gc.GC_OPT_BATCH_GRAPH),
                                stream=stream)
         for p, cost, g, ref in items:
+            _check(ref, _read(torch, g, cost, p))
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("flags", [0, gc.GC_OPT_FUSED_SWEEP, gc.GC_OPT_FUSED_SWEEP | gc.GC_OPT_BATCH_GRAPH,
+                                   gc.GC_OPT_WAVE_FIRST | gc.GC_OPT_BATCH_GRAPH],
+                         ids=["plain", "fused", "fused-graph", "wave-graph"])
+def test_batch_groups_and_variants(torch_cuda, orc, flags):
+    """Four 384x288x16 graphs (66 MB of sweep state each) split into two
+    sweep groups, mixed with small graphs; every solver variant gives the
+    single-graph cut (itself checked against the oracle for the small ones)."""
+    torch = torch_cuda
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        built = []
+        for seed in [(2, 0), (2, 1), (2, 2), (2, 3)]:
+            pr = sg.make_pair(sg.MID, seed)
+            p = gc.problem(sg.MID.w, sg.MID.h, sg.MID.m, sg.MID.cap, 1, 1023)
+            L = torch.from_numpy(pr.left).cuda()
+            R = torch.from_numpy(pr.right).cuda()
+            lab, cost, e, f, _ = gc.solve_pair(L, R, p, None, stream)
+            ws = gc.alloc_workspace(p)
+            g = gc.graph_build(p, cost, ws, stream)
+            built.append((p, cost, g, (lab.cpu().numpy(), f, e)))
+        for c in _cases(orc)[:4]:
+            built.append(_build(torch, orc, *c))
+        torch.cuda.synchronize()                 # _build works on the default stream
+        gc.maxflow_solve_batch([b[2] for b in built], gc.GcSolveOpts(relabel_period=32, flags=flags),
+                               stream=stream)
+        for p, cost, g, ref in built:
             _check(ref, _read(torch, g, cost, p))
     torch.cuda.synchronize()

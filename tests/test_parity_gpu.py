@@ -168,6 +168,45 @@ def test_repeat_solves_identical(torch_cuda, orc):
     _check_against_oracle(orc, cost_np, outs[0][0], outs[0][1], outs[0][2], (1, 1023, 1, 1023))
 
 
+_VARIANTS = {"wave-first": gc.GC_OPT_WAVE_FIRST, "fused": gc.GC_OPT_FUSED_SWEEP,
+             "fused-wave-first": gc.GC_OPT_FUSED_SWEEP | gc.GC_OPT_WAVE_FIRST}
+
+
+def _variant_cases():
+    rng = np.random.default_rng(78)
+    yield "ties-33x17x6", rng.integers(0, 2, (6, 17, 33)).astype(np.int32), (1, 1, 1, 1)
+    yield "random-soft-50x21x11", rng.integers(0, 31, (11, 21, 50)).astype(np.int32), (3, 4, 2, 5)
+    yield "m2-20x9", rng.integers(0, 31, (2, 9, 20)).astype(np.int32), (1, 1023, 1, 1023)
+    import oracle
+    for name, spec, seed in [("ragged-70x33x9", sg.spec_like(sg.MID, 70, 33, 9), (9, 8)),
+                             ("slanted-128x96x16", sg.spec_like(sg.MID, 128, 96, 16), (5, 5))]:
+        pr = sg.make_pair(spec, seed)
+        yield name, oracle.cost_volume(pr.left, pr.right, spec.m, spec.cap), (1, 1023, 1, 1023)
+
+
+@pytest.mark.parametrize("variant", list(_VARIANTS))
+@pytest.mark.parametrize("name,cost,params", list(_variant_cases()), ids=[c[0] for c in _variant_cases()])
+def test_solver_variants_parity(torch_cuda, orc, variant, name, cost, params):
+    """The wave-front pass and the fused sweep change the schedule only: the
+    canonical cut, energy and flow stay those of the oracle."""
+    for period in (1, 13, 64):
+        o = gc.GcSolveOpts(relabel_period=period, flags=_VARIANTS[variant])
+        lab, energy, flow, st = _solve_cost_gpu(torch_cuda, cost, *params, opts=o)
+        _check_against_oracle(orc, cost, lab, energy, flow, params)
+        assert st.active_last == 0
+
+
+@pytest.mark.parametrize("variant", ["fused", "fused-wave-first"])
+def test_solver_variants_mid_full_size(torch_cuda, orc, variant):
+    pr = sg.make_pair(sg.MID, (2, 1))
+    p = gc.problem(sg.MID.w, sg.MID.h, sg.MID.m, sg.MID.cap, 1, 1023)
+    L = torch_cuda.from_numpy(pr.left).cuda()
+    R = torch_cuda.from_numpy(pr.right).cuda()
+    o = gc.GcSolveOpts(flags=_VARIANTS[variant])
+    labels, cost, energy, flow, st = gc.solve_pair(L, R, p, o)
+    _check_against_oracle(orc, cost.cpu().numpy(), labels.cpu().numpy(), energy, flow, (1, 1023, 1, 1023))
+
+
 # ---------------------------------------------------------------------------
 # Hierarchical approximation, level 1 (Sec. 4.5)
 # ---------------------------------------------------------------------------
