@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=60, help="requests of the serving stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-low-rate", type=float, default=2.0,
+                    help="second stream below the GPU's capacity (0: skip)")
+    ap.add_argument("--serve-low-requests", type=int, default=24)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 5 plain 256 MiB device copies (reference for HBM counters)")
     return ap.parse_args()
@@ -72,6 +75,38 @@ def algorithmic_bytes(kind: str, nodes: int, active_mean: float) -> float:
     return 0.0
 
 
+PROFILES = os.path.join(ROOT, "profiles")
+HIP_SOURCE = os.path.join(ROOT, "paper_1803_01516_amd", "csrc", "gazecut.hip")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the ratio
+    the same counter shows on a plain device copy of known size), or None when
+    no summary covers the kernel or the HIP source has changed since the
+    counters were taken (the summary records the source's SHA-1)."""
+    import hashlib
+    path = os.path.join(PROFILES, f"{kernel}_384x288x16_traffic.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic-record: "):
+                rec = json.loads(line[len("traffic-record: "):])
+    if not rec or rec.get("kernel") != kernel:
+        return None
+    with open(HIP_SOURCE, "rb") as f:
+        if hashlib.sha1(f.read()).hexdigest() != rec.get("source_sha1"):
+            return None
+    return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+
+
+def _log(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def _pct(xs, q):
     return round(float(np.percentile(np.array(xs) * 1e3, q)), 2)
 
@@ -95,10 +130,12 @@ def bench_batch(args, gc, sg, torch):
         t = time.perf_counter()
         best, trials = rt.autotune(tune, stream=stream, use_graph=True)
         tune_s = time.perf_counter() - t
+        _log(f"batch: autotuned over {len(trials)} candidates in {tune_s:.1f} s")
         for it in tune:
             rt.release(it)
         one = [rt.make_item(i, spec, pair) for i, (spec, pair) in enumerate(mix)]
         t_one, tot_one = rt.run_one_per_launch(one, None, stream)
+        _log(f"batch: one pair per launch {tot_one:.2f} s")
         ref = [(it.energy, it.flow, it.labels.cpu()) for it in one]
         for it in one:
             rt.release(it)
@@ -106,6 +143,7 @@ def bench_batch(args, gc, sg, torch):
         torch.cuda.empty_cache()
         bat = [rt.make_item(i, spec, pair) for i, (spec, pair) in enumerate(mix)]
         t_bat, tot_bat = rt.run_batched(bat, best, stream)
+        _log(f"batch: batched {tot_bat:.2f} s")
         same = all(it.energy == r[0] and it.flow == r[1] and bool((it.labels.cpu() == r[2]).all())
                    for it, r in zip(bat, ref))
         nodes = sum(it.p.width * it.p.height * (it.p.labels - 1) for it in bat)
@@ -124,31 +162,37 @@ def bench_batch(args, gc, sg, torch):
             "speedup": round(tot_one / tot_bat, 3),
             "autotuned": {"tile": [best.tile_w, best.tile_h, best.tile_j],
                           "relabel_period": best.relabel_period,
-                          "fused_sweep": bool(best.flags & gc.GC_OPT_FUSED_SWEEP),
+                          "sweep": ("fused" if best.flags & gc.GC_OPT_FUSED_SWEEP else
+                                    "split" if best.flags & gc.GC_OPT_SPLIT_SWEEP else "by depth"),
                           "tuning_s": round(tune_s, 2), "candidates": len(trials)},
             "identical_results": same}
 
 
-def bench_serving(args, gc, sg, torch):
+def bench_serving(args, gc, sg, torch, rate, n_req):
     """Poisson request stream over 384x288x16, 640x480x64 and 1280x720x128
     pairs, served by continuous batching with admission by workspace
-    footprint.  Latency = completion - arrival."""
+    footprint, one batch engine (lane) per footprint class on its own stream.
+    Latency = completion - arrival."""
     from paper_1803_01516_amd import runtime as rt
-    stream = torch.cuda.Stream()
     pools = {s: [(sg.spec_like(sg.MID, *s), sg.make_pair(sg.spec_like(sg.MID, *s), (5, k, i)))
                  for i in range(2)] for k, s in enumerate(sg.SERVE_SHAPES)}
-    reqs = rt.poisson_requests(args.serve_requests, args.serve_rate, sg.SERVE_SHAPES, 2, seed=5)
-    opts = gc.GcSolveOpts(flags=gc.GC_OPT_BATCH_GRAPH)
-    with torch.cuda.stream(stream):
-        done, wall, srv = rt.serve(reqs, pools, int(args.serve_budget_gb * 1e9), opts, stream)
+    reqs = rt.poisson_requests(n_req, rate, sg.SERVE_SHAPES, 2, seed=5)
+    opts = gc.GcSolveOpts(flags=gc.GC_OPT_SWEEP_GRAPH)
+    _log(f"serving: {len(reqs)} requests at {rate:g}/s")
+    done, wall, srv = rt.serve(reqs, pools, int(args.serve_budget_gb * 1e9), opts)
+    _log(f"serving: done in {wall:.1f} s")
     torch.cuda.empty_cache()
-    out = {"workload": f"{len(reqs)} Poisson requests at {args.serve_rate:g}/s, uniform over "
+    out = {"workload": f"{len(reqs)} Poisson requests at {rate:g}/s, uniform over "
                        "384x288x16, 640x480x64, 1280x720x128",
            "completed": len(done), "wall_s": round(wall, 3),
            "pairs_per_s": round(len(done) / wall, 2), "rounds": srv.rounds,
+           "lanes": [{"max_mb": None if l.limit is None else l.limit >> 20, "max_graphs": l.max_members,
+                      "rounds": l.rounds} for l in srv.lanes],
            "peak_members": srv.peak_members, "peak_gb": round(srv.peak_used / 1e9, 2),
            "budget_gb": args.serve_budget_gb}
     out.update(rt.latency_summary(done))
+    out["by_shape"] = {"x".join(map(str, s)): rt.latency_summary([r for r in done if r.shape == s])
+                       for s in sg.SERVE_SHAPES}
     return out
 
 
@@ -193,6 +237,7 @@ def main():
         gc.extract_labels(g, cost, labels, result, stream)
         return st
 
+    _log(f"{args.pairs} pairs resident; {args.warmup} warm-up steps")
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -209,6 +254,7 @@ def main():
     t1 = time.perf_counter()
 
     elapsed = t1 - t0
+    _log(f"{args.steps} timed steps: {1e3 * elapsed / args.steps:.3f} ms/step")
     pushes = sum(s["pushes"] for s in stats)
     ms_per_step = 1e3 * elapsed / args.steps
     lat_ms = np.array(lat) * 1e3
@@ -229,9 +275,13 @@ def main():
         per_launch_ms = tot[kind] / max(1, launches[kind])
         bytes_launch = algorithmic_bytes(kind, nodes, active_mean)
         achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
+        kname = {"relax": "k_relax", "push": "k_push", "relabel": "k_relabel"}[kind]
+        traffic = measured_traffic(kname)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": {"relax": "k_relax", "push": "k_push", "relabel": "k_relabel"}[kind],
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(traffic),
+                "traffic_over_algorithmic": None if traffic is None else round(traffic / bytes_launch, 3),
+                "kernel": kname,
                 "avg_launch_us": round(per_launch_ms * 1e3, 2),
                 "launches_per_step": round(launches[kind] / args.steps, 1),
                 "bytes_per_launch": int(bytes_launch),
@@ -266,6 +316,7 @@ def main():
                     er, pc = sg.eq2_error(pairs[k].gt, lab_a.cpu().numpy())
                     errs.append(er)
                     pcts.append(pc)
+            _log(f"approx {variant}: {1e3 * float(np.median(lat_a)):.3f} ms/pair")
             approx[variant] = {"ms_per_pair": round(1e3 * float(np.median(lat_a)), 3),
                                "energy_gap_mean": round(float(np.mean(gaps)), 1),
                                "energy_gap_rel": round(float(np.mean(gaps)) / float(np.mean(
@@ -286,7 +337,12 @@ def main():
         del src, dst
 
     batch = bench_batch(args, gc, sg, torch) if args.batch_pairs > 0 else None
-    serving = bench_serving(args, gc, sg, torch) if args.serve_requests > 0 else None
+    serving = serving_low = None
+    if args.serve_requests > 0:
+        serving = bench_serving(args, gc, sg, torch, args.serve_rate, args.serve_requests)
+        if args.serve_low_rate > 0:
+            serving_low = bench_serving(args, gc, sg, torch, args.serve_low_rate,
+                                        args.serve_low_requests)
 
     cpu = None
     parity = None
@@ -309,6 +365,7 @@ def main():
             rr = result.cpu().numpy()
             ok = ok and int(rr[0]) == energy and int(rr[1]) == flow and \
                 bool((labels.cpu().numpy() == lab).all())
+        _log(f"cpu oracle: {n} pairs in {t:.1f} s")
         cpu = {"value": round(n / t, 4), "unit": "pairs/s", "cores": 1, "kind": "oracle",
                "sample": f"{n} pairs of the same 384x288x16 workload (seeds (2,0..{n - 1})), "
                          f"cost volume + graph + FIFO push-relabel max-flow + labels, "
@@ -345,6 +402,7 @@ def main():
         "copy_calibration": calib,
         "batch": batch,
         "serving": serving,
+        "serving_below_capacity": serving_low,
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,

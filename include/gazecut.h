@@ -95,14 +95,18 @@ typedef struct {
     int32_t reserved;
 } gc_solve_opts;
 
-/* gc_solve_opts.flags: bracket every kernel launch of the solve with a pair
- * of hipEvents on the solve stream and report summed device time per kernel
- * class in gc_solve_stats (adds a few microseconds per launch). */
+/* gc_solve_opts.flags: bracket every 8th launch of each kernel class with a
+ * pair of hipEvents on the solve stream; gc_solve_stats then holds every
+ * class's launch count and its device time estimated as the mean of the timed
+ * launches times that count (timing every launch would slow the host enough
+ * to leave the GPU idle between short sweeps). */
 #define GC_OPT_TIME_KERNELS 1
 
-/* gc_solve_opts.flags, batched solves: replay the push-relabel sweeps of a
- * round from a captured hipGraph (needs a non-null stream). */
-#define GC_OPT_BATCH_GRAPH 2
+/* gc_solve_opts.flags: replay the push-relabel sweeps of a relabel period
+ * from a captured hipGraph (needs a non-null stream; ignored with
+ * GC_OPT_TIME_KERNELS).  maxflow_solve keeps the last few captures per host
+ * thread, keyed by the graph's workspace, shape and the sweep options. */
+#define GC_OPT_SWEEP_GRAPH 2
 
 /* gc_solve_opts.flags: run the wave-front pass of Sec. 4.4 once before the
  * first global relabel (each column hands its excess along the data chain
@@ -110,9 +114,13 @@ typedef struct {
  * column).  Off by default.  Labels, energy and flow do not depend on it. */
 #define GC_OPT_WAVE_FIRST 4
 
-/* gc_solve_opts.flags: one fused push-relabel kernel per sweep instead of a
- * push kernel and a relabel kernel (same final result). */
+/* gc_solve_opts.flags: the sweep kernels.  FUSED_SWEEP runs one fused
+ * push-relabel kernel per sweep, SPLIT_SWEEP a push kernel and a relabel
+ * kernel; by default graphs with at least 32 depth layers (33 labels) get the
+ * fused kernel and shallower ones the split pair (a batch decides per sweep
+ * group, by its shallowest member).  The final result does not depend on it. */
 #define GC_OPT_FUSED_SWEEP 16
+#define GC_OPT_SPLIT_SWEEP 64
 
 /* Kernel classes of gc_solve_stats.kernel_ms / kernel_launches. */
 #define GC_K_PUSH 0           /* push sweep                                   */
@@ -129,7 +137,7 @@ typedef struct {
     int32_t bfs_passes;       /* tiled relaxation passes (all BFS work)       */
     int32_t active_last;      /* active nodes at the last check (0 when done) */
     int32_t kernel_launches[GC_K_CLASSES];  /* with GC_OPT_TIME_KERNELS only */
-    double kernel_ms[GC_K_CLASSES];         /* summed event time per class   */
+    double kernel_ms[GC_K_CLASSES];         /* estimated device time per class */
 } gc_solve_stats;
 
 /* Largest number of graphs one batch holds at a time. */
@@ -279,7 +287,7 @@ typedef struct gc_batch gc_batch;
 size_t gc_batch_footprint_bytes(void);
 
 /* Creates a batch over the caller's DEVICE table buffer; `o` fixes the
- * relabel period, relaxation tile and GC_OPT_BATCH_GRAPH for all members.
+ * relabel period, relaxation tile and GC_OPT_SWEEP_GRAPH for all members.
  * Errors: GC_E_ARG, GC_E_WORKSPACE. */
 int gc_batch_create(void *dev_table, size_t dev_bytes, const gc_solve_opts *o, gc_batch **out);
 

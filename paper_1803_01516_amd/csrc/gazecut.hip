@@ -33,6 +33,7 @@
 // LDS-tiled relaxations: each workgroup iterates its site x layer tile to a
 // local fixpoint, and passes repeat until no tile changes.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -141,6 +142,7 @@ Graph view(const gc_graph *g)
 {
     const gc_problem &p = g->p;
     Graph s;
+    memset(&s, 0, sizeof(s));                  // padding too: views are compared bytewise
     s.W = p.width; s.H = p.height; s.J = p.labels - 1;
     s.plane = (int64_t)s.W * s.H;
     s.N = s.plane * s.J;
@@ -1437,6 +1439,20 @@ int64_t relax_tiles(const Graph &s, const Opts &o)
     return (int64_t)((s.W + o.tw - 1) / o.tw) * ((s.H + o.th - 1) / o.th) * ((s.J + o.tj - 1) / o.tj);
 }
 
+// Sweep kind: forced by the flags, else the fused kernel for graphs with at
+// least kFusedMinLayers depth layers.  Measured on MI355X: with 63 layers
+// (450x375 and 640x480, 64 depth numbers) the fused sweep solves 10-20 %
+// faster; with 15 layers it needs more sweeps and global relabels and is
+// 10-15 % slower.
+constexpr int kFusedMinLayers = 32;
+
+inline bool sweep_fused(const Opts &o, int layers)
+{
+    if (o.flags & GC_OPT_FUSED_SWEEP) return true;
+    if (o.flags & GC_OPT_SPLIT_SWEEP) return false;
+    return layers >= kFusedMinLayers;
+}
+
 // The optional wave-front pass runs once, before the first global relabel
 // (heights are all zero then, so ignoring them loses nothing).
 inline bool wave_in_round(const Opts &o, int round)
@@ -1454,10 +1470,19 @@ int check_opts(const Opts &o)
 // the solve stream, summed per kernel class once the stream has drained.
 thread_local std::vector<hipEvent_t> t_events;
 
+// Every kTimeEvery-th launch of a class is timed (events on every launch slow
+// the host enough to leave the GPU idle between short sweeps); the class
+// total is the sampled mean times the launch count.  A timed launch carries
+// its start and stop events in its own dispatch (hipExtLaunchKernelGGL), so
+// the interval is the kernel's execution, as a profiler reports it, not the
+// kernel plus the queue's event packets.
+constexpr int kTimeEvery = 8;
+
 struct Launcher {
     hipStream_t st;
     bool timing;
     std::vector<int> cls;
+    int launched[GC_K_CLASSES] = {};
 
     hipEvent_t event(size_t i)
     {
@@ -1469,66 +1494,172 @@ struct Launcher {
         return t_events[i];
     }
 
-    template <typename F>
-    void run(int klass, F &&launch)
+    template <typename K, typename... Args>
+    void run(int klass, K kernel, dim3 grid, Args... args)
     {
-        if (!timing) { launch(); return; }
-        hipEvent_t a = event(2 * cls.size()), b = event(2 * cls.size() + 1);
-        if (!a || !b) { launch(); return; }
-        (void)hipEventRecord(a, st);
-        launch();
-        (void)hipEventRecord(b, st);
+        hipEvent_t a = nullptr, b = nullptr;
+        if (timing && launched[klass]++ % kTimeEvery == 0) {
+            a = event(2 * cls.size());
+            b = event(2 * cls.size() + 1);
+        }
+        if (!a || !b) {
+            hipLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, st, args...);
+            return;
+        }
+        hipExtLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, st, a, b, 0, args...);
         cls.push_back(klass);
     }
 
     // Call after the stream has been synchronised.
     void collect(gc_solve_stats *out)
     {
+        double ms_sum[GC_K_CLASSES] = {};
+        int timed[GC_K_CLASSES] = {};
         for (size_t i = 0; i < cls.size(); ++i) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, t_events[2 * i], t_events[2 * i + 1]) == hipSuccess) {
-                out->kernel_ms[cls[i]] += ms;
-                out->kernel_launches[cls[i]]++;
+                ms_sum[cls[i]] += ms;
+                timed[cls[i]]++;
             }
         }
+        for (int c = 0; c < GC_K_CLASSES; ++c) {
+            if (!timed[c]) continue;
+            out->kernel_launches[c] += launched[c];
+            out->kernel_ms[c] += ms_sum[c] / timed[c] * launched[c];
+        }
         cls.clear();
+        for (int &n : launched) n = 0;
     }
 };
 
+// The leading part of DevHeader the host reads back after a batch of
+// relaxation passes: the pass flags, the active count and the push count.
+struct HeaderRead {
+    int32_t flags[kMaxFlags];
+    int32_t active;
+    int32_t prefix_err;
+    int32_t pad[14];
+    unsigned long long pushes;
+};
+static_assert(sizeof(HeaderRead) == offsetof(DevHeader, tcap), "header prefix layout");
+
+// Pinned landing buffer for the read-backs, one per host thread (a pageable
+// destination would add a staging copy to every read-back).
+HeaderRead *header_buffer()
+{
+    thread_local HeaderRead *buf = nullptr;
+    thread_local HeaderRead fallback;
+    thread_local bool tried = false;
+    if (!tried) {
+        tried = true;
+        if (hipHostMalloc((void **)&buf, sizeof(HeaderRead), hipHostMallocDefault) != hipSuccess)
+            buf = nullptr;
+    }
+    return buf ? buf : &fallback;
+}
+
 // Runs relaxation passes until a pass changes nothing.  Passes are issued in
-// growing batches with one flag read-back per batch; a pass that follows a
-// pass without change returns at once, so over-issuing is cheap.
-int relax_to_fixpoint(const Graph &s, int mode, const Opts &o, Launcher &L, int *passes_out)
+// growing batches (4, 8, then 15: fewer than the flag ring holds, so a batch
+// never clears the flag of the pass before it) with one read-back per batch;
+// a pass that follows a pass without change returns at once, so over-issuing
+// is cheap.  With `count_active` every batch is followed by the termination
+// count of the sweeps (active nodes, block flags) and the push total, read
+// back with the flags: the values of the batch that reached the fixpoint are
+// the final ones, so the termination test costs no read-back of its own.
+int relax_to_fixpoint(const Graph &s, int mode, const Opts &o, Launcher &L, int *passes_out,
+                      bool count_active = false, HeaderRead *out = nullptr)
 {
     const int64_t tiles = relax_tiles(s, o);
     RelaxFn<Graph> fn = relax_kernel<Graph>(o.tw, o.th, o.tj);
     if (!fn) return GC_E_ARG;
-    if (tiles <= 0) return GC_OK;
+    if (tiles <= 0 && !count_active) return GC_OK;
     const int max_passes = 1 << 22;
-    int passes = 0, batch = 2;
+    const unsigned grid = grid_for(s.N);
+    HeaderRead *h = header_buffer();
+    int passes = 0, batch = 4;
     for (;;) {
         hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, L.st, s.hdr, passes + 1, batch);
-        for (int b = 1; b <= batch; ++b)
-            L.run(GC_K_RELAX, [&] {
-                hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(kBlock), 0, L.st, s, mode,
-                                   o.local_iters, passes + b);
-            });
+        for (int b = 1; b <= batch && tiles > 0; ++b)
+            L.run(GC_K_RELAX, fn, dim3((unsigned)tiles), s, mode, o.local_iters, passes + b);
+        if (count_active) {
+            hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, L.st, s.slots, 1);
+            L.run(GC_K_OTHER, k_count_active<Graph>, dim3(grid), s);
+            hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, L.st, s.slots, s.hdr, 0, nullptr);
+            hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, L.st, s.slots, s.hdr, 1, nullptr);
+        }
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
-        int32_t flags[kMaxFlags];
-        if (!hip_ok(hipMemcpyAsync(flags, s.hdr->flags, sizeof(flags), hipMemcpyDeviceToHost, L.st)))
-            return GC_E_HIP;
+        const size_t bytes = count_active ? sizeof(HeaderRead) : sizeof(h->flags);
+        if (!hip_ok(hipMemcpyAsync(h, s.hdr, bytes, hipMemcpyDeviceToHost, L.st))) return GC_E_HIP;
         if (!hip_ok(hipStreamSynchronize(L.st))) return GC_E_HIP;
-        bool done = false;
-        for (int b = 1; b <= batch; ++b) {
+        bool done = tiles <= 0;
+        for (int b = 1; b <= batch && !done; ++b) {
             ++passes;
-            if (!flags[passes % kMaxFlags]) { done = true; break; }
+            if (!h->flags[passes % kMaxFlags]) done = true;
         }
         if (done) break;
         if (passes >= max_passes) return GC_E_NOT_CONVERGED;
-        batch = batch * 2 > 8 ? 8 : batch * 2;
+        batch = batch >= 8 ? kMaxFlags - 1 : batch * 2;
     }
+    if (out) *out = *h;
     *passes_out += passes;
     return GC_OK;
+}
+
+// Captured sweep periods of single-graph solves, a few per host thread,
+// keyed by the graph view (workspace addresses, shape, pair totals) and the
+// sweep options; the least recently used capture is dropped first.
+struct SweepCapture {
+    Graph key;
+    int period = 0;
+    bool fused = false;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long used = 0;
+};
+constexpr int kSweepCaptures = 8;
+
+void launch_period(const Graph &s, int period, bool fused, hipStream_t st)
+{
+    const unsigned grid = grid_for(s.N);
+    for (int i = 0; i < period; ++i) {
+        if (fused) {
+            hipLaunchKernelGGL(k_sweep<Graph>, dim3(grid), dim3(kBlock), 0, st, s);
+        } else {
+            hipLaunchKernelGGL(k_push<Graph>, dim3(grid), dim3(kBlock), 0, st, s);
+            hipLaunchKernelGGL(k_relabel<Graph>, dim3(grid), dim3(kBlock), 0, st, s);
+        }
+    }
+    if (fused) hipLaunchKernelGGL(k_merge<Graph>, dim3(grid), dim3(kBlock), 0, st, s);
+}
+
+int replay_period(const Graph &s, int period, bool fused, hipStream_t st)
+{
+    thread_local SweepCapture cache[kSweepCaptures];
+    thread_local unsigned long long tick = 0;
+    SweepCapture *hit = nullptr, *victim = &cache[0];
+    for (SweepCapture &c : cache) {
+        if (c.exec && c.period == period && c.fused == fused && !memcmp(&c.key, &s, sizeof(Graph))) {
+            hit = &c;
+            break;
+        }
+        if (!c.exec || c.used < victim->used) victim = &c;
+    }
+    if (!hit) {
+        if (victim->exec) (void)hipGraphExecDestroy(victim->exec);
+        victim->exec = nullptr;
+        hipGraph_t g = nullptr;
+        if (!hip_ok(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal))) return GC_E_HIP;
+        launch_period(s, period, fused, st);
+        if (!hip_ok(hipStreamEndCapture(st, &g))) return GC_E_HIP;
+        const bool ok = hip_ok(hipGraphInstantiate(&victim->exec, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        if (!ok) { victim->exec = nullptr; return GC_E_HIP; }
+        victim->key = s;
+        victim->period = period;
+        victim->fused = fused;
+        hit = victim;
+    }
+    hit->used = ++tick;
+    return hip_ok(hipGraphLaunch(hit->exec, st)) ? GC_OK : GC_E_HIP;
 }
 
 int read_i32(const int32_t *dev, int32_t *host, hipStream_t st)
@@ -1720,45 +1851,44 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
     }
     Launcher L{st, (opt.flags & GC_OPT_TIME_KERNELS) != 0, {}};
     const unsigned grid = grid_for(s.N);
-    const bool fused = (opt.flags & GC_OPT_FUSED_SWEEP) != 0;
+    const bool fused = sweep_fused(opt, s.J);
+    const bool use_graph = st != nullptr && (opt.flags & GC_OPT_SWEEP_GRAPH) != 0 && !L.timing;
     int status = GC_OK;
     for (int round = 0;; ++round) {
         // wave-front pass along the columns, then exact global relabelling:
         // BFS distance to the deficit nodes
         if (wave_in_round(opt, round))
-            L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_wave<Graph>, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s); });
-        L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_mask<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 0); });
-        L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_seed<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 0); });
+            L.run(GC_K_OTHER, k_wave<Graph>, dim3(grid_for(s.plane)), s);
+        L.run(GC_K_OTHER, k_mask<Graph>, dim3(grid), s, 0);
+        L.run(GC_K_OTHER, k_seed<Graph>, dim3(grid), s, 0);
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
-        if ((rc = relax_to_fixpoint(s, 0, opt, L, &st_local.bfs_passes)) != GC_OK) return rc;
+        // termination count and push total come back with the last flags
+        HeaderRead hr;
+        if ((rc = relax_to_fixpoint(s, 0, opt, L, &st_local.bfs_passes, true, &hr)) != GC_OK) return rc;
         st_local.global_relabels++;
-        hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 1);
-        L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_count_active<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
-        hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, s.slots, s.hdr, 0, nullptr);
-        int32_t active = 0;
-        if ((rc = read_i32(&s.hdr->active, &active, st)) != GC_OK) return rc;
-        st_local.active_last = active;
-        if (active == 0) break;
+        st_local.active_last = hr.active;
+        st_local.pushes = (int64_t)hr.pushes;
+        if (hr.active == 0) break;
         if (st_local.sweeps >= opt.max_sweeps) { status = GC_E_NOT_CONVERGED; break; }
-        for (int i = 0; i < opt.period; ++i) {
-            if (fused) {
-                L.run(GC_K_PUSH, [&] { hipLaunchKernelGGL(k_sweep<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
-            } else {
-                L.run(GC_K_PUSH, [&] { hipLaunchKernelGGL(k_push<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
-                L.run(GC_K_RELABEL, [&] { hipLaunchKernelGGL(k_relabel<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
+        if (use_graph) {
+            if ((rc = replay_period(s, opt.period, fused, st)) != GC_OK) return rc;
+            st_local.sweeps += opt.period;
+        } else {
+            for (int i = 0; i < opt.period; ++i) {
+                if (fused) {
+                    L.run(GC_K_PUSH, k_sweep<Graph>, dim3(grid), s);
+                } else {
+                    L.run(GC_K_PUSH, k_push<Graph>, dim3(grid), s);
+                    L.run(GC_K_RELABEL, k_relabel<Graph>, dim3(grid), s);
+                }
+                st_local.sweeps++;
             }
-            st_local.sweeps++;
+            if (fused)
+                L.run(GC_K_OTHER, k_merge<Graph>, dim3(grid), s);
         }
-        if (fused)
-            L.run(GC_K_OTHER, [&] { hipLaunchKernelGGL(k_merge<Graph>, dim3(grid), dim3(kBlock), 0, st, s); });
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
     }
-    unsigned long long pushes = 0;
-    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, s.slots, s.hdr, 1, nullptr);
-    if (!hip_ok(hipMemcpyAsync(&pushes, &s.hdr->pushes, sizeof(pushes), hipMemcpyDeviceToHost, st)))
-        return GC_E_HIP;
-    if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
-    st_local.pushes = (int64_t)pushes;
+    // the last read-back synchronised the stream
     L.collect(&st_local);
     if (stats) *stats = st_local;
     return status;
@@ -1882,12 +2012,20 @@ void sweep_groups(const gc_batch *b, std::vector<int> &bounds)
     bounds.push_back(ng);
 }
 
+// Sweep kind of a group: by the flags, else by its shallowest member.
+bool group_fused(const gc_batch *b, int g0, int g1)
+{
+    int layers = 1 << 30;
+    for (int g = g0; g < g1; ++g) layers = b->mem[g].s.J < layers ? b->mem[g].s.J : layers;
+    return sweep_fused(b->opt, layers);
+}
+
 // One period of sweeps, group after group; grids[k] workgroups for group k.
 void launch_sweeps(gc_batch *b, hipStream_t st, const std::vector<int> &bounds,
                    const std::vector<int64_t> &grids)
 {
-    const bool fused = (b->opt.flags & GC_OPT_FUSED_SWEEP) != 0;
     for (size_t k = 0; k + 1 < bounds.size(); ++k) {
+        const bool fused = group_fused(b, bounds[k], bounds[k + 1]);
         const Batch B{b->dev, bounds[k], bounds[k + 1]};
         const dim3 grid = batch_grid(grids[k]);
         for (int i = 0; i < b->opt.period; ++i) {
@@ -1999,7 +2137,7 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
     RelaxFn<Batch> fn = relax_kernel<Batch>(o.tw, o.th, o.tj);
     std::vector<int32_t> gathered((size_t)ng * 16);
     std::vector<char> conv(ng, 0);
-    int passes = 0, batch = 2, n_conv = 0;
+    int passes = 0, batch = 4, n_conv = 0;
     while (n_conv < ng) {
         hipLaunchKernelGGL(k_batch_zero, dim3(ng), dim3(kSlots), 0, st, b->dev, 0, passes + 1, batch);
         for (int q = 1; q <= batch; ++q)
@@ -2019,7 +2157,7 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
         }
         passes += batch;
         if (passes >= (1 << 22)) return GC_E_NOT_CONVERGED;
-        batch = batch * 2 > 8 ? 8 : batch * 2;
+        batch = batch >= 8 ? kMaxFlags - 1 : batch * 2;      // as in relax_to_fixpoint
     }
     // termination test
     hipLaunchKernelGGL(k_batch_zero, dim3(ng), dim3(kSlots), 0, st, b->dev, 1, 0, 0);
@@ -2058,7 +2196,7 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
     std::vector<int64_t> grids(bounds.size() - 1);
     for (size_t k = 0; k + 1 < bounds.size(); ++k)
         grids[k] = hk->node_off[bounds[k + 1]] - hk->node_off[bounds[k]];
-    const bool use_graph = st != nullptr && (o.flags & GC_OPT_BATCH_GRAPH) != 0;
+    const bool use_graph = st != nullptr && (o.flags & GC_OPT_SWEEP_GRAPH) != 0;
     if (use_graph) {
         std::vector<int64_t> key;
         for (size_t k = 0; k + 1 < bounds.size(); ++k) {
@@ -2067,6 +2205,7 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
             grids[k] = cap;
             key.push_back(bounds[k]);
             key.push_back(cap);
+            key.push_back(group_fused(b, bounds[k], bounds[k + 1]));
         }
         key.push_back(bounds.back());
         if (b->exec_key != key || b->exec_stream != st) {

@@ -36,9 +36,10 @@ class GcSolveOpts(ctypes.Structure):
 
 
 GC_OPT_TIME_KERNELS = 1
-GC_OPT_BATCH_GRAPH = 2
+GC_OPT_SWEEP_GRAPH = 2
 GC_OPT_WAVE_FIRST = 4
 GC_OPT_FUSED_SWEEP = 16
+GC_OPT_SPLIT_SWEEP = 64
 GC_BATCH_MAX_GRAPHS = 256
 KERNEL_CLASSES = ("push", "relabel", "relax", "other")
 

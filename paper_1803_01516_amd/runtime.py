@@ -8,6 +8,7 @@ PyTorch provides device memory and streams.
 """
 from __future__ import annotations
 
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -45,8 +46,12 @@ class Item:
 
 
 def make_item(tag, spec: sg.SceneSpec, pair: sg.Pair, lam=1, device="cuda") -> Item:
+    """An item whose images are copied to `device` now; with device=None they
+    stay on the host until prepare() copies them on its stream."""
     import torch
     p = gc.problem(spec.w, spec.h, spec.m, spec.cap, lam, spec.inhibit)
+    if device is None:
+        return Item(tag, spec, pair.left, pair.right, p)
     return Item(tag, spec, torch.from_numpy(pair.left).to(device),
                 torch.from_numpy(pair.right).to(device), p)
 
@@ -54,6 +59,9 @@ def make_item(tag, spec: sg.SceneSpec, pair: sg.Pair, lam=1, device="cuda") -> I
 def prepare(item: Item, stream=None):
     """Allocates device buffers, computes the cost volume and builds the graph."""
     import torch
+    if isinstance(item.left, np.ndarray):
+        item.left = torch.from_numpy(item.left).cuda()
+        item.right = torch.from_numpy(item.right).cuda()
     dev = item.left.device
     p = item.p
     if item.cost is None:
@@ -81,7 +89,7 @@ def release(item: Item):
 
 TILE_CANDIDATES = ((8, 8, 16), (16, 8, 16), (8, 8, 32), (16, 16, 8))
 PERIOD_CANDIDATES = (32, 64, 128)
-SWEEP_CANDIDATES = (0, gc.GC_OPT_FUSED_SWEEP)      # push + relabel kernels, or the fused one
+SWEEP_CANDIDATES = (0, gc.GC_OPT_FUSED_SWEEP, gc.GC_OPT_SPLIT_SWEEP)   # by depth, fused, split
 
 
 def autotune(items, tiles=TILE_CANDIDATES, periods=PERIOD_CANDIDATES, sweeps=SWEEP_CANDIDATES,
@@ -91,7 +99,7 @@ def autotune(items, tiles=TILE_CANDIDATES, periods=PERIOD_CANDIDATES, sweeps=SWE
     seconds)]).  The items' graphs are rebuilt in place before every trial,
     so the trials solve the same graphs."""
     import torch
-    base = gc.GC_OPT_BATCH_GRAPH if use_graph else 0
+    base = gc.GC_OPT_SWEEP_GRAPH if use_graph else 0
     table = torch.empty(gc.batch_footprint_bytes(), dtype=torch.uint8, device="cuda")
     trials = []
     for tile in tiles:
@@ -203,99 +211,210 @@ def poisson_requests(n, rate, shapes=sg.SERVE_SHAPES, pool_per_shape=2, seed=5):
             for i in range(n)]
 
 
+# Requests go to a lane by footprint: each lane is a batch engine on its own
+# stream driven by its own host thread, so a small request does not wait for
+# the rounds of a 1280x720x128 graph; the lanes' kernels share the GPU.  A
+# lane is (footprint upper bound or None, most graphs in its batch): graphs
+# that fill the GPU on their own gain nothing from sharing rounds, so the
+# last lane takes one at a time.
+DEFAULT_LANES = ((512 << 20, gc.GC_BATCH_MAX_GRAPHS), (2 << 30, 16), (None, 1))
+
+
+class Lane:
+    def __init__(self, server, index, limit, max_members, opts, device):
+        import torch
+        self.server = server
+        self.index = index
+        self.limit = limit
+        self.max_members = max(1, min(int(max_members), gc.GC_BATCH_MAX_GRAPHS))
+        self.opts = opts
+        dev = torch.device(device)
+        self.device = dev.index if dev.index is not None else torch.cuda.current_device()
+        self.stream = torch.cuda.Stream(self.device)
+        self.batch = gc.Batch.on_device(opts, f"cuda:{self.device}")
+        self.cv = threading.Condition()
+        self.inbox = []
+        self.live = {}
+        self.rounds = 0
+        self.closing = False
+        self.error = None
+        self.thread = threading.Thread(target=self._run, name=f"lane{index}", daemon=True)
+        self.thread.start()
+
+    def accepts(self, footprint):
+        return self.limit is None or footprint <= self.limit
+
+    def submit(self, req):
+        with self.cv:
+            self.inbox.append(req)
+            self.cv.notify()
+
+    def pending(self):
+        """Requests submitted to this lane and not finished."""
+        with self.cv:
+            return len(self.inbox) + len(self.live)
+
+    def close(self):
+        with self.cv:
+            self.closing = True
+            self.cv.notify()
+        self.thread.join()
+        self.batch.close()
+
+    def _run(self):
+        import torch
+        try:
+            torch.cuda.set_device(self.device)
+            with torch.cuda.stream(self.stream):
+                while True:
+                    with self.cv:
+                        while not self.inbox and not self.live and not self.closing:
+                            self.cv.wait()
+                        if self.closing and not self.inbox and not self.live:
+                            return
+                        new, self.inbox = self.inbox, []
+                    for req in new:
+                        prepare(req.item, self.stream)
+                        self.batch.add(req.item.graph, req.rid)
+                        with self.cv:
+                            self.live[req.rid] = req
+                    self.server._members()
+                    for tag, st in self.batch.round(self.stream):
+                        with self.cv:
+                            req = self.live.pop(tag)
+                        finish(req.item, self.stream)
+                        req.item.stats = st.as_dict()
+                        if self.server.keep_labels:
+                            req.item.labels = req.item.labels.cpu().numpy()
+                        else:
+                            req.item.labels = None
+                        req.t_done = self.server.clock()
+                        release(req.item)
+                        self.server._complete(req)
+                    self.rounds += 1
+        except Exception as e:                         # reported by the serving thread
+            self.error = e
+            self.server._complete(None)
+
+
 class Server:
     """Continuous batching over the native batch engine.
 
     Requests are admitted in arrival order while the bytes of live graph
-    workspaces and cost volumes stay within `budget_bytes` and the batch has
-    room; an admitted request's cost volume and graph are built on the
-    serving stream and the graph joins the running batch at the next round,
-    so its work overlaps with the requests already on the GPU.  Finished
-    graphs leave the batch, their labels are read and their memory is freed.
+    workspaces and cost volumes stay within `budget_bytes` (the head of the
+    line waits for memory) and go to the first lane whose footprint bound
+    holds them.  A lane builds an admitted request's cost volume and graph on
+    its stream and adds the graph to its running batch at the next round, so
+    its work overlaps with the requests already on the GPU; finished graphs
+    leave the batch, their labels are read and their memory is freed.
     """
 
-    def __init__(self, budget_bytes, opts=None, stream=None, lam=1, device="cuda"):
+    def __init__(self, budget_bytes, opts=None, lanes=DEFAULT_LANES, device="cuda", keep_labels=False):
+        import time as _time
         self.budget = int(budget_bytes)
-        self.opts = opts
-        self.stream = stream
-        self.lam = lam
-        self.device = device
-        self.batch = gc.Batch.on_device(opts, device)
+        self.keep_labels = keep_labels
+        self.lock = threading.Condition()
         self.used = 0
-        self.live = {}
-        self.rounds = 0
         self.peak_used = 0
         self.peak_members = 0
+        self.done = []
+        self.t0 = _time.perf_counter()
+        self.lanes = [Lane(self, i, lim, mx, opts, device) for i, (lim, mx) in enumerate(lanes)]
+
+    def clock(self):
+        return time.perf_counter() - self.t0
+
+    @property
+    def rounds(self):
+        return sum(l.rounds for l in self.lanes)
+
+    def lane_for(self, item: Item) -> Lane:
+        for lane in self.lanes:
+            if lane.accepts(item.footprint):
+                return lane
+        raise ValueError(f"no lane takes {item.footprint} B")
 
     def fits(self, item: Item) -> bool:
-        return self.used + item.footprint <= self.budget and len(self.batch) < gc.GC_BATCH_MAX_GRAPHS
+        lane = self.lane_for(item)
+        with self.lock:
+            return (self.used + item.footprint <= self.budget
+                    and lane.pending() < lane.max_members)
 
     def admit(self, req: Request, item: Item, now: float):
-        prepare(item, self.stream)
-        self.batch.add(item.graph, req.rid)
-        self.used += item.footprint
-        self.peak_used = max(self.peak_used, self.used)
-        self.live[req.rid] = req
+        lane = self.lane_for(item)
+        with self.lock:
+            self.used += item.footprint
+            self.peak_used = max(self.peak_used, self.used)
         req.item = item
         req.t_admit = now
-        self.peak_members = max(self.peak_members, len(self.batch))
+        lane.submit(req)
 
-    def step(self, clock):
-        """One batch round; returns the requests that completed."""
-        out = []
-        for tag, st in self.batch.round(self.stream):
-            req = self.live.pop(tag)
-            finish(req.item, self.stream)
-            req.item.stats = st.as_dict()
-            req.t_done = clock()
-            self.used -= req.item.footprint
-            release(req.item)
-            out.append(req)
-        self.rounds += 1
-        return out
+    def _members(self):
+        n = sum(l.pending() for l in self.lanes)
+        with self.lock:
+            self.peak_members = max(self.peak_members, n)
+
+    def _complete(self, req):
+        with self.lock:
+            if req is not None:
+                self.used -= req.item.footprint
+                self.done.append(req)
+            self.lock.notify_all()
+
+    def wait(self, timeout):
+        with self.lock:
+            self.lock.wait(timeout)
+
+    def check(self):
+        for lane in self.lanes:
+            if lane.error is not None:
+                raise lane.error
+
+    def close(self):
+        for lane in self.lanes:
+            lane.close()
 
 
-def serve(requests, pools, budget_bytes, opts=None, stream=None, lam=1, keep_labels=False,
+def serve(requests, pools, budget_bytes, opts=None, lanes=DEFAULT_LANES, lam=1, keep_labels=False,
           max_wall_s=None):
     """Runs the request stream in real time.  `pools[shape][i]` is the
     (spec, pair) a request names.  Returns (completed requests, wall seconds,
-    server).  With keep_labels the label tensors are copied to the host."""
+    server).  With keep_labels the labels are kept as host arrays."""
     import torch
-    srv = Server(budget_bytes, opts, stream, lam)
+    srv = Server(budget_bytes, opts, lanes, keep_labels=keep_labels)
     queue = list(requests)
     qi = 0
-    done = []
-    t0 = time.perf_counter()
-
-    def clock():
-        return time.perf_counter() - t0
-
-    while len(done) < len(queue):
-        now = clock()
-        if max_wall_s is not None and now > max_wall_s:
-            break
-        while qi < len(queue) and queue[qi].arrival <= now:
-            req = queue[qi]
-            spec, pair = pools[req.shape][req.pool_index]
-            item = make_item(req.rid, spec, pair, lam)
-            if item.footprint > budget_bytes:
-                raise ValueError(f"request {req.rid} needs {item.footprint} B, budget {budget_bytes}")
-            if not srv.fits(item):
-                break                               # head of line waits for memory
-            srv.admit(req, item, now)
-            qi += 1
-        if len(srv.batch) == 0:
+    srv.t0 = time.perf_counter()
+    try:
+        while True:
+            srv.check()
+            with srv.lock:
+                n_done = len(srv.done)
+            if n_done == len(queue):
+                break
+            now = srv.clock()
+            if max_wall_s is not None and now > max_wall_s:
+                break
+            while qi < len(queue) and queue[qi].arrival <= now:
+                req = queue[qi]
+                spec, pair = pools[req.shape][req.pool_index]
+                item = make_item(req.rid, spec, pair, lam, device=None)
+                if item.footprint > budget_bytes:
+                    raise ValueError(f"request {req.rid} needs {item.footprint} B, budget {budget_bytes}")
+                if not srv.fits(item):
+                    break                               # head of line waits for memory
+                srv.admit(req, item, now)
+                qi += 1
+            wait = 0.002
             if qi < len(queue):
-                time.sleep(max(0.0, min(0.001, queue[qi].arrival - clock())))
-            continue
-        for req in srv.step(clock):
-            if keep_labels:
-                req.item.labels = req.item.labels.cpu().numpy()
-            else:
-                req.item.labels = None
-            done.append(req)
+                wait = max(0.0, min(wait, queue[qi].arrival - srv.clock()))
+            srv.wait(wait)
+    finally:
+        srv.close()
     torch.cuda.synchronize()
-    return done, clock(), srv
+    with srv.lock:
+        done = list(srv.done)
+    return done, srv.clock(), srv
 
 
 def latency_summary(done):

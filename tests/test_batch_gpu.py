@@ -71,7 +71,7 @@ def _check(ref, got):
 def test_batch_matches_oracle(torch_cuda, orc, use_graph):
     torch = torch_cuda
     stream = torch.cuda.Stream() if use_graph else None
-    opts = gc.GcSolveOpts(flags=gc.GC_OPT_BATCH_GRAPH if use_graph else 0)
+    opts = gc.GcSolveOpts(flags=gc.GC_OPT_SWEEP_GRAPH if use_graph else 0)
     built = []
     ctx = torch.cuda.stream(stream) if stream is not None else torch.cuda.stream(torch.cuda.current_stream())
     with ctx:
@@ -127,15 +127,15 @@ def test_batch_larger_than_one_launch_grid(torch_cuda):
     assert sum(-(-sg.LARGE.w * sg.LARGE.h * (sg.LARGE.m - 1) // 256) for _ in items) > 65535
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        gc.maxflow_solve_batch([it[2] for it in items], gc.GcSolveOpts(flags=gc.GC_OPT_BATCH_GRAPH),
+        gc.maxflow_solve_batch([it[2] for it in items], gc.GcSolveOpts(flags=gc.GC_OPT_SWEEP_GRAPH),
                                stream=stream)
         for p, cost, g, ref in items:
             _check(ref, _read(torch, g, cost, p))
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("flags", [0, gc.GC_OPT_FUSED_SWEEP, gc.GC_OPT_FUSED_SWEEP | gc.GC_OPT_BATCH_GRAPH,
-                                   gc.GC_OPT_WAVE_FIRST | gc.GC_OPT_BATCH_GRAPH],
+@pytest.mark.parametrize("flags", [0, gc.GC_OPT_FUSED_SWEEP, gc.GC_OPT_FUSED_SWEEP | gc.GC_OPT_SWEEP_GRAPH,
+                                   gc.GC_OPT_WAVE_FIRST | gc.GC_OPT_SWEEP_GRAPH],
                          ids=["plain", "fused", "fused-graph", "wave-graph"])
 def test_batch_groups_and_variants(torch_cuda, orc, flags):
     """Four 384x288x16 graphs (66 MB of sweep state each) split into two

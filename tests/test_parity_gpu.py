@@ -33,16 +33,20 @@ def _cost_gpu(torch, left, right, p):
     return cost
 
 
-def _solve_cost_gpu(torch, cost_np, pen_h, inh_h, pen_v=None, inh_v=None, opts=None):
+def _solve_cost_gpu(torch, cost_np, pen_h, inh_h, pen_v=None, inh_v=None, opts=None, stream=None):
     m, h, w = cost_np.shape
     p = gc.problem(w, h, m, 30, pen_h, inh_h, pen_v, inh_v)
     cost = torch.from_numpy(np.ascontiguousarray(cost_np, dtype=np.int32)).cuda()
     ws = gc.alloc_workspace(p)
-    g = gc.graph_build(p, cost, ws)
-    st = gc.maxflow_solve(g, opts)
     labels = torch.empty((h, w), dtype=torch.int32, device="cuda")
     res = torch.zeros(2, dtype=torch.int64, device="cuda")
-    gc.extract_labels(g, cost, labels, res)
+    if stream is not None:
+        torch.cuda.synchronize()                 # inputs were made on the current stream
+    g = gc.graph_build(p, cost, ws, stream)
+    st = gc.maxflow_solve(g, opts, stream)
+    gc.extract_labels(g, cost, labels, res, stream)
+    if stream is not None:
+        stream.synchronize()
     r = res.cpu().numpy()
     return labels.cpu().numpy(), int(r[0]), int(r[1]), st
 
@@ -169,6 +173,7 @@ def test_repeat_solves_identical(torch_cuda, orc):
 
 
 _VARIANTS = {"wave-first": gc.GC_OPT_WAVE_FIRST, "fused": gc.GC_OPT_FUSED_SWEEP,
+             "split": gc.GC_OPT_SPLIT_SWEEP, "graph": gc.GC_OPT_SWEEP_GRAPH,
              "fused-wave-first": gc.GC_OPT_FUSED_SWEEP | gc.GC_OPT_WAVE_FIRST}
 
 
@@ -177,6 +182,7 @@ def _variant_cases():
     yield "ties-33x17x6", rng.integers(0, 2, (6, 17, 33)).astype(np.int32), (1, 1, 1, 1)
     yield "random-soft-50x21x11", rng.integers(0, 31, (11, 21, 50)).astype(np.int32), (3, 4, 2, 5)
     yield "m2-20x9", rng.integers(0, 31, (2, 9, 20)).astype(np.int32), (1, 1023, 1, 1023)
+    yield "deep-40x30x40", rng.integers(0, 31, (40, 30, 40)).astype(np.int32), (1, 1023, 1, 1023)
     import oracle
     for name, spec, seed in [("ragged-70x33x9", sg.spec_like(sg.MID, 70, 33, 9), (9, 8)),
                              ("slanted-128x96x16", sg.spec_like(sg.MID, 128, 96, 16), (5, 5))]:
@@ -189,9 +195,10 @@ def _variant_cases():
 def test_solver_variants_parity(torch_cuda, orc, variant, name, cost, params):
     """The wave-front pass and the fused sweep change the schedule only: the
     canonical cut, energy and flow stay those of the oracle."""
+    stream = torch_cuda.cuda.Stream() if variant == "graph" else None   # capture needs a stream
     for period in (1, 13, 64):
         o = gc.GcSolveOpts(relabel_period=period, flags=_VARIANTS[variant])
-        lab, energy, flow, st = _solve_cost_gpu(torch_cuda, cost, *params, opts=o)
+        lab, energy, flow, st = _solve_cost_gpu(torch_cuda, cost, *params, opts=o, stream=stream)
         _check_against_oracle(orc, cost, lab, energy, flow, params)
         assert st.active_last == 0
 

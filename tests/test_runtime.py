@@ -43,18 +43,21 @@ def _alone(spec, pair, lam=1):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("budget_mb", [4096, 6])
-def test_serving_results_same_alone_and_in_mix(budget_mb):
+@pytest.mark.parametrize("budget_mb,lanes", [(4096, ((None, 256),)), (6, ((None, 256),)),
+                                             (4096, ((2 << 20, 256), (None, 1)))],
+                         ids=["one-lane", "one-lane-tight-budget", "two-lanes"])
+def test_serving_results_same_alone_and_in_mix(budget_mb, lanes):
     """Requests arriving at 2000/s overlap on the GPU (or, with a 6 MB budget,
-    wait for memory); each result equals the same pair solved alone."""
-    import torch
+    wait for memory; with two lanes, small and larger requests run in two
+    batches on two streams at once); each result equals the same pair solved
+    alone."""
     pools = _pools(SMALL_SHAPES)
     reqs = rt.poisson_requests(24, 2000.0, SMALL_SHAPES, pool_per_shape=2, seed=6)
-    stream = torch.cuda.Stream()
-    opts = gc.GcSolveOpts(flags=gc.GC_OPT_BATCH_GRAPH)
-    with torch.cuda.stream(stream):
-        done, wall, srv = rt.serve(reqs, pools, budget_mb << 20, opts, stream, keep_labels=True)
+    opts = gc.GcSolveOpts(flags=gc.GC_OPT_SWEEP_GRAPH)
+    done, wall, srv = rt.serve(reqs, pools, budget_mb << 20, opts, lanes, keep_labels=True)
     assert len(done) == len(reqs)
+    if len(lanes) > 1:
+        assert all(l.rounds > 0 for l in srv.lanes)     # both lanes served requests
     assert srv.used == 0
     if budget_mb > 100:
         assert srv.peak_members > 1                 # requests overlapped
@@ -93,10 +96,10 @@ def test_autotune_picks_a_candidate():
     mix = rt.batch_mix(3, SMALL_SHAPES, seed=9)
     items = [rt.make_item(i, s, p) for i, (s, p) in enumerate(mix)]
     best, trials = rt.autotune(items, tiles=((8, 8, 16), (16, 8, 16)), periods=(16, 64))
-    assert len(trials) == 8
+    assert len(trials) == 12
     assert (best.tile_w, best.tile_h, best.tile_j) in {(8, 8, 16), (16, 8, 16)}
     assert best.relabel_period in (16, 64)
-    assert best.flags & ~gc.GC_OPT_FUSED_SWEEP == 0
+    assert best.flags & ~(gc.GC_OPT_FUSED_SWEEP | gc.GC_OPT_SPLIT_SWEEP) == 0
     for it in items:                      # the last trial left solved graphs
         rt.finish(it)
         assert it.energy == it.flow
