@@ -113,9 +113,10 @@ def _pct(xs, q):
 
 def bench_batch(args, gc, sg, torch):
     """Uneven batch: pairs drawn uniformly from 320x240x16, 384x288x16,
-    450x375x64 and 640x480x64, solved one pair per launch and in one batch
-    (autotuned tile and relabel period, sweeps replayed from a hipGraph).
-    Latency of a pair = its completion time from the start of the run."""
+    450x375x64 and 640x480x64, solved one pair per launch, as one batched
+    solve (maxflow_solve_batch: concurrent lanes, largest first; options
+    autotuned) and in rounds of the merged engine.  Latency of a pair = its
+    completion time from the start of the run."""
     from paper_1803_01516_amd import runtime as rt
     stream = torch.cuda.Stream()
     mix = rt.batch_mix(args.batch_pairs, sg.BATCH_SHAPES, seed=4)
@@ -133,32 +134,39 @@ def bench_batch(args, gc, sg, torch):
         _log(f"batch: autotuned over {len(trials)} candidates in {tune_s:.1f} s")
         for it in tune:
             rt.release(it)
-        one = [rt.make_item(i, spec, pair) for i, (spec, pair) in enumerate(mix)]
-        t_one, tot_one = rt.run_one_per_launch(one, None, stream)
-        _log(f"batch: one pair per launch {tot_one:.2f} s")
-        ref = [(it.energy, it.flow, it.labels.cpu()) for it in one]
-        for it in one:
-            rt.release(it)
-        del one
-        torch.cuda.empty_cache()
-        bat = [rt.make_item(i, spec, pair) for i, (spec, pair) in enumerate(mix)]
-        t_bat, tot_bat = rt.run_batched(bat, best, stream)
-        _log(f"batch: batched {tot_bat:.2f} s")
-        same = all(it.energy == r[0] and it.flow == r[1] and bool((it.labels.cpu() == r[2]).all())
-                   for it, r in zip(bat, ref))
-        nodes = sum(it.p.width * it.p.height * (it.p.labels - 1) for it in bat)
-        for it in bat:
-            rt.release(it)
-        del bat
-        torch.cuda.empty_cache()
+
+        def run(fn, opts, name):
+            items = [rt.make_item(i, spec, pair) for i, (spec, pair) in enumerate(mix)]
+            times, total = fn(items, opts, stream)
+            _log(f"batch: {name} {total:.2f} s")
+            out = [(it.energy, it.flow, it.labels.cpu()) for it in items]
+            for it in items:
+                rt.release(it)
+            del items
+            torch.cuda.empty_cache()
+            return times, total, out
+
+        t_one, tot_one, ref = run(rt.run_one_per_launch, None, "one pair per launch")
+        t_bat, tot_bat, got = run(rt.run_batched, best, "batched (lanes)")
+        merged_opts = gc.GcSolveOpts(relabel_period=best.relabel_period, tile_w=best.tile_w,
+                                     tile_h=best.tile_h, tile_j=best.tile_j,
+                                     flags=(best.flags & ~gc.GC_OPT_SWEEP_GRAPH) | gc.GC_OPT_BATCH_MERGED)
+        t_mrg, tot_mrg, got_m = run(rt.run_merged, merged_opts, "merged rounds")
+        same = all(a[0] == b[0] == c[0] and a[1] == b[1] == c[1] and bool((a[2] == b[2]).all())
+                   and bool((a[2] == c[2]).all()) for a, b, c in zip(ref, got, got_m))
     n = len(mix)
+    nodes = sum(s.w * s.h * (s.m - 1) for s, _ in mix)
+
+    def block(times, total):
+        return {"pairs_per_s": round(n / total, 2), "total_s": round(total, 3),
+                "p50_ms": _pct(times, 50), "p99_ms": _pct(times, 99)}
+
     return {"workload": f"{n} seeded pairs uniform over 320x240x16, 384x288x16, 450x375x64, "
                         "640x480x64 (6-10 slanted planes, sigma 3, cap 30, penalty 1, inhibit 1023)",
             "nodes_total": nodes,
-            "batched": {"pairs_per_s": round(n / tot_bat, 2), "total_s": round(tot_bat, 3),
-                        "p50_ms": _pct(t_bat, 50), "p99_ms": _pct(t_bat, 99)},
-            "one_per_launch": {"pairs_per_s": round(n / tot_one, 2), "total_s": round(tot_one, 3),
-                               "p50_ms": _pct(t_one, 50), "p99_ms": _pct(t_one, 99)},
+            "batched": dict(block(t_bat, tot_bat), mode=f"maxflow_solve_batch, {gc.GC_BATCH_LANES} concurrent lanes"),
+            "merged_rounds": block(t_mrg, tot_mrg),
+            "one_per_launch": block(t_one, tot_one),
             "speedup": round(tot_one / tot_bat, 3),
             "autotuned": {"tile": [best.tile_w, best.tile_h, best.tile_j],
                           "relabel_period": best.relabel_period,

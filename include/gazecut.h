@@ -138,6 +138,7 @@ typedef struct {
     int32_t active_last;      /* active nodes at the last check (0 when done) */
     int32_t kernel_launches[GC_K_CLASSES];  /* with GC_OPT_TIME_KERNELS only */
     double kernel_ms[GC_K_CLASSES];         /* estimated device time per class */
+    double done_ms;           /* maxflow_solve_batch: host ms from its start to this graph's end */
 } gc_solve_stats;
 
 /* Largest number of graphs one batch holds at a time. */
@@ -311,9 +312,25 @@ int gc_batch_add(gc_batch *b, const gc_graph *g, int64_t tag);
 int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solve_stats *done_stats,
                    int32_t max_done, int32_t *n_done);
 
-/* Solves n graphs in one batch, refilling it as members finish.  stats
+/* Concurrent lanes of maxflow_solve_batch (host threads, one HIP stream each). */
+#define GC_BATCH_LANES 4
+
+/* gc_solve_opts.flags, maxflow_solve_batch: run the graphs in rounds of the
+ * merged batch engine (gc_batch_*, one launch per phase over all members, on
+ * `stream`, using dev_table) instead of concurrent lanes. */
+#define GC_OPT_BATCH_MERGED 128
+
+/* Solves n built graphs and returns when all are solved; extract_labels then
+ * reads each.  By default the graphs go, largest first, to GC_BATCH_LANES
+ * concurrent lanes: host threads that each own a HIP stream (default
+ * priority) and solve one graph at a time exactly as maxflow_solve does, so
+ * one graph's latency-bound phases (relaxation passes, read-backs) overlap
+ * other graphs' sweeps; dev_table may then be NULL.  With
+ * GC_OPT_BATCH_MERGED the graphs run in rounds of the merged engine on
+ * `stream`, refilled as members finish (dev_table: see gc_batch_create).
+ * Either way the work starts after what is queued on `stream` so far.  stats
  * (optional) receives n entries in input order.  Returns GC_E_NOT_CONVERGED
- * if any graph hit max_sweeps.  extract_labels then reads each graph. */
+ * if any graph hit max_sweeps, else the first error of any graph. */
 int maxflow_solve_batch(gc_graph *const *gs, int32_t n, void *dev_table, size_t dev_bytes,
                         const gc_solve_opts *o, gc_solve_stats *stats, void *stream);
 

@@ -36,10 +36,15 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <numeric>
+#include <thread>
 #include <vector>
 
 #include "gazecut.h"
@@ -1427,7 +1432,17 @@ int check_opts(const Opts &o)
 
 // Optional per-launch device timing: a pair of events around each launch on
 // the solve stream, summed per kernel class once the stream has drained.
-thread_local std::vector<hipEvent_t> t_events;
+// Per-thread HIP objects are released when the thread ends (the batched
+// solve runs graphs on short-lived worker threads).
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    ~EventPool()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+thread_local EventPool t_pool;
+thread_local std::vector<hipEvent_t> &t_events = t_pool.ev;
 
 // Every kTimeEvery-th launch of a class is timed (events on every launch slow
 // the host enough to leave the GPU idle between short sweeps); the class
@@ -1504,17 +1519,25 @@ static_assert(sizeof(HeaderRead) == offsetof(DevHeader, tcap), "header prefix la
 
 // Pinned landing buffer for the read-backs, one per host thread (a pageable
 // destination would add a staging copy to every read-back).
+struct PinnedHeader {
+    HeaderRead *buf = nullptr;
+    HeaderRead fallback;
+    bool tried = false;
+    ~PinnedHeader()
+    {
+        if (buf) (void)hipHostFree(buf);
+    }
+};
+
 HeaderRead *header_buffer()
 {
-    thread_local HeaderRead *buf = nullptr;
-    thread_local HeaderRead fallback;
-    thread_local bool tried = false;
-    if (!tried) {
-        tried = true;
-        if (hipHostMalloc((void **)&buf, sizeof(HeaderRead), hipHostMallocDefault) != hipSuccess)
-            buf = nullptr;
+    thread_local PinnedHeader h;
+    if (!h.tried) {
+        h.tried = true;
+        if (hipHostMalloc((void **)&h.buf, sizeof(HeaderRead), hipHostMallocDefault) != hipSuccess)
+            h.buf = nullptr;
     }
-    return buf ? buf : &fallback;
+    return h.buf ? h.buf : &h.fallback;
 }
 
 // Runs relaxation passes until a pass changes nothing.  Passes are issued in
@@ -1573,6 +1596,10 @@ struct SweepCapture {
     bool fused = false;
     hipGraphExec_t exec = nullptr;
     unsigned long long used = 0;
+    ~SweepCapture()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
 };
 constexpr int kSweepCaptures = 8;
 
@@ -2185,17 +2212,16 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
     return GC_OK;
 }
 
-GC_API int maxflow_solve_batch(gc_graph *const *gs, int32_t n, void *dev_table, size_t dev_bytes,
-                               const gc_solve_opts *o, gc_solve_stats *stats, void *stream)
+namespace {
+
+// Merged rounds: the graphs share launches, refilled as members finish.
+int solve_batch_merged(gc_graph *const *gs, int32_t n, void *dev_table, size_t dev_bytes,
+                       const gc_solve_opts *o, gc_solve_stats *stats, void *stream)
 {
-    if (n < 0 || (n > 0 && !gs)) return GC_E_ARG;
-    for (int i = 0; i < n; ++i) {
-        int rc = graph_check(gs[i]);
-        if (rc != GC_OK) return rc;
-    }
     gc_batch *b = nullptr;
     int rc = gc_batch_create(dev_table, dev_bytes, o, &b);
     if (rc != GC_OK) return rc;
+    const auto t0 = std::chrono::steady_clock::now();
     int next = 0, done = 0;
     std::vector<int64_t> tags(kMaxBatch);
     std::vector<gc_solve_stats> sts(kMaxBatch);
@@ -2210,7 +2236,10 @@ GC_API int maxflow_solve_batch(gc_graph *const *gs, int32_t n, void *dev_table, 
             gc_batch_destroy(b);
             return rc;
         }
+        if (nd > 0 && !hip_ok(hipStreamSynchronize((hipStream_t)stream))) { gc_batch_destroy(b); return GC_E_HIP; }
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         for (int i = 0; i < nd; ++i) {
+            sts[i].done_ms = ms;
             if (stats) stats[tags[i]] = sts[i];
             if (sts[i].active_last != 0) status = GC_E_NOT_CONVERGED;
         }
@@ -2218,6 +2247,77 @@ GC_API int maxflow_solve_batch(gc_graph *const *gs, int32_t n, void *dev_table, 
     }
     gc_batch_destroy(b);
     return status;
+}
+
+// Concurrent lanes: worker threads with their own streams take the graphs,
+// largest first, and solve each as maxflow_solve does.
+int solve_batch_lanes(gc_graph *const *gs, int32_t n, const gc_solve_opts *o, gc_solve_stats *stats,
+                      void *stream)
+{
+    int dev = 0;
+    if (!hip_ok(hipGetDevice(&dev))) return GC_E_HIP;
+    hipEvent_t start = nullptr;
+    if (!hip_ok(hipEventCreateWithFlags(&start, hipEventDisableTiming))) return GC_E_HIP;
+    if (!hip_ok(hipEventRecord(start, (hipStream_t)stream))) { (void)hipEventDestroy(start); return GC_E_HIP; }
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return node_count(&gs[a]->p) > node_count(&gs[b]->p);
+    });
+    const auto t0 = std::chrono::steady_clock::now();
+    std::atomic<int> next{0}, error{GC_OK}, unconverged{0};
+    auto worker = [&]() {
+        int rc = hip_ok(hipSetDevice(dev)) ? GC_OK : GC_E_HIP;
+        hipStream_t st = nullptr;
+        if (rc == GC_OK && !hip_ok(hipStreamCreateWithFlags(&st, hipStreamNonBlocking))) rc = GC_E_HIP;
+        if (rc == GC_OK && !hip_ok(hipStreamWaitEvent(st, start, 0))) rc = GC_E_HIP;
+        while (rc == GC_OK && error.load() == GC_OK) {
+            const int k = next.fetch_add(1);
+            if (k >= n) break;
+            const int i = order[k];
+            gc_solve_stats one;
+            memset(&one, 0, sizeof(one));
+            const int r = maxflow_solve(gs[i], o, &one, st);   // returns with its stream drained
+            one.done_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (stats) stats[i] = one;
+            if (r == GC_E_NOT_CONVERGED) unconverged = 1;
+            else if (r != GC_OK) rc = r;
+        }
+        if (st) {
+            if (!hip_ok(hipStreamSynchronize(st)) && rc == GC_OK) rc = GC_E_HIP;
+            (void)hipStreamDestroy(st);
+        }
+        if (rc != GC_OK) {
+            int expect = GC_OK;
+            error.compare_exchange_strong(expect, rc);
+        }
+    };
+    const int lanes = n < GC_BATCH_LANES ? n : GC_BATCH_LANES;
+    std::vector<std::thread> th;
+    th.reserve(lanes);
+    for (int l = 0; l < lanes; ++l) th.emplace_back(worker);
+    for (std::thread &t : th) t.join();
+    (void)hipEventDestroy(start);
+    if (error.load() != GC_OK) return error.load();
+    return unconverged.load() ? GC_E_NOT_CONVERGED : GC_OK;
+}
+
+}  // namespace
+
+GC_API int maxflow_solve_batch(gc_graph *const *gs, int32_t n, void *dev_table, size_t dev_bytes,
+                               const gc_solve_opts *o, gc_solve_stats *stats, void *stream)
+{
+    if (n < 0 || (n > 0 && !gs)) return GC_E_ARG;
+    for (int i = 0; i < n; ++i) {
+        int rc = graph_check(gs[i]);
+        if (rc != GC_OK) return rc;
+    }
+    const Opts opt = resolve(o);
+    int rc = check_opts(opt);
+    if (rc != GC_OK) return rc;
+    if (n == 0) return GC_OK;
+    if (opt.flags & GC_OPT_BATCH_MERGED) return solve_batch_merged(gs, n, dev_table, dev_bytes, o, stats, stream);
+    return solve_batch_lanes(gs, n, o, stats, stream);
 }
 
 GC_API int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *labels,

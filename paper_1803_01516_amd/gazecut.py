@@ -40,6 +40,8 @@ GC_OPT_SWEEP_GRAPH = 2
 GC_OPT_WAVE_FIRST = 4
 GC_OPT_FUSED_SWEEP = 16
 GC_OPT_SPLIT_SWEEP = 64
+GC_OPT_BATCH_MERGED = 128
+GC_BATCH_LANES = 4
 GC_BATCH_MAX_GRAPHS = 256
 KERNEL_CLASSES = ("push", "relabel", "relax", "other")
 
@@ -48,12 +50,13 @@ class GcSolveStats(ctypes.Structure):
     _fields_ = [("pushes", ctypes.c_int64), ("sweeps", ctypes.c_int32),
                 ("global_relabels", ctypes.c_int32), ("bfs_passes", ctypes.c_int32),
                 ("active_last", ctypes.c_int32), ("kernel_launches", ctypes.c_int32 * 4),
-                ("kernel_ms", ctypes.c_double * 4)]
+                ("kernel_ms", ctypes.c_double * 4), ("done_ms", ctypes.c_double)]
 
     def as_dict(self):
         d = {"pushes": int(self.pushes), "sweeps": int(self.sweeps),
              "global_relabels": int(self.global_relabels),
-             "bfs_passes": int(self.bfs_passes), "active_last": int(self.active_last)}
+             "bfs_passes": int(self.bfs_passes), "active_last": int(self.active_last),
+             "done_ms": float(self.done_ms)}
         for i, k in enumerate(KERNEL_CLASSES):
             d[f"{k}_launches"] = int(self.kernel_launches[i])
             d[f"{k}_ms"] = float(self.kernel_ms[i])
@@ -332,10 +335,13 @@ class Batch:
     def close(self):
         if self._h:
             self._lib.gc_batch_destroy(self._h)
-            self._h = ctypes.c_void_p()
+            self._h = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:                    # interpreter shutdown: module globals gone
+            pass
 
     def __len__(self):
         return int(self._lib.gc_batch_members(self._h))
@@ -359,15 +365,17 @@ class Batch:
 
 
 def maxflow_solve_batch(graphs, opts: GcSolveOpts | None = None, stream=None, table=None):
-    """Solves a list of built graphs together; returns their stats in order."""
+    """Solves a list of built graphs together (concurrent lanes, or merged
+    rounds with GC_OPT_BATCH_MERGED); returns their stats in order."""
     import torch
     n = len(graphs)
     arr = (ctypes.POINTER(GcGraph) * max(1, n))(*[ctypes.pointer(g.handle) for g in graphs])
-    if table is None:
+    merged = opts is not None and bool(opts.flags & GC_OPT_BATCH_MERGED)
+    if table is None and merged:
         table = torch.empty(batch_footprint_bytes(), dtype=torch.uint8, device="cuda")
+    ptr, size = (table.data_ptr(), table.numel()) if table is not None else (None, 0)
     sts = (GcSolveStats * max(1, n))()
-    _check(load().maxflow_solve_batch(arr, n, ctypes.c_void_p(table.data_ptr()),
-                                      ctypes.c_size_t(table.numel()),
+    _check(load().maxflow_solve_batch(arr, n, ctypes.c_void_p(ptr), ctypes.c_size_t(size),
                                       ctypes.byref(opts) if opts is not None else None, sts,
                                       _stream_ptr(stream)), "maxflow_solve_batch")
     return [sts[i] for i in range(n)]

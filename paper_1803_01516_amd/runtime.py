@@ -155,8 +155,28 @@ def run_one_per_launch(items, opts=None, stream=None):
 
 
 def run_batched(items, opts=None, stream=None):
-    """Solves all items in one batch; each item's labels are read as soon as
-    it leaves the batch.  Returns completion times and the total."""
+    """Solves all items with one maxflow_solve_batch call (concurrent lanes,
+    largest graphs first), then reads every item's labels.  Returns each
+    item's solve completion time (from the library's clock, seconds from the
+    call) and the total."""
+    import torch
+    for it in items:
+        prepare(it, stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = gc.maxflow_solve_batch([it.graph for it in items], opts, stream)
+    for it, st in zip(items, sts):
+        finish(it, stream)
+        it.stats = st.as_dict()
+        it.t_done = st.done_ms * 1e-3
+    torch.cuda.synchronize()
+    return [it.t_done for it in items], time.perf_counter() - t0
+
+
+def run_merged(items, opts=None, stream=None):
+    """Solves all items in rounds of the merged batch engine (one launch per
+    phase over all members); each item's labels are read as soon as it
+    leaves the batch.  Returns completion times and the total."""
     import torch
     for it in items:
         prepare(it, stream)
@@ -300,10 +320,11 @@ class Lane:
 class Server:
     """Continuous batching over the native batch engine.
 
-    Requests are admitted in arrival order while the bytes of live graph
-    workspaces and cost volumes stay within `budget_bytes` (the head of the
-    line waits for memory) and go to the first lane whose footprint bound
-    holds them.  A lane builds an admitted request's cost volume and graph on
+    Requests go to the first lane whose footprint bound holds them and are
+    admitted first come, first served within their lane while the bytes of
+    live graph workspaces and cost volumes stay within `budget_bytes` and the
+    lane has room (a request that has to wait holds back only later requests
+    of its own lane).  A lane builds an admitted request's cost volume and graph on
     its stream and adds the graph to its running batch at the next round, so
     its work overlaps with the requests already on the GPU; finished graphs
     leave the batch, their labels are read and their memory is freed.
@@ -384,6 +405,7 @@ def serve(requests, pools, budget_bytes, opts=None, lanes=DEFAULT_LANES, lam=1, 
     srv = Server(budget_bytes, opts, lanes, keep_labels=keep_labels)
     queue = list(requests)
     qi = 0
+    waiting = []                                        # arrived, not admitted, in arrival order
     srv.t0 = time.perf_counter()
     try:
         while True:
@@ -401,10 +423,21 @@ def serve(requests, pools, budget_bytes, opts=None, lanes=DEFAULT_LANES, lam=1, 
                 item = make_item(req.rid, spec, pair, lam, device=None)
                 if item.footprint > budget_bytes:
                     raise ValueError(f"request {req.rid} needs {item.footprint} B, budget {budget_bytes}")
-                if not srv.fits(item):
-                    break                               # head of line waits for memory
-                srv.admit(req, item, now)
+                waiting.append((req, item))
                 qi += 1
+            # first come, first served within a lane: a request that does not
+            # fit (lane full or memory budget) holds back the later requests
+            # of its own lane only
+            blocked = set()
+            still = []
+            for req, item in waiting:
+                lane = srv.lane_for(item)
+                if lane.index in blocked or not srv.fits(item):
+                    blocked.add(lane.index)
+                    still.append((req, item))
+                else:
+                    srv.admit(req, item, now)
+            waiting = still
             wait = 0.002
             if qi < len(queue):
                 wait = max(0.0, min(wait, queue[qi].arrival - srv.clock()))

@@ -67,11 +67,14 @@ def _check(ref, got):
     assert (lab == ol).all()
 
 
-@pytest.mark.parametrize("use_graph", [False, True])
-def test_batch_matches_oracle(torch_cuda, orc, use_graph):
+@pytest.mark.parametrize("merged", [False, True], ids=["lanes", "merged"])
+@pytest.mark.parametrize("use_graph", [False, True], ids=["direct", "graph"])
+def test_batch_matches_oracle(torch_cuda, orc, use_graph, merged):
+    """Concurrent lanes (worker threads, one stream each) and merged rounds."""
     torch = torch_cuda
     stream = torch.cuda.Stream() if use_graph else None
-    opts = gc.GcSolveOpts(flags=gc.GC_OPT_SWEEP_GRAPH if use_graph else 0)
+    opts = gc.GcSolveOpts(flags=(gc.GC_OPT_SWEEP_GRAPH if use_graph else 0) |
+                          (gc.GC_OPT_BATCH_MERGED if merged else 0))
     built = []
     ctx = torch.cuda.stream(stream) if stream is not None else torch.cuda.stream(torch.cuda.current_stream())
     with ctx:
@@ -127,7 +130,8 @@ def test_batch_larger_than_one_launch_grid(torch_cuda):
     assert sum(-(-sg.LARGE.w * sg.LARGE.h * (sg.LARGE.m - 1) // 256) for _ in items) > 65535
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        gc.maxflow_solve_batch([it[2] for it in items], gc.GcSolveOpts(flags=gc.GC_OPT_SWEEP_GRAPH),
+        gc.maxflow_solve_batch([it[2] for it in items],
+                               gc.GcSolveOpts(flags=gc.GC_OPT_SWEEP_GRAPH | gc.GC_OPT_BATCH_MERGED),
                                stream=stream)
         for p, cost, g, ref in items:
             _check(ref, _read(torch, g, cost, p))
@@ -157,7 +161,8 @@ def test_batch_groups_and_variants(torch_cuda, orc, flags):
         for c in _cases(orc)[:4]:
             built.append(_build(torch, orc, *c))
         torch.cuda.synchronize()                 # _build works on the default stream
-        gc.maxflow_solve_batch([b[2] for b in built], gc.GcSolveOpts(relabel_period=32, flags=flags),
+        gc.maxflow_solve_batch([b[2] for b in built],
+                               gc.GcSolveOpts(relabel_period=32, flags=flags | gc.GC_OPT_BATCH_MERGED),
                                stream=stream)
         for p, cost, g, ref in built:
             _check(ref, _read(torch, g, cost, p))

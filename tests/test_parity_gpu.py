@@ -154,6 +154,47 @@ def test_large_parity_full_size(torch_cuda, orc):
     assert (labels.cpu().numpy() == gold["labels"].astype(np.int32)).all()
 
 
+@pytest.mark.parametrize("shape", [(1280, 720, 128), (640, 480, 64)], ids=["1280x720x128", "640x480x64"])
+def test_full_size_certificates(torch_cuda, orc, shape):
+    """The largest serving and batch shapes, too large for the oracle's
+    max-flow: the cost volume is compared whole; the solve is checked by
+    properties that hold at any size.  Flow = energy certifies a minimum cut
+    (every cut bounds every flow).  For sampled sites, moving one label down
+    must raise the energy strictly (the labelling is the pointwise-minimal
+    optimum, so no optimum lies below it) and moving it up must not lower it;
+    the energy change is taken from the oracle's energy on the 3x3 crop
+    around the site, which holds every term the site enters."""
+    w, h, m = shape
+    spec = sg.spec_like(sg.MID, w, h, m)
+    pr = sg.make_pair(spec, (5, 2, 0))
+    p = gc.problem(w, h, m, spec.cap, 1, 1023)
+    L = torch_cuda.from_numpy(pr.left).cuda()
+    R = torch_cuda.from_numpy(pr.right).cuda()
+    labels, cost, energy, flow, st = gc.solve_pair(L, R, p)
+    assert st.active_last == 0
+    assert energy == flow
+    cost_np = cost.cpu().numpy()
+    del cost
+    assert (cost_np == orc.cost_volume(pr.left, pr.right, m, spec.cap)).all()
+    lab = labels.cpu().numpy()
+    assert lab.min() >= 0 and lab.max() < m
+    assert orc.energy(cost_np, lab, 1, 1023) == energy
+    rng = np.random.default_rng(11)
+    for y, x in zip(rng.integers(0, h, 48), rng.integers(0, w, 48)):
+        y0, y1, x0, x1 = max(0, y - 1), min(h, y + 2), max(0, x - 1), min(w, x + 2)
+        cc = np.ascontiguousarray(cost_np[:, y0:y1, x0:x1])
+        cl = np.ascontiguousarray(lab[y0:y1, x0:x1])
+        base = orc.energy(cc, cl, 1, 1023)
+        a = int(cl[y - y0, x - x0])
+        for l in range(m):
+            if l == a:
+                continue
+            cl[y - y0, x - x0] = l
+            e2 = orc.energy(cc, cl, 1, 1023)
+            assert e2 > base if l < a else e2 >= base, (y, x, a, l, base, e2)
+        cl[y - y0, x - x0] = a
+
+
 def test_repeat_solves_identical(torch_cuda, orc):
     """The cut is schedule-independent: rebuilding and re-solving in place,
     with different relabel periods and tiles, gives identical results."""

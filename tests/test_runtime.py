@@ -79,11 +79,14 @@ def test_batched_runner_matches_one_per_launch_and_oracle(orc):
     mix = rt.batch_mix(8, SMALL_SHAPES, seed=7)
     a = [rt.make_item(i, s, p) for i, (s, p) in enumerate(mix)]
     b = [rt.make_item(i, s, p) for i, (s, p) in enumerate(mix)]
+    c = [rt.make_item(i, s, p) for i, (s, p) in enumerate(mix)]
     ta, tot_a = rt.run_one_per_launch(a)
     tb, tot_b = rt.run_batched(b, gc.GcSolveOpts(relabel_period=32))
-    for x, y, (spec, pair) in zip(a, b, mix):
-        assert x.energy == y.energy == x.flow == y.flow
-        assert (x.labels.cpu() == y.labels.cpu()).all()
+    tc, tot_c = rt.run_merged(c, gc.GcSolveOpts(relabel_period=32))
+    for x, y, z in zip(a, b, c):
+        assert x.energy == y.energy == z.energy == x.flow == y.flow == z.flow
+        assert (x.labels.cpu() == y.labels.cpu()).all() and (x.labels.cpu() == z.labels.cpu()).all()
+    assert all(0 < t <= tot_b + 1e-3 for t in tb)
     spec, pair = mix[0]
     cost = orc.cost_volume(pair.left, pair.right, spec.m, spec.cap)
     lab, f, e = orc.solve(cost, 1, 1023)
