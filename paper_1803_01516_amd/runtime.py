@@ -236,7 +236,10 @@ def poisson_requests(n, rate, shapes=sg.SERVE_SHAPES, pool_per_shape=2, seed=5):
 # the rounds of a 1280x720x128 graph; the lanes' kernels share the GPU.  A
 # lane is (footprint upper bound or None, most graphs in its batch): graphs
 # that fill the GPU on their own gain nothing from sharing rounds, so the
-# last lane takes one at a time.
+# unbounded lane takes one at a time (a second unbounded lane was measured:
+# two 1280x720x128 graphs at once share the memory bandwidth and each takes
+# nearly twice as long, so latency got worse).  Lanes of equal bound may be
+# listed; a request then goes to the least loaded of them.
 DEFAULT_LANES = ((512 << 20, gc.GC_BATCH_MAX_GRAPHS), (2 << 30, 16), (None, 1))
 
 
@@ -350,10 +353,14 @@ class Server:
         return sum(l.rounds for l in self.lanes)
 
     def lane_for(self, item: Item) -> Lane:
-        for lane in self.lanes:
-            if lane.accepts(item.footprint):
-                return lane
-        raise ValueError(f"no lane takes {item.footprint} B")
+        """The lane class with the smallest bound that holds the item; among
+        lanes of that class, the one with the fewest requests."""
+        fit = [l for l in self.lanes if l.accepts(item.footprint)]
+        if not fit:
+            raise ValueError(f"no lane takes {item.footprint} B")
+        bound = min(fit, key=lambda l: float("inf") if l.limit is None else l.limit).limit
+        same = [l for l in fit if l.limit == bound]
+        return min(same, key=lambda l: l.pending())
 
     def fits(self, item: Item) -> bool:
         lane = self.lane_for(item)
@@ -425,15 +432,15 @@ def serve(requests, pools, budget_bytes, opts=None, lanes=DEFAULT_LANES, lam=1, 
                     raise ValueError(f"request {req.rid} needs {item.footprint} B, budget {budget_bytes}")
                 waiting.append((req, item))
                 qi += 1
-            # first come, first served within a lane: a request that does not
-            # fit (lane full or memory budget) holds back the later requests
-            # of its own lane only
+            # first come, first served within a lane class (footprint bound):
+            # a request that does not fit (its lanes full or the memory
+            # budget) holds back the later requests of its own class only
             blocked = set()
             still = []
             for req, item in waiting:
                 lane = srv.lane_for(item)
-                if lane.index in blocked or not srv.fits(item):
-                    blocked.add(lane.index)
+                if lane.limit in blocked or not srv.fits(item):
+                    blocked.add(lane.limit)
                     still.append((req, item))
                 else:
                     srv.admit(req, item, now)
