@@ -52,6 +52,8 @@ def _load():
     I64 = ctypes.c_int64
     lib.orc_cost_volume.argtypes = [P, P, I, I, I, I, P]
     lib.orc_cost_volume.restype = I
+    lib.orc_cost_volume_rgb.argtypes = [P, P, I, I, I, I, P]
+    lib.orc_cost_volume_rgb.restype = I
     lib.orc_energy.argtypes = [P, P, I, I, I, I, I, I, I]
     lib.orc_energy.restype = I64
     lib.orc_graph_build.argtypes = [P, I, I, I, I, I, I, I]
@@ -115,6 +117,20 @@ def cost_volume(left: np.ndarray, right: np.ndarray, m: int, cap: int) -> np.nda
     out = np.empty((m, h, w), dtype=np.int32)
     _check(_load().orc_cost_volume(_ptr(left), _ptr(right), w, h, m, cap, _ptr(out)),
            "cost_volume")
+    return out
+
+
+def cost_volume_rgb(left: np.ndarray, right: np.ndarray, m: int, cap: int) -> np.ndarray:
+    """int32 [m][h][w]; colour sum of absolute differences per cross point
+    (images uint8 [h][w][3])."""
+    left = np.ascontiguousarray(left, dtype=np.uint8)
+    right = np.ascontiguousarray(right, dtype=np.uint8)
+    if left.ndim != 3 or left.shape[2] != 3 or right.shape != left.shape:
+        raise ValueError("colour images must be [h][w][3] and of equal shape")
+    h, w = left.shape[:2]
+    out = np.empty((m, h, w), dtype=np.int32)
+    _check(_load().orc_cost_volume_rgb(_ptr(left), _ptr(right), w, h, m, cap, _ptr(out)),
+           "cost_volume_rgb")
     return out
 
 

@@ -8,7 +8,9 @@
  * the benchmark use it.  It shares no source with the HIP library.
  *
  * What it computes, all in 64-bit integers:
- *   - the data-cost volume g(x, y, S) at every cross point   (Sec. 4.3, Sec. 3)
+ *   - the data-cost volume g(x, y, S) at every cross point   (Sec. 4.3, Sec. 3),
+ *     grayscale truncated absolute difference or colour sum of absolute
+ *     differences
  *   - the energy E(X) = sum_v g_v(X_v) + sum_(u,v) h~(X_u - X_v)  (Sec. 2, Sec. 3)
  *   - the layered (Ishikawa) graph as an explicit arc list    (Sec. 3, Fig. 4)
  *   - its exact max-flow by two unrelated textbook algorithms:
@@ -71,6 +73,35 @@ int orc_cost_volume(const uint8_t *left, const uint8_t *right, int w, int h,
                     int d = (int)left[y * w + xl] - (int)right[y * w + xr];
                     if (d < 0) d = -d;
                     g = d < cap ? d : cap;
+                }
+                cost[((int64_t)S * h + y) * w + x] = g;
+            }
+    return ORC_OK;
+}
+
+/* The colour data term of Sec. 4.3: the sum over the red, green and blue
+ * channels of the absolute differences of the two pixels of the cross point
+ * (0..765), capped at `cap` (cap >= 765 leaves it untruncated); a cross
+ * point outside the image costs cap.  Images are [h][w][3] bytes, channels
+ * interleaved. */
+int orc_cost_volume_rgb(const uint8_t *left, const uint8_t *right, int w, int h,
+                        int m, int cap, int32_t *cost)
+{
+    if (w < 0 || h < 0 || m < 1 || cap < 0 || !cost) return ORC_E_ARG;
+    for (int S = 0; S < m; S++)
+        for (int y = 0; y < h; y++)
+            for (int x = 0; x < w; x++) {
+                int xl = x - S + (m - 1);
+                int xr = x + S - (m - 1);
+                int32_t g = cap;
+                if (xl >= 0 && xl < w && xr >= 0 && xr < w) {
+                    int sad = 0;
+                    for (int c = 0; c < 3; c++) {
+                        int d = (int)left[((int64_t)y * w + xl) * 3 + c] -
+                                (int)right[((int64_t)y * w + xr) * 3 + c];
+                        sad += d < 0 ? -d : d;
+                    }
+                    g = sad < cap ? sad : cap;
                 }
                 cost[((int64_t)S * h + y) * w + x] = g;
             }

@@ -63,6 +63,51 @@ def test_cost_in_image_count_and_truncation(orc):
     assert (same[m - 1] == 0).all()
 
 
+def test_cost_rgb_hand_example(orc):
+    """Colour data term (Sec. 4.3): the sum of the three channel differences.
+    One row of three sites, m = 2: depth S = 1 is zero disparity (xl = xr =
+    x), S = 0 joins left pixel x+1 with right pixel x-1, in the image only
+    for the middle site.  Values worked by hand."""
+    L = np.array([[[10, 20, 30], [200, 0, 5], [7, 7, 7]]], np.uint8)
+    R = np.array([[[13, 15, 30], [100, 50, 255], [0, 9, 1]]], np.uint8)
+    c = orc.cost_volume_rgb(L, R, 2, 765)
+    # S = 1: |10-13|+|20-15|+0 = 8; |200-100|+|0-50|+|5-255| = 400; 7+2+6 = 15
+    assert c[1].tolist() == [[8, 400, 15]]
+    # S = 0: the middle site pairs left pixel 2 with right pixel 0:
+    # |7-13|+|7-15|+|7-30| = 37; the outer sites are outside: cost = cap
+    assert c[0].tolist() == [[765, 37, 765]]
+    assert orc.cost_volume_rgb(L, R, 2, 100)[1].tolist() == [[8, 100, 15]]
+
+
+def test_cost_rgb_channel_sum_and_symmetry(orc):
+    """Grey images repeated in all three channels cost three times the grey
+    difference; permuting the channels of both images changes nothing;
+    identical images cost 0 at zero disparity."""
+    rng = np.random.default_rng(12)
+    h, w, m = 5, 33, 7
+    gl = rng.integers(0, 256, (h, w)).astype(np.uint8)
+    gr = rng.integers(0, 256, (h, w)).astype(np.uint8)
+    L3, R3 = np.repeat(gl[..., None], 3, 2), np.repeat(gr[..., None], 3, 2)
+    grey = orc.cost_volume(gl, gr, m, 255).astype(np.int64)
+    rgb = orc.cost_volume_rgb(L3, R3, m, 765).astype(np.int64)
+    inside = grey < 255 + 1
+    assert (rgb[inside] == np.where(grey[inside] == 255, 765, 3 * grey[inside])).all()
+    cl = rng.integers(0, 256, (h, w, 3)).astype(np.uint8)
+    cr = rng.integers(0, 256, (h, w, 3)).astype(np.uint8)
+    a = orc.cost_volume_rgb(cl, cr, m, 765)
+    perm = [2, 0, 1]
+    assert (a == orc.cost_volume_rgb(cl[..., perm], cr[..., perm], m, 765)).all()
+    same = orc.cost_volume_rgb(cl, cl, m, 765)
+    assert (same[m - 1] == 0).all()
+    per_channel = sum(orc.cost_volume(np.ascontiguousarray(cl[..., k]), np.ascontiguousarray(cr[..., k]),
+                                      m, 255).astype(np.int64) for k in range(3))
+    x = np.arange(w)
+    for S in range(m):
+        ins = ((x - S + m - 1) >= 0) & ((x - S + m - 1) < w) & ((x + S - m + 1) >= 0) & ((x + S - m + 1) < w)
+        assert (a[S][:, ins] == per_channel[S][:, ins]).all()
+        assert (a[S][:, ~ins] == 765).all()
+
+
 def test_scene_zero_noise_true_cost_is_zero(orc):
     spec = dataclasses.replace(sg.MID, w=96, h=40, sigma=0.0)
     p = sg.make_pair(spec, (99, 1))
