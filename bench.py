@@ -295,6 +295,69 @@ def main():
                 "bytes_per_launch": int(bytes_launch),
                 "device_ms_per_step": {k: round(v / args.steps, 3) for k, v in tot.items()}}
 
+    # pairwise-term variants on the same pairs (Fig. 6 compares inhibit 0 and
+    # 1023; the vertical pairs' inhibit is a reading of Sec. 3): exact cuts,
+    # quality by eq. (2) against the generated truth
+    variants = {}
+    if not args.no_approx:
+        for name, (pen, inh_h, inh_v) in (("inhibit_1023", (args.lam, 1023, 1023)),
+                                          ("inhibit_0", (args.lam, 0, 0)),
+                                          ("inhibit_horizontal_only", (args.lam, 1023, 0))):
+            pv = gc.problem(spec.w, spec.h, spec.m, spec.cap, pen, inh_h, pen, inh_v)
+            lat_v, errs, pcts = [], [], []
+            for i in range(len(pairs) + 1):
+                k = i % len(pairs)
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                gc.stereo_cost_volume(lefts[k], rights[k], pv, cost, stream)
+                g = gc.graph_build(pv, cost, ws, stream)
+                gc.maxflow_solve(g, None, stream)
+                gc.extract_labels(g, cost, labels, result, stream)
+                torch.cuda.synchronize()
+                if i >= 1:
+                    lat_v.append(time.perf_counter() - a)
+                    er, pc = sg.eq2_error(pairs[k].gt, labels.cpu().numpy())
+                    errs.append(er)
+                    pcts.append(pc)
+            variants[name] = {"penalty": pen, "inhibit_h": inh_h, "inhibit_v": inh_v,
+                              "ms_per_pair": round(1e3 * float(np.median(lat_v)), 3),
+                              "eq2_error_mean": round(float(np.mean(errs)), 1),
+                              "pct_exact_mean": round(float(np.mean(pcts)), 1)}
+            _log(f"variant {name}: {variants[name]['ms_per_pair']} ms/pair, "
+                 f"eq2 error {variants[name]['eq2_error_mean']}")
+
+    # the paper's own data term (Sec. 4.3): colour pairs of the same shape,
+    # RGB sum of absolute differences, inhibit 1023, a penalty sweep around
+    # the paper's 14 and its inhibit-0 comparison (Fig. 6 analogue)
+    rgb = {}
+    if not args.no_approx:
+        rspec = sg.MID_RGB
+        rpairs = [sg.make_pair(rspec, (2, i)) for i in range(args.pairs)]
+        rl = [torch.from_numpy(q.left).to(dev) for q in rpairs]
+        rr = [torch.from_numpy(q.right).to(dev) for q in rpairs]
+        for pen, inh in ((4, 1023), (8, 1023), (14, 1023), (20, 1023), (14, 0)):
+            pv = gc.problem(rspec.w, rspec.h, rspec.m, rspec.cap, pen, inh)
+            lat_v, errs, pcts = [], [], []
+            for i in range(len(rpairs) + 1):
+                k = i % len(rpairs)
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                gc.stereo_cost_volume_rgb(rl[k], rr[k], pv, cost, stream)
+                g = gc.graph_build(pv, cost, ws, stream)
+                gc.maxflow_solve(g, None, stream)
+                gc.extract_labels(g, cost, labels, result, stream)
+                torch.cuda.synchronize()
+                if i >= 1:
+                    lat_v.append(time.perf_counter() - a)
+                    er, pc = sg.eq2_error(rpairs[k].gt, labels.cpu().numpy())
+                    errs.append(er)
+                    pcts.append(pc)
+            key = f"penalty_{pen}_inhibit_{inh}"
+            rgb[key] = {"ms_per_pair": round(1e3 * float(np.median(lat_v)), 3),
+                        "eq2_error_mean": round(float(np.mean(errs)), 1),
+                        "pct_exact_mean": round(float(np.mean(pcts)), 1)}
+            _log(f"rgb {key}: {rgb[key]['ms_per_pair']} ms/pair, eq2 error {rgb[key]['eq2_error_mean']}")
+
     # the paper's approximate cuts (Sec. 4.5) on the same pairs, timed the same way
     approx = {}
     if not args.no_approx:
@@ -407,6 +470,9 @@ def main():
         "energy_last": int(r[0]), "flow_last": int(r[1]),
         "eq2_error_last": err, "pct_exact_last": pct,
         "approx": approx or None,
+        "pairwise_variants": variants or None,
+        "rgb_sad": ({"workload": "384x288 colour pairs, 16 depth numbers, RGB sum of absolute "
+                                 "differences (untruncated), seeds (2, 0..7)", **rgb} if rgb else None),
         "copy_calibration": calib,
         "batch": batch,
         "serving": serving,

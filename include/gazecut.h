@@ -167,6 +167,16 @@ size_t gc_graph_footprint_bytes(const gc_problem *p);
 int stereo_cost_volume(const uint8_t *left, const uint8_t *right, const gc_problem *p,
                        int32_t *cost, void *stream);
 
+/* The colour data term of Sec. 4.3: g(x, y, S) = min(|dR| + |dG| + |dB|,
+ * p->cap) over the two pixels of the cross point (0..765; cap >= 765 leaves
+ * it untruncated, the paper's form, used with penalty 14 and inhibit 1023),
+ * cap outside the image.
+ * left, right: DEVICE uint8 [height][width][3], channels interleaved.
+ * cost:        DEVICE int32 [labels][height][width] (label-major), written.
+ * Errors: GC_E_ARG (NULL), GC_E_SHAPE, GC_E_HIP. */
+int stereo_cost_volume_rgb(const uint8_t *left, const uint8_t *right, const gc_problem *p,
+                           int32_t *cost, void *stream);
+
 /* Builds the layered graph of Sec. 3 (Fig. 4) in `ws`: for every site the
  * nodes v_1..v_{m-1} ("v_k on the source side" means X_v >= k) with the data
  * chain v_k -> v_{k+1} of capacity g(k) and an unbounded reverse arc,

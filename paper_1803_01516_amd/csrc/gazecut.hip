@@ -374,6 +374,34 @@ k_cost_volume(const uint8_t *__restrict__ left, const uint8_t *__restrict__ righ
     cost[((int64_t)S * H + y) * W + x] = g;
 }
 
+// Colour data term (Sec. 4.3): sum over the three channels of the absolute
+// differences, capped; images are [h][w][3] bytes.  Consecutive threads read
+// consecutive 3-byte pixels, so a wave's loads stay within a few lines.
+__global__ void __launch_bounds__(kBlock)
+k_cost_volume_rgb(const uint8_t *__restrict__ left, const uint8_t *__restrict__ right,
+                  int W, int H, int m, int cap, int32_t *__restrict__ cost)
+{
+    int x = blockIdx.x * blockDim.x + threadIdx.x;
+    int y = blockIdx.y;
+    int S = blockIdx.z;
+    if (x >= W) return;
+    int xl = x - S + (m - 1);
+    int xr = x + S - (m - 1);
+    int32_t g = cap;
+    if (xl >= 0 && xl < W && xr >= 0 && xr < W) {
+        const uint8_t *a = left + ((int64_t)y * W + xl) * 3;
+        const uint8_t *b = right + ((int64_t)y * W + xr) * 3;
+        int sad = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int d = (int)a[c] - (int)b[c];
+            sad += d < 0 ? -d : d;
+        }
+        g = sad < cap ? sad : cap;
+    }
+    cost[((int64_t)S * H + y) * W + x] = g;
+}
+
 // Node classes of a thin-skin graph: a level inside the site's window is
 // free; levels at or above its top are forced to the source side, levels
 // below its bottom to the sink side.
@@ -1717,6 +1745,22 @@ GC_API int stereo_cost_volume(const uint8_t *left, const uint8_t *right, const g
     hipStream_t st = (hipStream_t)stream;
     dim3 grid(grid_for(p->width), (unsigned)p->height, (unsigned)p->labels);
     hipLaunchKernelGGL(k_cost_volume, grid, dim3(kBlock), 0, st, left, right, p->width,
+                       p->height, p->labels, p->cap, cost);
+    return hip_ok(hipGetLastError()) ? GC_OK : GC_E_HIP;
+}
+
+GC_API int stereo_cost_volume_rgb(const uint8_t *left, const uint8_t *right, const gc_problem *p,
+                                  int32_t *cost, void *stream)
+{
+    int rc = gc_problem_check(p);
+    if (rc == GC_E_CAP_OVERFLOW) rc = GC_OK;     // the cost volume itself cannot overflow
+    if (rc != GC_OK) return rc;
+    if (!left || !right || !cost) return GC_E_ARG;
+    if (p->width == 0 || p->height == 0) return GC_OK;
+    if (p->height > 65535 || p->labels > 65535) return GC_E_SHAPE;
+    hipStream_t st = (hipStream_t)stream;
+    dim3 grid(grid_for(p->width), (unsigned)p->height, (unsigned)p->labels);
+    hipLaunchKernelGGL(k_cost_volume_rgb, grid, dim3(kBlock), 0, st, left, right, p->width,
                        p->height, p->labels, p->cap, cost);
     return hip_ok(hipGetLastError()) ? GC_OK : GC_E_HIP;
 }

@@ -64,7 +64,8 @@ class GcSolveStats(ctypes.Structure):
 
 
 EXPORTS = ("gc_status_str", "gc_last_hip_error", "gc_problem_check", "gc_graph_footprint_bytes",
-           "stereo_cost_volume", "graph_build", "maxflow_solve", "extract_labels",
+           "stereo_cost_volume", "stereo_cost_volume_rgb", "graph_build", "maxflow_solve",
+           "extract_labels",
            "gc_coarse_problem", "coarse_cost_volume", "graph_build_window", "approx_level2_cut",
            "gc_batch_footprint_bytes", "gc_batch_create", "gc_batch_destroy", "gc_batch_members",
            "gc_batch_add", "gc_batch_round", "maxflow_solve_batch")
@@ -102,6 +103,8 @@ def load(path: str = LIB_PATH):
     lib.gc_graph_footprint_bytes.restype = ctypes.c_size_t
     lib.stereo_cost_volume.argtypes = [P, P, ctypes.POINTER(GcProblem), P, P]
     lib.stereo_cost_volume.restype = ctypes.c_int
+    lib.stereo_cost_volume_rgb.argtypes = [P, P, ctypes.POINTER(GcProblem), P, P]
+    lib.stereo_cost_volume_rgb.restype = ctypes.c_int
     lib.graph_build.argtypes = [ctypes.POINTER(GcProblem), P, P, ctypes.c_size_t,
                                 ctypes.POINTER(GcGraph), P]
     lib.graph_build.restype = ctypes.c_int
@@ -174,6 +177,16 @@ def stereo_cost_volume(left, right, p: GcProblem, cost, stream=None):
                                      _stream_ptr(stream)), "stereo_cost_volume")
 
 
+def stereo_cost_volume_rgb(left, right, p: GcProblem, cost, stream=None):
+    """left/right: uint8 [h][w][3] CUDA tensors (channels interleaved);
+    cost: int32 [m][h][w] CUDA tensor."""
+    if left.dim() != 3 or left.shape[2] != 3 or tuple(right.shape) != tuple(left.shape):
+        raise ValueError("colour images must be [h][w][3] and of equal shape")
+    _check(load().stereo_cost_volume_rgb(ctypes.c_void_p(left.data_ptr()), ctypes.c_void_p(right.data_ptr()),
+                                         ctypes.byref(p), ctypes.c_void_p(cost.data_ptr()),
+                                         _stream_ptr(stream)), "stereo_cost_volume_rgb")
+
+
 @dataclass
 class Graph:
     handle: GcGraph
@@ -218,8 +231,9 @@ def alloc_workspace(p: GcProblem, device="cuda"):
 
 def solve_pair(left, right, p: GcProblem, opts: GcSolveOpts | None = None, stream=None,
                ws=None):
-    """Runs the whole path on one pair of uint8 CUDA tensors.  Returns
-    (labels tensor, cost tensor, energy, flow, stats)."""
+    """Runs the whole path on one pair of uint8 CUDA tensors ([h][w] grey or
+    [h][w][3] colour).  Returns (labels tensor, cost tensor, energy, flow,
+    stats)."""
     import torch
     dev = left.device
     cost = torch.empty((p.labels, p.height, p.width), dtype=torch.int32, device=dev)
@@ -227,7 +241,10 @@ def solve_pair(left, right, p: GcProblem, opts: GcSolveOpts | None = None, strea
     result = torch.zeros(2, dtype=torch.int64, device=dev)
     if ws is None:
         ws = alloc_workspace(p, dev)
-    stereo_cost_volume(left, right, p, cost, stream)
+    if left.dim() == 3:
+        stereo_cost_volume_rgb(left, right, p, cost, stream)
+    else:
+        stereo_cost_volume(left, right, p, cost, stream)
     g = graph_build(p, cost, ws, stream)
     st = maxflow_solve(g, opts, stream)
     extract_labels(g, cost, labels, result, stream)

@@ -44,6 +44,7 @@ class SceneSpec:
     inhibit: int = 1023
     textureless: float = 0.0      # fraction of sites covered by flat regions
     name: str = ""
+    channels: int = 1             # 3: colour images [h][w][3] (texels are RGB triples)
 
 
 # Workloads (shapes, value distributions and structure of the paper's
@@ -52,6 +53,10 @@ TINY = SceneSpec(64, 48, 8, (3, 3), False, 2.0, 20, name="tiny-64x48x8")
 MID = SceneSpec(384, 288, 16, (6, 10), True, 3.0, 30, name="mid-384x288x16")
 LARGE = SceneSpec(450, 375, 64, (12, 12), True, 2.0, 30, textureless=0.10,
                   name="large-450x375x64")
+# Colour pairs for the paper's own data term (Sec. 4.3: RGB sum of absolute
+# differences, untruncated, penalty 14, inhibit 1023).
+MID_RGB = SceneSpec(384, 288, 16, (6, 10), True, 3.0, 765, lam=14, channels=3,
+                    name="mid-rgb-384x288x16")
 BATCH_SHAPES = ((320, 240, 16), (384, 288, 16), (450, 375, 64), (640, 480, 64))
 SERVE_SHAPES = ((384, 288, 16), (640, 480, 64), (1280, 720, 128))
 
@@ -137,7 +142,8 @@ def render(S: np.ndarray, spec: SceneSpec, rng: np.random.Generator):
     xl = x - S + (m - 1)
     xr = x + S - (m - 1)
     assert xl.min() >= 0 and xl.max() < w and xr.min() >= 0 and xr.max() < w
-    T = rng.integers(0, 256, size=(h, 2 * w))
+    ch = () if spec.channels == 1 else (spec.channels,)
+    T = rng.integers(0, 256, size=(h, 2 * w) + ch)
     rects = _regions(rng, w, h, spec.textureless)
     # Consecutive sites share a pixel iff their depths differ by one, so the
     # classes along a row are runs that break wherever the depth is flat.
@@ -146,7 +152,8 @@ def render(S: np.ndarray, spec: SceneSpec, rng: np.random.Generator):
     first = np.where(~same, np.broadcast_to(x, (h, w)), 0)
     first = np.maximum.accumulate(first, axis=1)          # first site of the class
     cls_xl = np.take_along_axis(xl, first, axis=1)        # its left pixel
-    tex = np.take_along_axis(T, cls_xl, axis=1)           # class texel
+    idx = cls_xl if not ch else cls_xl[..., None]
+    tex = np.take_along_axis(T, idx, axis=1)              # class texel
     if rects:
         cid = np.cumsum(~same, axis=1) - 1 + (np.arange(h) * w)[:, None]
         over = np.full(h * w, -1, dtype=np.int64)
@@ -155,6 +162,8 @@ def render(S: np.ndarray, spec: SceneSpec, rng: np.random.Generator):
             site_over[y0:y0 + rh, x0:x0 + rw] = val
         np.maximum.at(over, cid.ravel(), site_over.ravel())
         o = over[cid]
+        if ch:
+            o = o[..., None]                              # a grey texel in every channel
         tex = np.where(o >= 0, o, tex)
     left = T[:, :w].copy()
     right = T[:, w:].copy()

@@ -116,6 +116,17 @@ def test_scene_zero_noise_true_cost_is_zero(orc):
     assert (g == 0).all()
 
 
+def test_colour_scene_zero_noise_true_cost_is_zero(orc):
+    """Colour pairs render the same geometry with RGB texels: without noise
+    the true cross points cost 0 under the colour data term."""
+    spec = dataclasses.replace(sg.MID_RGB, w=96, h=40, sigma=0.0)
+    p = sg.make_pair(spec, (99, 2))
+    assert p.left.shape == (40, 96, 3)
+    cost = orc.cost_volume_rgb(p.left, p.right, spec.m, spec.cap)
+    g = np.take_along_axis(cost, p.gt[None].astype(np.int64), 0)[0]
+    assert (g == 0).all()
+
+
 def test_scene_determinism_and_continuity():
     a = sg.make_pair(sg.TINY, (1, 5))
     b = sg.make_pair(sg.TINY, (1, 5))

@@ -70,6 +70,36 @@ def test_cost_volume_bit_exact(torch_cuda, orc, spec, seed):
     assert (cost == ref).all()
 
 
+@pytest.mark.parametrize("spec,seed", [(dataclasses.replace(sg.MID_RGB, w=64, h=48, m=8), (1, 0)),
+                                       (sg.MID_RGB, (2, 0)),
+                                       (dataclasses.replace(sg.MID_RGB, w=37, h=19, m=5, cap=100), (9, 9))],
+                         ids=["rgb-64x48x8", "rgb-384x288x16", "rgb-ragged-capped"])
+def test_cost_volume_rgb_bit_exact(torch_cuda, orc, spec, seed):
+    """Colour data term (Sec. 4.3) against the oracle, untruncated and capped."""
+    pr = sg.make_pair(spec, seed)
+    p = gc.problem(spec.w, spec.h, spec.m, spec.cap, spec.lam, spec.inhibit)
+    L = torch_cuda.from_numpy(pr.left).cuda()
+    R = torch_cuda.from_numpy(pr.right).cuda()
+    cost = torch_cuda.empty((spec.m, spec.h, spec.w), dtype=torch_cuda.int32, device="cuda")
+    gc.stereo_cost_volume_rgb(L, R, p, cost)
+    assert (cost.cpu().numpy() == orc.cost_volume_rgb(pr.left, pr.right, spec.m, spec.cap)).all()
+
+
+def test_rgb_solve_parity_full_size(torch_cuda, orc):
+    """The paper's own setting on a 384x288x16 colour pair: colour data term,
+    penalty 14, inhibit 1023; the whole path against the oracle."""
+    spec = sg.MID_RGB
+    pr = sg.make_pair(spec, (2, 0))
+    p = gc.problem(spec.w, spec.h, spec.m, spec.cap, spec.lam, spec.inhibit)
+    L = torch_cuda.from_numpy(pr.left).cuda()
+    R = torch_cuda.from_numpy(pr.right).cuda()
+    labels, cost, energy, flow, st = gc.solve_pair(L, R, p)
+    cost_np = cost.cpu().numpy()
+    assert (cost_np == orc.cost_volume_rgb(pr.left, pr.right, spec.m, spec.cap)).all()
+    _check_against_oracle(orc, cost_np, labels.cpu().numpy(), energy, flow,
+                          (spec.lam, spec.inhibit, spec.lam, spec.inhibit))
+
+
 def _image_cases():
     yield "tiny-s10", sg.TINY, (1, 0), (1, 1023, 1, 1023)
     yield "tiny-s11", sg.TINY, (1, 1), (1, 1023, 1, 1023)
@@ -127,17 +157,20 @@ def test_empty_problem(torch_cuda):
     assert res.cpu().tolist() == [0, 0]
 
 
-@pytest.mark.parametrize("lam", [1, 2])
-def test_mid_parity_full_size(torch_cuda, orc, lam):
-    """384x288x16, the workload the benchmark times."""
+@pytest.mark.parametrize("lam,inh_h,inh_v", [(1, 1023, 1023), (2, 1023, 1023), (1, 0, 0), (1, 1023, 0)],
+                         ids=["lam1", "lam2", "inhibit0", "inhibit-h-only"])
+def test_mid_parity_full_size(torch_cuda, orc, lam, inh_h, inh_v):
+    """384x288x16, the workload the benchmark times, with the pairwise-term
+    variants it reports (pure linear smoothness; inhibit on horizontal pairs
+    only)."""
     pr = sg.make_pair(sg.MID, (2, 0))
-    p = gc.problem(sg.MID.w, sg.MID.h, sg.MID.m, sg.MID.cap, lam, 1023)
+    p = gc.problem(sg.MID.w, sg.MID.h, sg.MID.m, sg.MID.cap, lam, inh_h, lam, inh_v)
     L = torch_cuda.from_numpy(pr.left).cuda()
     R = torch_cuda.from_numpy(pr.right).cuda()
     labels, cost, energy, flow, st = gc.solve_pair(L, R, p)
     cost_np = cost.cpu().numpy()
     assert (cost_np == orc.cost_volume(pr.left, pr.right, sg.MID.m, sg.MID.cap)).all()
-    _check_against_oracle(orc, cost_np, labels.cpu().numpy(), energy, flow, (lam, 1023, lam, 1023))
+    _check_against_oracle(orc, cost_np, labels.cpu().numpy(), energy, flow, (lam, inh_h, lam, inh_v))
 
 
 def test_large_parity_full_size(torch_cuda, orc):
