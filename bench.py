@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--pairs", type=int, default=8, help="distinct resident pairs cycled")
     ap.add_argument("--lam", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=3, help="pairs the oracle solves")
+    ap.add_argument("--cpu-sample", type=int, default=5, help="pairs the oracle solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
     ap.add_argument("--no-approx", action="store_true", help="skip the approximate variants")
@@ -437,7 +437,14 @@ def main():
             ok = ok and int(rr[0]) == energy and int(rr[1]) == flow and \
                 bool((labels.cpu().numpy() == lab).all())
         _log(f"cpu oracle: {n} pairs in {t:.1f} s")
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
         cpu = {"value": round(n / t, 4), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+               "host": {"cpus_visible": os.cpu_count(), "model": model},
                "sample": f"{n} pairs of the same 384x288x16 workload (seeds (2,0..{n - 1})), "
                          f"cost volume + graph + FIFO push-relabel max-flow + labels, "
                          f"single-threaded C -O2"}
