@@ -45,6 +45,12 @@ def test_problem_validation_and_footprint():
     assert gc.problem_check(big) == -4
     assert gc.footprint_bytes(big) == 0
     assert gc.problem_check(gc.problem(0, 0, 1, 30, 1, 1023)) == 0      # empty is valid
+    # node indices stay below 2^29 (32-bit index arithmetic in the kernels)
+    assert gc.problem_check(gc.problem(8192, 8192, 9, 1, 1, 1023)) == -2   # exactly 2^29 nodes
+    assert gc.problem_check(gc.problem(8192, 8191, 9, 1, 1, 1023)) == 0
+    # the largest serving shape with the untruncated colour term fits the int32 bound
+    assert gc.problem_check(gc.problem(1280, 720, 128, 765, 14, 1023)) == 0
+    assert gc.problem_check(gc.problem(1920, 1080, 16, 765, 14, 1023)) == -4
     assert gc.load().gc_status_str(-5).decode().startswith("iteration cap")
 
 
