@@ -289,6 +289,8 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
                 "traffic_over_algorithmic": None if traffic is None else round(traffic / bytes_launch, 3),
+                # measured memory-side bytes per launch over the same launch time
+                "traffic_GBs": None if traffic is None else round(traffic / (per_launch_ms * 1e-3) / 1e9, 1),
                 "kernel": kname,
                 "avg_launch_us": round(per_launch_ms * 1e3, 2),
                 "launches_per_step": round(launches[kind] / args.steps, 1),
