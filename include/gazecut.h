@@ -85,7 +85,7 @@ typedef struct {
 
 /* Solver options; a zero-filled struct selects the defaults. */
 typedef struct {
-    int32_t relabel_period;   /* push-relabel sweeps between global relabels (default 64) */
+    int32_t relabel_period;   /* most push-relabel sweeps between global relabels (default 64) */
     int32_t max_sweeps;       /* give up with GC_E_NOT_CONVERGED after this many (default 1<<20) */
     int32_t tile_w;           /* BFS tile extent along x (default 8)           */
     int32_t tile_h;           /* along y (default 8)                          */
@@ -121,6 +121,13 @@ typedef struct {
  * group, by its shallowest member).  The final result does not depend on it. */
 #define GC_OPT_FUSED_SWEEP 16
 #define GC_OPT_SPLIT_SWEEP 64
+
+/* gc_solve_opts.flags, maxflow_solve: by default the first period runs
+ * relabel_period sweeps and each later one twice the largest height of an
+ * active node at the global relabel before it (at least 16, at most
+ * relabel_period); FIXED_PERIOD runs relabel_period sweeps every time.
+ * Batched merged rounds always run full periods. */
+#define GC_OPT_FIXED_PERIOD 32
 
 /* Kernel classes of gc_solve_stats.kernel_ms / kernel_launches. */
 #define GC_K_PUSH 0           /* push sweep                                   */

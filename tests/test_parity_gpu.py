@@ -248,6 +248,7 @@ def test_repeat_solves_identical(torch_cuda, orc):
 
 _VARIANTS = {"wave-first": gc.GC_OPT_WAVE_FIRST, "fused": gc.GC_OPT_FUSED_SWEEP,
              "split": gc.GC_OPT_SPLIT_SWEEP, "graph": gc.GC_OPT_SWEEP_GRAPH,
+             "fixed-period": gc.GC_OPT_FIXED_PERIOD,
              "fused-wave-first": gc.GC_OPT_FUSED_SWEEP | gc.GC_OPT_WAVE_FIRST}
 
 
