@@ -14,10 +14,15 @@
  *     h~(d) = penalty * |d| + inhibit * (|d| - 1) * T(|d| > 1).
  *
  * Calls, in pipeline order:
- *   stereo_cost_volume  data term g at every cross point        (Sec. 4.3)
+ *   stereo_cost_volume  data term g at every cross point        (Sec. 4.3;
+ *                       stereo_cost_volume_rgb: its colour form)
  *   graph_build         layered graph, terminals as overflows    (Sec. 3 Fig. 4, Sec. 4.4)
  *   maxflow_solve       push-relabel with global relabelling     (Sec. 4.4)
  *   extract_labels      minimal source side -> depth numbers, E  (Sec. 3: the cut is the surface)
+ *
+ * Also: the hierarchical approximations of Sec. 4.5 (coarse_cost_volume,
+ * graph_build_window, approx_level2_cut) and batched solves of many graphs
+ * (maxflow_solve_batch, gc_batch_*).
  *
  * Conventions for every call:
  *   - Buffers marked DEVICE are hipMalloc'd (e.g. torch CUDA tensors) and
@@ -130,7 +135,7 @@ typedef struct {
 #define GC_OPT_FIXED_PERIOD 32
 
 /* Kernel classes of gc_solve_stats.kernel_ms / kernel_launches. */
-#define GC_K_PUSH 0           /* push sweep                                   */
+#define GC_K_PUSH 0           /* push sweep, or fused push-relabel sweep       */
 #define GC_K_RELABEL 1        /* relabel sweep (also merges inflow)           */
 #define GC_K_RELAX 2          /* one tiled BFS relaxation pass                */
 #define GC_K_OTHER 3          /* arc masks, BFS seeds, active count           */
