@@ -100,7 +100,8 @@ typedef struct {
     int32_t reserved;
 } gc_solve_opts;
 
-/* gc_solve_opts.flags: bracket every 8th launch of each kernel class with a
+/* gc_solve_opts.flags: bracket one launch in 16 of each kernel class (chosen by a hash
+ * of its number, so the sample does not alias with the sweep periods) with a
  * pair of hipEvents on the solve stream; gc_solve_stats then holds every
  * class's launch count and its device time estimated as the mean of the timed
  * launches times that count (timing every launch would slow the host enough

@@ -1518,13 +1518,29 @@ struct EventPool {
 thread_local EventPool t_pool;
 thread_local std::vector<hipEvent_t> &t_events = t_pool.ev;
 
-// Every kTimeEvery-th launch of a class is timed (events on every launch slow
-// the host enough to leave the GPU idle between short sweeps); the class
-// total is the sampled mean times the launch count.  A timed launch carries
+// One launch in kTimeEvery of each class is timed (events on every launch
+// slow the host enough to leave the GPU idle between short sweeps); the class
+// total is the sampled mean times the launch count.  Which launches are
+// timed follows a hash of the launch's number within its class, counted
+// over all solves of the host thread: a fixed stride aliases with the sweep
+// periods and relaxation batches, and a count restarted per solve samples
+// the same positions of every solve (both biased the mean by 5-17 % against
+// the profiler's per-dispatch times; this scheme by under 2 % for the sweeps).  A timed launch carries
 // its start and stop events in its own dispatch (hipExtLaunchKernelGGL), so
 // the interval is the kernel's execution, as a profiler reports it, not the
 // kernel plus the queue's event packets.
-constexpr int kTimeEvery = 8;
+constexpr int kTimeEvery = 16;
+
+inline bool timed_launch(int klass, int k)
+{
+    uint32_t h = (uint32_t)k * 0x9E3779B1u + (uint32_t)klass * 0x85EBCA77u;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    return (h % kTimeEvery) == 0;
+}
+
+thread_local uint32_t t_class_launches[GC_K_CLASSES];
 
 struct Launcher {
     hipStream_t st;
@@ -1546,7 +1562,7 @@ struct Launcher {
     void run(int klass, K kernel, dim3 grid, Args... args)
     {
         hipEvent_t a = nullptr, b = nullptr;
-        if (timing && launched[klass]++ % kTimeEvery == 0) {
+        if (timing && (++launched[klass], timed_launch(klass, (int)t_class_launches[klass]++))) {
             a = event(2 * cls.size());
             b = event(2 * cls.size() + 1);
         }
