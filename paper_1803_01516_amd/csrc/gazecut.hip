@@ -293,76 +293,6 @@ __device__ inline void decode(const Graph &s, int64_t n, int &j, int &y, int &x)
     x = r - y * s.W;
 }
 
-// Residual of the out-arc of node n in direction d (0 if the arc does not
-// exist).  Valid-range checks use the node coordinates.
-__device__ inline int32_t out_res(const Graph &s, int64_t n, int j, int y, int x, int d)
-{
-    const int64_t P = s.plane, W = s.W;
-    switch (d) {
-    case D_DOWN: return j + 1 < s.J ? s.rd[n] : 0;
-    case D_UP:   return j > 0 ? kInf : 0;
-    case D_E:    return x + 1 < s.W ? s.re[n] : 0;
-    case D_W:    return x > 0 ? s.te - s.re[n - 1] : 0;
-    case D_S:    return y + 1 < s.H ? s.rs[n] : 0;
-    case D_N:    return y > 0 ? s.ts - s.rs[n - W] : 0;
-    case D_EM:   return (x + 1 < s.W && j > 0) ? s.rem[n] : 0;
-    case D_EP:   return (x + 1 < s.W && j + 1 < s.J) ? s.rep[n] : 0;
-    case D_WM:   return (x > 0 && j > 0) ? s.ie - s.rep[n - P - 1] : 0;
-    case D_WP:   return (x > 0 && j + 1 < s.J) ? s.ie - s.rem[n + P - 1] : 0;
-    case D_SM:   return (y + 1 < s.H && j > 0) ? s.rsm[n] : 0;
-    case D_SP:   return (y + 1 < s.H && j + 1 < s.J) ? s.rsp[n] : 0;
-    case D_NM:   return (y > 0 && j > 0) ? s.is - s.rsp[n - P - W] : 0;
-    case D_NP:   return (y > 0 && j + 1 < s.J) ? s.is - s.rsm[n + P - W] : 0;
-    }
-    return 0;
-}
-
-// Residual of the in-arc into node n from its neighbour in direction d.
-__device__ inline int32_t in_res(const Graph &s, int64_t n, int j, int y, int x, int d)
-{
-    const int64_t P = s.plane, W = s.W;
-    switch (d) {
-    case D_DOWN: return j + 1 < s.J ? kInf : 0;                 // v_{k+1} -> v_k
-    case D_UP:   return j > 0 ? s.rd[n - P] : 0;                // v_{k-1} -> v_k
-    case D_E:    return x + 1 < s.W ? s.te - s.re[n] : 0;
-    case D_W:    return x > 0 ? s.re[n - 1] : 0;
-    case D_S:    return y + 1 < s.H ? s.ts - s.rs[n] : 0;
-    case D_N:    return y > 0 ? s.rs[n - W] : 0;
-    case D_EM:   return (x + 1 < s.W && j > 0) ? s.ie - s.rem[n] : 0;
-    case D_EP:   return (x + 1 < s.W && j + 1 < s.J) ? s.ie - s.rep[n] : 0;
-    case D_WM:   return (x > 0 && j > 0) ? s.rep[n - P - 1] : 0;
-    case D_WP:   return (x > 0 && j + 1 < s.J) ? s.rem[n + P - 1] : 0;
-    case D_SM:   return (y + 1 < s.H && j > 0) ? s.is - s.rsm[n] : 0;
-    case D_SP:   return (y + 1 < s.H && j + 1 < s.J) ? s.is - s.rsp[n] : 0;
-    case D_NM:   return (y > 0 && j > 0) ? s.rsp[n - P - W] : 0;
-    case D_NP:   return (y > 0 && j + 1 < s.J) ? s.rsm[n + P - W] : 0;
-    }
-    return 0;
-}
-
-// Move `delta` along the out-arc of n in direction d (residual bookkeeping
-// only; the caller moves the excess).
-__device__ inline void push_res(const Graph &s, int64_t n, int d, int32_t delta)
-{
-    const int64_t P = s.plane, W = s.W;
-    switch (d) {
-    case D_DOWN: s.rd[n] -= delta; break;
-    case D_UP:   s.rd[n - P] += delta; break;
-    case D_E:    s.re[n] -= delta; break;
-    case D_W:    s.re[n - 1] += delta; break;
-    case D_S:    s.rs[n] -= delta; break;
-    case D_N:    s.rs[n - W] += delta; break;
-    case D_EM:   s.rem[n] -= delta; break;
-    case D_EP:   s.rep[n] -= delta; break;
-    case D_WM:   s.rep[n - P - 1] += delta; break;
-    case D_WP:   s.rem[n + P - 1] += delta; break;
-    case D_SM:   s.rsm[n] -= delta; break;
-    case D_SP:   s.rsp[n] -= delta; break;
-    case D_NM:   s.rsp[n - P - W] += delta; break;
-    case D_NP:   s.rsm[n + P - W] += delta; break;
-    }
-}
-
 __device__ inline int64_t nbr(const Graph &s, int64_t n, int d)
 {
     return n + dir_dj(d) * s.plane + dir_dy(d) * (int64_t)s.W + dir_dx(d);
@@ -479,6 +409,35 @@ __device__ inline int32_t res_from_word(const Graph &s, int d, int32_t w)
     case D_WM: case D_WP: return s.ie - w;
     default:   return s.is - w;                        // D_NM, D_NP
     }
+}
+
+// Residual of the in-arc into n from its neighbour in direction d, from the
+// pair word of that arc.
+__device__ inline int32_t in_res_from_word(const Graph &s, int d, int32_t w)
+{
+    switch (d) {
+    case D_DOWN: return kInf;                           // v_{k+1} -> v_k
+    case D_E:    return s.te - w;
+    case D_S:    return s.ts - w;
+    case D_EM: case D_EP: return s.ie - w;
+    case D_SM: case D_SP: return s.is - w;
+    default:     return w;                              // word holds the in-residual
+    }
+}
+
+// Word and partner height of arc d of node n, read without a branch: for a
+// missing arc (ok false) both read node n's own height, an in-bounds address
+// whose value the caller ignores.  With unconditional loads the compiler
+// issues all of a node's loads before the first wait; loads under per-arc
+// branches were issued and awaited one arc at a time.
+__device__ inline int32_t load_word(const Graph &s, int64_t n, int d, bool ok)
+{
+    return *(ok ? word_ptr(s, n, d) : s.ht + n);
+}
+
+__device__ inline int32_t load_height(const Graph &s, int64_t n, int d, bool ok)
+{
+    return s.ht[ok ? nbr(s, n, d) : n];
 }
 
 // Graph initialisation.  Terminal arcs are folded into node overflows: the
@@ -627,9 +586,11 @@ k_coarse_cost(const int32_t *__restrict__ cost, int W, int H, int m, int b,
     coarse[((int64_t)Sc * hc + Y) * wc + X] = sum;
 }
 
-// Push sweep.  All 14 stored words and neighbour heights of an active node
-// are loaded up front (one round of memory latency); pushes then run in
-// registers and write the new words directly.
+// Push sweep.  The 14 neighbour heights of an active node are loaded first;
+// only arcs to a neighbour exactly one below are admissible, so only their
+// words are loaded next (a second round of memory latency that saves most
+// word loads).  Pushes then run in registers and write the new words
+// directly.
 template <class Src>
 __global__ void __launch_bounds__(kBlock)
 k_push(Src src)
@@ -645,18 +606,22 @@ k_push(Src src)
             int j, y, x;
             decode(s, n, j, y, x);
             const unsigned ex_mask = arc_exists(s, j, y, x);
-            int32_t w[14], hv[14];
+            unsigned cand = 0;                // existing arcs to height h - 1
 #pragma unroll
             for (int d = 0; d < 14; ++d) {
                 const bool ok = (ex_mask >> d) & 1u;
-                w[d] = ok ? *word_ptr(s, n, d) : 0;
-                hv[d] = ok ? s.ht[nbr(s, n, d)] : kInf;
+                const int32_t hv = ok ? s.ht[nbr(s, n, d)] : kInf;
+                cand |= (hv == h - 1 ? 1u : 0u) << d;
             }
+            int32_t w[14];
+#pragma unroll
+            for (int d = 0; d < 14; ++d)
+                w[d] = ((cand >> d) & 1u) ? *word_ptr(s, n, d) : 0;
 #pragma unroll
             for (int d = 0; d < 14; ++d) {
-                if (!((ex_mask >> d) & 1u)) continue;
+                if (!((cand >> d) & 1u)) continue;
                 const int32_t r = res_from_word(s, d, w[d]);
-                if (e > 0 && r > 0 && hv[d] == h - 1) {
+                if (e > 0 && r > 0) {
                     const int32_t delta = e < r ? e : r;
                     *word_ptr(s, n, d) = word_is_forward(d) ? w[d] - delta : w[d] + delta;
                     const int64_t v = nbr(s, n, d);
@@ -701,8 +666,8 @@ k_relabel(Src src)
 #pragma unroll
             for (int d = 0; d < 14; ++d) {
                 const bool ok = (ex_mask >> d) & 1u;
-                w[d] = ok ? *word_ptr(s, n, d) : 0;
-                hv[d] = ok ? s.ht[nbr(s, n, d)] : kInf;
+                w[d] = load_word(s, n, d, ok);
+                hv[d] = load_height(s, n, d, ok);
             }
             int32_t hmin = kInf;
 #pragma unroll
@@ -761,8 +726,14 @@ k_sweep(Src src)
 #pragma unroll
             for (int d = 0; d < 14; ++d) {
                 const bool ok = (ex_mask >> d) & 1u;
-                r[d] = ok ? res_from_word(s, d, *word_ptr(s, n, d)) : 0;
-                hv[d] = ok ? s.ht[nbr(s, n, d)] : kInf;
+                r[d] = load_word(s, n, d, ok);
+                hv[d] = load_height(s, n, d, ok);
+            }
+#pragma unroll
+            for (int d = 0; d < 14; ++d) {       // after all loads are issued
+                const bool ok = (ex_mask >> d) & 1u;
+                r[d] = ok ? res_from_word(s, d, r[d]) : 0;
+                hv[d] = ok ? hv[d] : kInf;
             }
             int32_t hmin = kInf;
 #pragma unroll
@@ -836,11 +807,15 @@ k_mask(Src src, int mode)
     int j, y, x;
     decode(s, n, j, y, x);
     if (s.win && is_frozen(s, j, y, x)) { s.mask[n] = 0; return; }
+    const unsigned ex_mask = arc_exists(s, j, y, x);
+    int32_t w[14];
+#pragma unroll
+    for (int d = 0; d < 14; ++d) w[d] = load_word(s, n, d, (ex_mask >> d) & 1u);
     unsigned mk = 0;
 #pragma unroll
     for (int d = 0; d < 14; ++d) {
-        int32_t r = mode == 0 ? out_res(s, n, j, y, x, d) : in_res(s, n, j, y, x, d);
-        mk |= (r > 0 ? 1u : 0u) << d;
+        const int32_t r = mode == 0 ? res_from_word(s, d, w[d]) : in_res_from_word(s, d, w[d]);
+        mk |= (((ex_mask >> d) & 1u) && r > 0 ? 1u : 0u) << d;
     }
     s.mask[n] = (uint16_t)mk;
     });
