@@ -867,7 +867,6 @@ k_relax(Src src, int mode, int max_rounds, int pass)
     constexpr int NPT = NI / kBlock;
     __shared__ int32_t sv[NH];
     __shared__ uint16_t smk[NI];
-    __shared__ int s_run;
     for_blocks(src, 1, [&](const Graph &s, int64_t lb) {
     // mode 0: BFS distance to the deficits in ht; mode 1: reachability in aux
     int32_t *__restrict__ val = mode == 0 ? s.ht : s.aux;
@@ -879,43 +878,50 @@ k_relax(Src src, int mode, int max_rounds, int pass)
     if (pass > 1 && flags[(pass - 1) % kMaxFlags] == 0) return;     // converged already
     const int tile = (int)lb;
     const int bx = tile % ntx, by = (tile / ntx) % nty, bz = tile / (ntx * nty);
-    // Neighbouring tiles may rewrite their stamps during this pass, so one
-    // thread decides for the whole block.
-    if (tid == 0) {
-        int run = pass == 1;
-        if (pass > 1) {
-            for (int dz = -1; dz <= 1; ++dz)
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        const int tz = bz + dz, ty = by + dy, tx = bx + dx;
-                        if (tz < 0 || tz >= ntz || ty < 0 || ty >= nty || tx < 0 || tx >= ntx) continue;
-                        const int st = stamps[(tz * nty + ty) * ntx + tx];
-                        if ((st >> 1) == pass - 1) run = 1;
-                    }
-        }
-        s_run = run;
+    // Thread t < 27 reads the stamp of tile t of the 3x3x3 neighbourhood (one
+    // round trip instead of 27 in a row); neighbouring tiles may rewrite
+    // their stamps during this pass, so the block-wide OR of what was read
+    // decides for the whole block.
+    int changed = pass == 1;
+    if (pass > 1 && tid < 27) {
+        const int tz = bz + tid / 9 - 1, ty = by + (tid / 3) % 3 - 1, tx = bx + tid % 3 - 1;
+        if (tz >= 0 && tz < ntz && ty >= 0 && ty < nty && tx >= 0 && tx < ntx)
+            changed = (stamps[(tz * nty + ty) * ntx + tx] >> 1) == pass - 1;
     }
-    __syncthreads();
-    if (!s_run) return;
+    if (!__syncthreads_or(changed)) return;
     const int x0 = bx * TW, y0 = by * TH, j0 = bz * TJ;
 
-    for (int i = tid; i < NH; i += kBlock) {
+    // Halo values and masks: all of a thread's loads are issued before the
+    // first wait; a position outside the grid reads element 0 (in bounds)
+    // and is replaced by infinity / an empty mask.
+    constexpr int NHT = (NH + kBlock - 1) / kBlock;
+    int32_t hv[NHT];
+    bool hin[NHT];
+#pragma unroll
+    for (int k = 0; k < NHT; ++k) {
+        const int i = tid + k * kBlock;
         const int lx = i % HW, t = i / HW, ly = t % HH, lj = t / HH;
         const int gx = x0 + lx - 1, gy = y0 + ly - 1, gj = j0 + lj - 1;
-        int32_t v = kInf;
-        if (gx >= 0 && gx < s.W && gy >= 0 && gy < s.H && gj >= 0 && gj < s.J)
-            v = val[((int64_t)gj * s.H + gy) * s.W + gx];
-        sv[i] = v;
+        hin[k] = i < NH && gx >= 0 && gx < s.W && gy >= 0 && gy < s.H && gj >= 0 && gj < s.J;
+        hv[k] = val[hin[k] ? ((int64_t)gj * s.H + gy) * s.W + gx : 0];
     }
+    uint16_t mv[NPT];
+    bool mok[NPT];
 #pragma unroll
     for (int k = 0; k < NPT; ++k) {
         const int i = tid + k * kBlock;
         const int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
         const int gx = x0 + lx, gy = y0 + ly, gj = j0 + lj;
-        const unsigned mk =
-            (gx < s.W && gy < s.H && gj < s.J) ? s.mask[((int64_t)gj * s.H + gy) * s.W + gx] : 0u;
-        smk[i] = (uint16_t)mk;
+        mok[k] = gx < s.W && gy < s.H && gj < s.J;
+        mv[k] = s.mask[mok[k] ? ((int64_t)gj * s.H + gy) * s.W + gx : 0];
     }
+#pragma unroll
+    for (int k = 0; k < NHT; ++k) {
+        const int i = tid + k * kBlock;
+        if (i < NH) sv[i] = hin[k] ? hv[k] : kInf;
+    }
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) smk[tid + k * kBlock] = mok[k] ? mv[k] : (uint16_t)0;
     constexpr int hoff[14] = {
         (dir_dj(0) * HH + dir_dy(0)) * HW + dir_dx(0),   (dir_dj(1) * HH + dir_dy(1)) * HW + dir_dx(1),
         (dir_dj(2) * HH + dir_dy(2)) * HW + dir_dx(2),   (dir_dj(3) * HH + dir_dy(3)) * HW + dir_dx(3),
