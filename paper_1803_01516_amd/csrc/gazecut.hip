@@ -109,8 +109,8 @@ struct Graph {
     uint16_t *mask;
     int32_t *stamps;          // per relaxation tile: last pass that changed it
     int32_t *wlo, *whi;       // per-site label window of a thin-skin graph
-    uint8_t *bact;            // per 256-node block: holds an active node
-    uint8_t *binf;            // per 256-node block: received inflow in the last push sweep
+    uint8_t *bact;            // per 64-node group: holds an active node
+    uint8_t *binf;            // per 64-node group: received inflow in the last push sweep
     DevHeader *hdr;
     Slot *slots;
     int32_t W, H, J;
@@ -120,6 +120,12 @@ struct Graph {
 };
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Activity flags cover 64-node groups, the nodes of one wavefront of a
+// block, so that each wavefront decides, clears and sets its own flags with
+// no barrier.  Every block has four, also past the last node.
+constexpr int kGroup = 64;
+inline size_t flag_bytes(int64_t n) { return (size_t)((n + kBlock - 1) / kBlock) * (kBlock / kGroup); }
 
 thread_local int t_last_hip = 0;
 
@@ -161,8 +167,8 @@ Graph view(const gc_graph *g)
     s.mask = (uint16_t *)b; b += align256((size_t)s.N * 2);
     s.wlo = (int32_t *)b; b += align256((size_t)s.plane * 4);
     s.whi = (int32_t *)b; b += align256((size_t)s.plane * 4);
-    s.bact = (uint8_t *)b; b += align256((size_t)(s.N + kBlock - 1) / kBlock);
-    s.binf = (uint8_t *)b; b += align256((size_t)(s.N + kBlock - 1) / kBlock);
+    s.bact = (uint8_t *)b; b += align256(flag_bytes(s.N));
+    s.binf = (uint8_t *)b; b += align256(flag_bytes(s.N));
     s.stamps = (int32_t *)b;
     s.te = 2 * p.penalty_h; s.ts = 2 * p.penalty_v;
     s.ie = p.inhibit_h; s.is = p.inhibit_v;
@@ -189,6 +195,17 @@ __device__ inline long long wave_sum_i64(long long v)
 }
 
 __device__ inline bool lane0() { return (threadIdx.x & 63) == 0; }
+
+// Activity-flag group of this thread's wavefront in block lb.
+__device__ inline int64_t group_of(int64_t lb) { return lb * (kBlock / kGroup) + (threadIdx.x >> 6); }
+
+__device__ inline bool wave_any(bool p) { return __ballot(p) != 0; }
+
+__device__ inline int wave_sum(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
 
 // Sum over a kBlock-thread block; the result is valid in thread 0.  Every
 // thread of the block must call it.
@@ -596,7 +613,8 @@ __global__ void __launch_bounds__(kBlock)
 k_push(Src src)
 {
     for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
-    if (!s.bact[lb]) return;                  // no active node in this block
+    const int64_t g = group_of(lb);
+    if (!s.bact[g]) return;                   // no active node in this wavefront's group
     int64_t n = lb * kBlock + threadIdx.x;
     int cnt = 0;
     if (n < s.N) {
@@ -626,7 +644,7 @@ k_push(Src src)
                     *word_ptr(s, n, d) = word_is_forward(d) ? w[d] - delta : w[d] + delta;
                     const int64_t v = nbr(s, n, d);
                     atomicAdd(&s.ein[v], delta);
-                    s.binf[v / kBlock] = 1;
+                    s.binf[v / kGroup] = 1;
                     e -= delta;
                     ++cnt;
                 }
@@ -634,8 +652,8 @@ k_push(Src src)
             s.ex[n] = e;
         }
     }
-    cnt = block_sum(cnt);
-    if (threadIdx.x == 0 && cnt) atomicAdd(&my_slot(s.slots, lb).pushes, (unsigned long long)cnt);
+    cnt = wave_sum(cnt);                      // no barrier: the wavefront finishes alone
+    if (lane0() && cnt) atomicAdd(&my_slot(s.slots, g).pushes, (unsigned long long)cnt);
     });
 }
 
@@ -646,17 +664,17 @@ __global__ void __launch_bounds__(kBlock)
 k_relabel(Src src)
 {
     for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
-    if (!s.bact[lb] && !s.binf[lb]) return;   // nothing arrived, nothing to lift
+    // Loads that do not depend on each other are written before the first
+    // use or store, so they go out together (the compiler cannot move a load
+    // above a store to another of the state arrays: they might alias).
+    const int64_t g = group_of(lb);
+    const uint8_t was_active = s.bact[g], got_inflow = s.binf[g];
+    if (!was_active && !got_inflow) return;   // nothing arrived, nothing to lift
     int64_t n = lb * kBlock + threadIdx.x;
     bool active = false;
     if (n < s.N) {
-        int32_t in = s.ein[n];
-        int32_t e = s.ex[n];
-        if (in != 0) {
-            e += in;
-            s.ex[n] = e;
-            s.ein[n] = 0;
-        }
+        const int32_t in = s.ein[n];
+        const int32_t e = s.ex[n] + in;
         const int32_t h = s.ht[n];
         if (e > 0 && h < kInf) {
             int j, y, x;
@@ -678,11 +696,15 @@ k_relabel(Src src)
             if (nh > h) s.ht[n] = nh;
             active = nh < kInf;
         }
+        if (in != 0) {                        // stores last: no load waits behind them
+            s.ex[n] = e;
+            s.ein[n] = 0;
+        }
     }
-    const int any = block_sum(active ? 1 : 0);
-    if (threadIdx.x == 0) {
-        s.bact[lb] = any > 0;
-        s.binf[lb] = 0;
+    const bool any = wave_any(active);        // no barrier: the wavefront finishes alone
+    if (lane0()) {
+        if (any != (was_active != 0)) s.bact[g] = any;
+        if (got_inflow) s.binf[g] = 0;
     }
     });
 }
@@ -702,22 +724,23 @@ __global__ void __launch_bounds__(kBlock)
 k_sweep(Src src)
 {
     for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
-    __shared__ int s_go;
-    if (threadIdx.x == 0) {
-        const bool inflow = s.binf[lb] != 0;
-        if (inflow) s.binf[lb] = 0;               // cleared before the inflow is merged
-        s_go = inflow || s.bact[lb];
-    }
-    __syncthreads();
-    if (!s_go) return;
+    const int64_t g = group_of(lb);
+    const uint8_t inflow = s.binf[g], was_active = s.bact[g];
+    if (!inflow && !was_active) return;
+    // The flag is cleared before the inflow is merged.  A push landing in
+    // between may still lose its flag (neither side waits for its stores);
+    // its inflow then waits in ein for a later flag or for k_merge, which
+    // ends every period by merging every node.
+    if (inflow && lane0()) s.binf[g] = 0;
     const int64_t n = lb * kBlock + threadIdx.x;
     bool active = false;
     int cnt = 0;
     if (n < s.N) {
         int32_t e = s.ex[n];
+        const int32_t in = s.ein[n];
+        int32_t h = s.ht[n];                      // loaded with ex and ein, before the exchange
         const int32_t e0 = e;
-        if (s.ein[n] != 0) e += atomicExch(&s.ein[n], 0);
-        int32_t h = s.ht[n];
+        if (in != 0) e += atomicExch(&s.ein[n], 0);
         if (e > 0 && h < kInf) {
             int j, y, x;
             decode(s, n, j, y, x);
@@ -750,7 +773,7 @@ k_sweep(Src src)
                     atomicAdd(word_ptr(s, n, d), word_is_forward(d) ? -delta : delta);
                     const int64_t v = nbr(s, n, d);
                     atomicAdd(&s.ein[v], delta);
-                    s.binf[v / kBlock] = 1;
+                    s.binf[v / kGroup] = 1;
                     e -= delta;
                     ++cnt;
                 }
@@ -759,12 +782,11 @@ k_sweep(Src src)
         }
         if (e != e0) s.ex[n] = e;
     }
-    const int any = block_sum(active ? 1 : 0);
-    __syncthreads();
-    cnt = block_sum(cnt);
-    if (threadIdx.x == 0) {
-        s.bact[lb] = any > 0;
-        if (cnt) atomicAdd(&my_slot(s.slots, lb).pushes, (unsigned long long)cnt);
+    const bool any = wave_any(active);        // no barrier: the wavefront finishes alone
+    cnt = wave_sum(cnt);
+    if (lane0()) {
+        if (any != (was_active != 0)) s.bact[g] = any;
+        if (cnt) atomicAdd(&my_slot(s.slots, g).pushes, (unsigned long long)cnt);
     }
     });
 }
@@ -999,15 +1021,17 @@ k_count_active(Src src)
         a = (s.ex[n] > 0 && h < kInf) ? 1 : 0;
         hmax = a ? h : 0;
     }
+    const bool wave_active = wave_any(a != 0);
+    if (lane0()) {                            // group flags of the sweeps that follow
+        const int64_t g = group_of(lb);
+        s.bact[g] = wave_active;
+        s.binf[g] = 0;
+    }
     a = block_sum(a);
     hmax = block_max(hmax);
-    if (threadIdx.x == 0) {
-        if (a) {
-            atomicAdd(&my_slot(s.slots, lb).active, a);
-            atomicMax(&my_slot(s.slots, lb).max_height, hmax);
-        }
-        s.bact[lb] = a > 0;                   // block flags of the sweeps that follow
-        s.binf[lb] = 0;
+    if (threadIdx.x == 0 && a) {
+        atomicAdd(&my_slot(s.slots, lb).active, a);
+        atomicMax(&my_slot(s.slots, lb).max_height, hmax);
     }
     });
 }
@@ -1771,9 +1795,8 @@ GC_API size_t gc_graph_footprint_bytes(const gc_problem *p)
     if (gc_problem_check(p) != GC_OK) return 0;
     size_t n = (size_t)node_count(p);
     const size_t sites = (size_t)p->width * p->height;
-    const size_t blocks = (n + kBlock - 1) / kBlock;
     return align256(sizeof(DevHeader)) + align256(kSlots * sizeof(Slot)) + 11 * align256(n * 4) +
-           align256(n * 2) + 2 * align256(sites * 4) + 2 * align256(blocks) +
+           align256(n * 2) + 2 * align256(sites * 4) + 2 * align256(flag_bytes((int64_t)n)) +
            align256(max_tiles(p) * 4);
 }
 
