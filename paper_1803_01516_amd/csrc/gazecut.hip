@@ -709,8 +709,8 @@ k_relabel(Src src)
     });
 }
 
-// Fused sweep: one kernel per push-relabel step.  Every node of a block
-// that holds an active node or received inflow merges its inflow, relabels
+// Fused sweep: one kernel per push-relabel step.  Every node of a 64-node
+// group that holds an active node or received inflow merges its inflow, relabels
 // to one above its lowest residual neighbour when no neighbour is lower, and
 // pushes along residual arcs to lower neighbours.  Neighbour heights are
 // read while they change; a stale height is never above the current one
@@ -792,8 +792,8 @@ k_sweep(Src src)
 }
 
 // Merges the inflow left by the last fused sweep into the excess.  Every
-// block is visited: a block's inflow flag is cleared and set by different
-// workgroups of one sweep without ordering, so it may read 0 while inflow is
+// node is visited: a group's inflow flag is cleared and set by different
+// wavefronts of one sweep without ordering, so it may read 0 while inflow is
 // pending.
 template <class Src>
 __global__ void __launch_bounds__(kBlock)
@@ -1644,8 +1644,13 @@ HeaderRead *header_buffer()
 // count of the sweeps (active nodes, block flags) and the push total, read
 // back with the flags: the values of the batch that reached the fixpoint are
 // the final ones, so the termination test costs no read-back of its own.
+// Passes go out in batches with one read-back each; a pass after one that
+// changed nothing returns at once, so a batch longer than needed costs a
+// few microseconds per extra pass while a read-back idles the GPU for a
+// host round trip.  The first batch is `first_batch` passes (the caller's
+// estimate), later ones double up to kMaxFlags - 1.
 int relax_to_fixpoint(const Graph &s, int mode, const Opts &o, Launcher &L, int *passes_out,
-                      bool count_active = false, HeaderRead *out = nullptr)
+                      bool count_active = false, HeaderRead *out = nullptr, int first_batch = 4)
 {
     const int64_t tiles = relax_tiles(s, o);
     RelaxFn<Graph> fn = relax_kernel<Graph>(o.tw, o.th, o.tj);
@@ -1654,7 +1659,8 @@ int relax_to_fixpoint(const Graph &s, int mode, const Opts &o, Launcher &L, int 
     const int max_passes = 1 << 22;
     const unsigned grid = grid_for(s.N);
     HeaderRead *h = header_buffer();
-    int passes = 0, batch = 4;
+    int passes = 0;
+    int batch = first_batch < 1 ? 1 : first_batch > kMaxFlags - 1 ? kMaxFlags - 1 : first_batch;
     for (;;) {
         hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, L.st, s.hdr, passes + 1, batch);
         for (int b = 1; b <= batch && tiles > 0; ++b)
@@ -1676,7 +1682,7 @@ int relax_to_fixpoint(const Graph &s, int mode, const Opts &o, Launcher &L, int 
         }
         if (done) break;
         if (passes >= max_passes) return GC_E_NOT_CONVERGED;
-        batch = batch >= 8 ? kMaxFlags - 1 : batch * 2;
+        batch = batch * 2 > kMaxFlags - 1 ? kMaxFlags - 1 : batch * 2;
     }
     if (out) *out = *h;
     *passes_out += passes;
@@ -1951,6 +1957,7 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
     const bool fused = sweep_fused(opt, s.J);
     const bool use_graph = st != nullptr && (opt.flags & GC_OPT_SWEEP_GRAPH) != 0 && !L.timing;
     int status = GC_OK;
+    int batch_hint = 4;
     for (int round = 0;; ++round) {
         // wave-front pass along the columns, then exact global relabelling:
         // BFS distance to the deficit nodes
@@ -1959,9 +1966,13 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
         L.run(GC_K_OTHER, k_mask<Graph>, dim3(grid), s, 0);
         L.run(GC_K_OTHER, k_seed<Graph>, dim3(grid), s, 0);
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
-        // termination count and push total come back with the last flags
+        // termination count and push total come back with the last flags;
+        // the first batch of passes is sized from the previous relabel's
         HeaderRead hr;
-        if ((rc = relax_to_fixpoint(s, 0, opt, L, &st_local.bfs_passes, true, &hr)) != GC_OK) return rc;
+        const int passes_before = st_local.bfs_passes;
+        if ((rc = relax_to_fixpoint(s, 0, opt, L, &st_local.bfs_passes, true, &hr, batch_hint)) != GC_OK)
+            return rc;
+        batch_hint = st_local.bfs_passes - passes_before + 1;
         st_local.global_relabels++;
         st_local.active_last = hr.active;
         st_local.pushes = (int64_t)hr.pushes;
