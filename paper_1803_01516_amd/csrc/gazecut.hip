@@ -961,12 +961,26 @@ k_relax(Src src, int mode, int max_rounds, int pass)
         orig[k] = sv[((lj + 1) * HH + (ly + 1)) * HW + (lx + 1)];
     }
 
+    // Within a round each thread takes its nodes in sequence and sees its own
+    // updates at once, so it helps if they are consecutive levels of one
+    // column, visited in the direction values travel: a round then carries a
+    // value several levels along the chain instead of one.  Thread t owns
+    // column t % C of the tile's C = TW * TH columns and NPT consecutive
+    // levels (when the block covers the columns a whole number of times;
+    // otherwise i = t + k * kBlock, which keeps a column's levels in one
+    // thread when C is a multiple of kBlock).  Distances to the deficits
+    // (mode 0) grow upwards from the bottom of the chain, reachability from
+    // the excess (mode 1) spreads downwards; odd rounds take the reverse order.
+    constexpr int C = TW * TH;
+    constexpr bool kColumns = C <= kBlock && kBlock % C == 0;
     bool capped = true;
     for (int round = 0; round < max_rounds; ++round) {
         bool ch = false;
+        const bool upward = ((round & 1) == 0) == (mode == 0);
 #pragma unroll
         for (int k = 0; k < NPT; ++k) {
-            const int i = tid + k * kBlock;
+            const int kk = upward ? NPT - 1 - k : k;
+            const int i = kColumns ? tid % C + C * (NPT * (tid / C) + kk) : tid + kk * kBlock;
             const unsigned m = smk[i];
             if (!m) continue;
             const int lx = i % TW, t = i / TW, ly = t % TH, lj = t / TH;
