@@ -40,7 +40,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=5, help="pairs the oracle solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel event timing")
-    ap.add_argument("--no-approx", action="store_true", help="skip the approximate variants")
+    ap.add_argument("--no-approx", action="store_true",
+                    help="skip the variant sections (approximate cuts, pairwise and colour "
+                         "variants, the larger 450x375x64 pair)")
     ap.add_argument("--batch-pairs", type=int, default=64, help="pairs of the uneven batch (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=60, help="requests of the serving stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -397,6 +399,43 @@ def main():
                                "eq2_error_mean": round(float(np.mean(errs)), 1),
                                "pct_exact_mean": round(float(np.mean(pcts)), 1)}
 
+    # the larger configuration: 450x375 pairs with 64 depth numbers (12
+    # slanted planes, 10 % textureless), exact solve, default options
+    large = None
+    if not args.no_approx:
+        lspec = sg.LARGE
+        lp = gc.problem(lspec.w, lspec.h, lspec.m, lspec.cap, 1, lspec.inhibit)
+        lws = gc.alloc_workspace(lp, dev)
+        lpairs = [sg.make_pair(lspec, (3, i)) for i in range(3)]
+        ll = [torch.from_numpy(q.left).to(dev) for q in lpairs]
+        lr = [torch.from_numpy(q.right).to(dev) for q in lpairs]
+        gc.solve_pair(ll[0], lr[0], lp, None, stream, lws)          # warm-up
+        lat_l, sw_l, rl_l, ps_l, errs, pcts, exact = [], [], [], [], [], [], True
+        for k in range(len(lpairs)):
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            lab_l, _, e_l, f_l, st_l = gc.solve_pair(ll[k], lr[k], lp, None, stream, lws)
+            torch.cuda.synchronize()
+            lat_l.append(time.perf_counter() - a)
+            exact = exact and e_l == f_l                     # min-cut energy = max flow
+            sw_l.append(st_l.sweeps); rl_l.append(st_l.global_relabels); ps_l.append(st_l.bfs_passes)
+            er, pc = sg.eq2_error(lpairs[k].gt, lab_l.cpu().numpy())
+            errs.append(er)
+            pcts.append(pc)
+        large = {"workload": "450x375 grayscale pairs, 64 depth numbers, 12 slanted planes, 10 % "
+                             "textureless, sigma 2, cap 30, penalty 1, inhibit 1023, seeds (3, 0..2)",
+                 "nodes": lspec.w * lspec.h * (lspec.m - 1),
+                 "ms_per_pair": round(1e3 * float(np.median(lat_l)), 3),
+                 "ms_per_pair_all": [round(1e3 * x, 2) for x in lat_l],
+                 "sweeps_per_pair": round(float(np.mean(sw_l)), 1),
+                 "global_relabels_per_pair": round(float(np.mean(rl_l)), 2),
+                 "bfs_passes_per_pair": round(float(np.mean(ps_l)), 1),
+                 "eq2_error_mean": round(float(np.mean(errs)), 1),
+                 "pct_exact_mean": round(float(np.mean(pcts)), 1),
+                 "energy_equals_flow": exact}
+        _log(f"larger pair 450x375x64: {large['ms_per_pair']} ms/pair")
+        del lws, ll, lr
+
     calib = None
     if args.copy_calibration:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
@@ -480,6 +519,7 @@ def main():
         "eq2_error_last": err, "pct_exact_last": pct,
         "approx": approx or None,
         "pairwise_variants": variants or None,
+        "larger_pair": large,
         "rgb_sad": ({"workload": "384x288 colour pairs, 16 depth numbers, RGB sum of absolute "
                                  "differences (untruncated), seeds (2, 0..7)", **rgb} if rgb else None),
         "copy_calibration": calib,
