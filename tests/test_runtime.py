@@ -106,3 +106,33 @@ def test_autotune_picks_a_candidate():
     for it in items:                      # the last trial left solved graphs
         rt.finish(it)
         assert it.energy == it.flow
+
+
+@pytest.mark.gpu
+def test_batched_full_mix_certificates(orc):
+    """The benchmark's batched workload at its full size: the seeded 64-pair
+    mix over 320x240x16, 384x288x16, 450x375x64 and 640x480x64, solved by
+    maxflow_solve_batch with default options (concurrent lanes).  Every pair
+    carries the optimality certificate energy = flow, its labels' energy
+    recomputed on the host from the oracle's cost volume equals it, and the
+    first pair of each 16-label shape equals the oracle's cut bit for bit."""
+    import torch
+    mix = rt.batch_mix(64, sg.BATCH_SHAPES, seed=4)
+    items = [rt.make_item(i, s, p) for i, (s, p) in enumerate(mix)]
+    times, total = rt.run_batched(items)
+    assert len(times) == 64 and all(0 < t <= total + 1e-3 for t in times)
+    checked = set()
+    for it, (spec, pair) in zip(items, mix):
+        assert it.energy == it.flow
+        lab = it.labels.cpu().numpy()
+        assert lab.min() >= 0 and lab.max() < spec.m
+        cost = orc.cost_volume(pair.left, pair.right, spec.m, spec.cap)
+        assert orc.energy(cost, lab, 1, spec.inhibit) == it.energy
+        if spec.m == 16 and (spec.w, spec.h) not in checked:
+            checked.add((spec.w, spec.h))
+            ref_lab, ref_flow, ref_e = orc.solve(cost, 1, spec.inhibit)
+            assert it.energy == ref_e and it.flow == ref_flow
+            assert (lab == ref_lab).all()
+        rt.release(it)
+    assert checked == {(320, 240), (384, 288)}
+    torch.cuda.synchronize()
