@@ -136,3 +136,36 @@ def test_batched_full_mix_certificates(orc):
         rt.release(it)
     assert checked == {(320, 240), (384, 288)}
     torch.cuda.synchronize()
+
+
+@pytest.mark.gpu
+def test_serving_full_size_certificates(orc):
+    """The benchmark's serving workload at full size: requests at 200/s over
+    384x288x16, 640x480x64 and 1280x720x128 pairs, served with the default
+    footprint lanes and captured sweep periods.  Every result carries energy
+    = flow, its labels' energy recomputed on the host equals it, and it is
+    the same cut as the pair solved alone."""
+    import torch
+    pools = {s: [(sg.spec_like(sg.MID, *s), sg.make_pair(sg.spec_like(sg.MID, *s), (5, k, i)))
+                 for i in range(2)] for k, s in enumerate(sg.SERVE_SHAPES)}
+    reqs = rt.poisson_requests(12, 200.0, sg.SERVE_SHAPES, 2, seed=5)
+    opts = gc.GcSolveOpts(flags=gc.GC_OPT_SWEEP_GRAPH)
+    done, wall, srv = rt.serve(reqs, pools, 200 << 30, opts, keep_labels=True)
+    assert len(done) == len(reqs) and srv.used == 0
+    cache = {}
+    for r in done:
+        key = (r.shape, r.pool_index)
+        spec, pair = pools[r.shape][r.pool_index]
+        if key not in cache:
+            cost = orc.cost_volume(pair.left, pair.right, spec.m, spec.cap)
+            p = gc.problem(spec.w, spec.h, spec.m, spec.cap, 1, spec.inhibit)
+            lab, _, e, f, _ = gc.solve_pair(torch.from_numpy(pair.left).cuda(),
+                                           torch.from_numpy(pair.right).cuda(), p, opts)
+            cache[key] = (orc.energy(cost, lab.cpu().numpy(), 1, spec.inhibit), lab.cpu().numpy(), e, f)
+            del cost
+        e_host, lab, e, f = cache[key]
+        assert e == f == e_host
+        assert r.item.energy == r.item.flow == e
+        assert (r.item.labels == lab).all()
+    assert {r.shape for r in done} == set(sg.SERVE_SHAPES)
+    torch.cuda.synchronize()
