@@ -285,6 +285,14 @@ def approx_level2_cut(skin: Graph, cost, labels, result, stream=None):
            "approx_level2_cut")
 
 
+# Relabel period of the two solves of an approximate cut when the caller
+# gives no options: the delegate-point graph and the thin skin are shallow,
+# their flow settles within a few dozen sweeps, and 32 measured 22-28 %
+# faster level-1 cuts on 384x288x16 than the exact solve's default of 64
+# (16 and 24 were slower again).  The cut itself does not depend on it.
+APPROX_RELABEL_PERIOD = 32
+
+
 def approx_level1(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, stream=None,
                   ws=None, ws_coarse=None, level: int = 1):
     """Delegate-point cut, then the cut inside the thin skin: exact (level 1)
@@ -293,6 +301,8 @@ def approx_level1(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = Non
     flow -1 and no fine stats."""
     import torch
     dev = cost.device
+    if opts is None:
+        opts = GcSolveOpts(relabel_period=APPROX_RELABEL_PERIOD)
     c = coarse_problem(p, block)
     ccost = torch.empty((c.labels, c.height, c.width), dtype=torch.int32, device=dev)
     clab = torch.empty((c.height, c.width), dtype=torch.int32, device=dev)
