@@ -94,8 +94,16 @@ def _load():
     lib.orc_approx_level1.restype = I
     lib.orc_brute_force_window.argtypes = [P, I, I, I, I, I, I, I, P, P, P, P]
     lib.orc_brute_force_window.restype = I
-    lib.orc_approx_level2.argtypes = [P, I, I, I, I, I, I, I, I, P, P, P]
+    lib.orc_approx_level2.argtypes = [P, I, I, I, I, I, I, I, I, I, P, P, P]
     lib.orc_approx_level2.restype = I
+    lib.orc_level2_skin.argtypes = [P, I, I, I, I, I, I, I, P, P, I, I, I, P, P, P, P]
+    lib.orc_level2_skin.restype = I
+    lib.orc_solve_window_max_side.argtypes = [P, I, I, I, I, I, I, I, P, P, P, P]
+    lib.orc_solve_window_max_side.restype = I
+    lib.orc_graph_push.argtypes = [P, I64, I64]
+    lib.orc_graph_push.restype = None
+    lib.orc_graph_find_arc.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.orc_graph_find_arc.restype = I64
     _lib = lib
     return lib
 
@@ -209,6 +217,17 @@ class Graph:
         lab = np.empty((self.h, self.w), dtype=np.int32)
         _check(self._lib.orc_labels_max_side(self._g, _ptr(lab)), "labels_max_side")
         return lab
+
+    def find_arc(self, u: int, v: int) -> int:
+        return int(self._lib.orc_graph_find_arc(self._g, int(u), int(v)))
+
+    def push(self, arc: int, delta: int):
+        """Moves delta along an arc with no feasibility check (for checker tests)."""
+        self._lib.orc_graph_push(self._g, int(arc), int(delta))
+
+    def node(self, x: int, y: int, k: int) -> int:
+        """Node id of level k (1..m-1) of site (x, y); 0 is s, 1 is t."""
+        return 2 + ((k - 1) * self.h + y) * self.w + x
 
     def check_flow(self, excess: np.ndarray | None = None) -> int:
         if excess is None:
@@ -325,7 +344,7 @@ def brute_force_window(cost: np.ndarray, lo: np.ndarray, hi: np.ndarray, pen_h: 
 
 
 def approx_level2(cost: np.ndarray, b: int, pen_h: int, inh_h: int, pen_v: int | None = None,
-                  inh_v: int | None = None):
+                  inh_v: int | None = None, wave_steps: int = 64):
     """Level-2 approximation (Sec. 4.5).  Returns (labels, energy, coarse labels)."""
     cost = np.ascontiguousarray(cost, dtype=np.int32)
     m, h, w = cost.shape
@@ -333,5 +352,42 @@ def approx_level2(cost: np.ndarray, b: int, pen_h: int, inh_h: int, pen_v: int |
     cl = np.empty((-(-h // b), -(-w // b)), dtype=np.int32)
     e = np.zeros(1, dtype=np.int64)
     _check(_load().orc_approx_level2(_ptr(cost), w, h, m, *_params(pen_h, inh_h, pen_v, inh_v),
-                                     int(b), _ptr(lab), _ptr(e), _ptr(cl)), "approx_level2")
+                                     int(b), int(wave_steps), _ptr(lab), _ptr(e), _ptr(cl)),
+           "approx_level2")
     return lab, int(e[0]), cl
+
+
+def level2_skin(cost: np.ndarray, lo: np.ndarray, hi: np.ndarray, b: int, wave_steps: int,
+                pen_h: int, inh_h: int, pen_v: int | None = None, inh_v: int | None = None,
+                blocks: bool = True):
+    """Level-2 cut inside given windows.  Returns (labels, excess, heights, block
+    rounds); excess and heights are the state after the wave, before the blocks,
+    as int64 [m-1][h][w] (heights >= 2**52 mean unreachable)."""
+    cost = np.ascontiguousarray(cost, dtype=np.int32)
+    m, h, w = cost.shape
+    lo = np.ascontiguousarray(lo, dtype=np.int32)
+    hi = np.ascontiguousarray(hi, dtype=np.int32)
+    lab = np.empty((h, w), dtype=np.int32)
+    ex = np.zeros((max(m - 1, 0), h, w), dtype=np.int64)
+    ht = np.zeros((max(m - 1, 0), h, w), dtype=np.int64)
+    rounds = np.zeros(1, dtype=np.int64)
+    _check(_load().orc_level2_skin(_ptr(cost), w, h, m, *_params(pen_h, inh_h, pen_v, inh_v),
+                                   _ptr(lo), _ptr(hi), int(b), int(wave_steps), int(bool(blocks)),
+                                   _ptr(lab), _ptr(ex), _ptr(ht), _ptr(rounds)), "level2_skin")
+    return lab, ex, ht, int(rounds[0])
+
+
+def solve_window_max_side(cost: np.ndarray, lo: np.ndarray, hi: np.ndarray, pen_h: int,
+                          inh_h: int, pen_v: int | None = None, inh_v: int | None = None):
+    """Back-most minimiser of E with lo <= X <= hi (maximal source side of a
+    Dinic max flow).  Returns (labels, flow)."""
+    cost = np.ascontiguousarray(cost, dtype=np.int32)
+    m, h, w = cost.shape
+    lo = np.ascontiguousarray(lo, dtype=np.int32)
+    hi = np.ascontiguousarray(hi, dtype=np.int32)
+    lab = np.empty((h, w), dtype=np.int32)
+    f = np.zeros(1, dtype=np.int64)
+    _check(_load().orc_solve_window_max_side(_ptr(cost), w, h, m,
+                                             *_params(pen_h, inh_h, pen_v, inh_v), _ptr(lo),
+                                             _ptr(hi), _ptr(lab), _ptr(f)), "solve_window_max_side")
+    return lab, int(f[0])

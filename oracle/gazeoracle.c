@@ -599,6 +599,22 @@ int orc_labels_max_side(const orc_graph *g, int32_t *labels)
     return rc;
 }
 
+/* Moves delta units along arc a of the residual graph with no check at all
+ * (tests use it to build infeasible flows for orc_check_flow). */
+void orc_graph_push(orc_graph *g, int64_t a, int64_t delta)
+{
+    g->res[a] -= delta;
+    g->res[g->rev[a]] += delta;
+}
+
+/* Index of the first arc from node u to node v, or -1. */
+int64_t orc_graph_find_arc(const orc_graph *g, int32_t u, int32_t v)
+{
+    for (int64_t a = g->first[u]; a < g->first[u + 1]; a++)
+        if (g->head[a] == v) return a;
+    return -1;
+}
+
 /* Feasibility of the current flow: 0 <= flow <= cap on every arc pair and
  * conservation at every grid node (excess given, or zero when NULL). */
 int orc_check_flow(const orc_graph *g, const int64_t *excess)
@@ -751,23 +767,40 @@ int orc_approx_level1(const int32_t *cost, int w, int h, int m, int pen_h, int i
 /* ------------------------------------------------------------------------ */
 /* Hierarchical approximation, level 2 (Sec. 4.5).                           */
 /*                                                                          */
-/* The wave-front pass runs over the whole thin skin and the push-relabel   */
-/* loop cuts every block separately.  Readings (the paper omits the         */
-/* details): the wave front is one pass down every column of the skin, from */
-/* its top to its bottom, in which each free node hands the chain arc below  */
-/* it as much of its excess as the arc's residual allows; a block is the     */
-/* b x b sites of one delegate point over the full depth of their skin (all */
-/* of them share one window), so only the arcs between delegate points go   */
-/* unused; each block's cut is its exact minimum cut read off as the         */
-/* minimal source side; a site's label is the deepest source-side node of   */
-/* its column.  Splitting the skin's depth into b-level blocks as well would */
-/* leave blocks in the middle of the skin without any sink.                  */
-/*                                                                          */
-/* State here is the skin with its terminals folded into node balances:     */
-/* bal[v] = capacity of arcs into v from forced-source nodes (and s) minus   */
-/* capacity of arcs from v to forced-sink nodes (and t); res[v][d] is the    */
-/* residual of the arc from v to its neighbour in direction d, kept only    */
-/* between two free nodes.                                                   */
+/* The wave-front fetch runs over the whole thin skin, as in level 1, and   */
+/* the push-relabel loop cuts every block (b x b x b cross points) on its    */
+/* own.  The paper omits the details; the readings here are:                 */
+/*   skin    the level-1 windows; levels outside them are folded into node   */
+/*           balances, so the state is a preflow on the skin's free nodes    */
+/*           with excess (positive balance) and deficits (negative);        */
+/*   wave    the wave-front pre-phase of Sec. 4.4 (an initialisation, then  */
+/*           A-1 wave steps): the initialisation gives every free node its   */
+/*           exact residual distance to                                      */
+/*           the nearest deficit (deficits at 1, unreachable at infinity);   */
+/*           each of the A-1 wave steps is synchronous: every node with      */
+/*           excess and finite height pushes, arc by arc in a fixed order,   */
+/*           min(excess, residual) to neighbours exactly one lower (heights  */
+/*           of the step's start), then every node that holds excess after   */
+/*           the inflow is merged is lifted to one above its lowest residual */
+/*           neighbour if that is higher (again the heights of the step's    */
+/*           start: a Jacobi step, so the result does not depend on the      */
+/*           order in which nodes are visited);                              */
+/*   block   the free nodes of the b x b sites of one delegate point whose   */
+/*           level k lies in the label group k / b (the node that carries    */
+/*           the chain arc of label k); its push-relabel loop uses the arcs  */
+/*           between its own nodes only and runs in rounds: exact in-block   */
+/*           distances to the block's deficits, stop if no node with excess  */
+/*           has a finite one, else 2n synchronous push / relabel steps of   */
+/*           the rule above (n = nodes of the block);                       */
+/*   cut     read off the final state as a push-relabel solver reads it      */
+/*           from its distances: a free node is on the sink side iff a       */
+/*           residual path leads from it to a node whose deficit is still    */
+/*           unfilled (the maximal source side), and X_v counts the source- */
+/*           side levels of the column (a prefix, through the unbounded      */
+/*           upward chain arcs).                                             */
+/* Once the state is a maximum preflow of the skin (a long enough wave, or   */
+/* blocks that cover the skin) this is the back-most minimum of E inside the */
+/* windows.                                                                  */
 /* ------------------------------------------------------------------------ */
 
 /* neighbour offsets (dk, dy, dx) of the 14 arcs of a node v_k */
@@ -777,6 +810,13 @@ static const int NB[14][3] = {
     {-1, 0, +1}, {+1, 0, +1}, {-1, 0, -1}, {+1, 0, -1}, /* E/W one level up/down */
     {-1, +1, 0}, {+1, +1, 0}, {-1, -1, 0}, {+1, -1, 0}  /* S/N one level up/down */
 };
+
+/* the direction of the arc from the neighbour back to v */
+static int nb_opposite(int d)
+{
+    static const int o[14] = {1, 0, 3, 2, 5, 4, 9, 8, 7, 6, 13, 12, 11, 10};
+    return o[d];
+}
 
 /* Capacity of the arc from v_k (site x, y) to its neighbour in direction d
  * (Sec. 3, Fig. 4): chain down g(k), chain up unbounded, same level h1,
@@ -793,160 +833,311 @@ static int64_t arc_cap(const int32_t *cost, int w, int h, int x, int y, int k, i
     return 0;
 }
 
-/* Tiny max-flow by shortest augmenting paths on a dense matrix. */
-static int64_t ek_maxflow(int n, int64_t *cap, int src, int snk, uint8_t *src_side)
+/* The skin: every level of the full layout, free or not. */
+typedef struct {
+    int w, h, m;
+    size_t ns, nn;
+    const int32_t *lo, *hi;
+    uint8_t *free_;         /* level inside its site's window */
+    int64_t *ex;            /* balance: excess > 0, deficit < 0 */
+    int64_t *res;           /* res[v*14 + d]: residual from v to its free neighbour in d */
+    int64_t *ht, *ht2, *ein;
+} skin_t;
+
+static size_t sk_node(const skin_t *s, int x, int y, int k)
 {
-    int64_t flow = 0;
-    int *prev = (int *)malloc(sizeof(int) * n), *q = (int *)malloc(sizeof(int) * n);
-    for (;;) {
-        for (int i = 0; i < n; i++) prev[i] = -1;
-        int qh = 0, qt = 0;
-        q[qt++] = src; prev[src] = src;
-        while (qh < qt && prev[snk] < 0) {
-            int u = q[qh++];
-            for (int v = 0; v < n; v++)
-                if (prev[v] < 0 && cap[(int64_t)u * n + v] > 0) { prev[v] = u; q[qt++] = v; }
-        }
-        if (prev[snk] < 0) break;
-        int64_t b = ORC_INF;
-        for (int v = snk; v != src; v = prev[v])
-            if (cap[(int64_t)prev[v] * n + v] < b) b = cap[(int64_t)prev[v] * n + v];
-        for (int v = snk; v != src; v = prev[v]) {
-            cap[(int64_t)prev[v] * n + v] -= b;
-            cap[(int64_t)v * n + prev[v]] += b;
-        }
-        flow += b;
-    }
-    /* minimal source side: reachable from src in the residual network */
-    for (int i = 0; i < n; i++) src_side[i] = prev[i] >= 0;
-    free(prev); free(q);
-    return flow;
+    return (((size_t)k - 1) * s->h + (size_t)y) * s->w + (size_t)x;
 }
 
+/* the free neighbour of v in direction d, or -1 */
+static int64_t sk_nbr(const skin_t *s, size_t v, int d)
+{
+    int k = (int)(v / s->ns) + 1;
+    int y = (int)((v % s->ns) / s->w), x = (int)(v % s->w);
+    int k2 = k + NB[d][0], y2 = y + NB[d][1], x2 = x + NB[d][2];
+    if (x2 < 0 || x2 >= s->w || y2 < 0 || y2 >= s->h || k2 < 1 || k2 > s->m - 1) return -1;
+    size_t u = sk_node(s, x2, y2, k2);
+    return s->free_[u] ? (int64_t)u : -1;
+}
+
+static void skin_free(skin_t *s)
+{
+    free(s->free_); free(s->ex); free(s->res); free(s->ht); free(s->ht2); free(s->ein);
+}
+
+/* Folds every arc between a free node and a forced one into the free
+ * node's balance: arcs from forced-source levels (and s) are saturated into
+ * its excess, arcs into forced-sink levels (and t) become its deficit. */
+static int skin_build(skin_t *s, const int32_t *cost, int w, int h, int m, int pen_h, int inh_h,
+                      int pen_v, int inh_v, const int32_t *lo, const int32_t *hi)
+{
+    memset(s, 0, sizeof(*s));
+    s->w = w; s->h = h; s->m = m; s->lo = lo; s->hi = hi;
+    s->ns = (size_t)w * h;
+    s->nn = s->ns * (size_t)(m - 1);
+    size_t n1 = s->nn ? s->nn : 1;
+    s->free_ = (uint8_t *)calloc(n1, 1);
+    s->ex = (int64_t *)calloc(n1, sizeof(int64_t));
+    s->res = (int64_t *)calloc(n1 * 14, sizeof(int64_t));
+    s->ht = (int64_t *)malloc(n1 * sizeof(int64_t));
+    s->ht2 = (int64_t *)malloc(n1 * sizeof(int64_t));
+    s->ein = (int64_t *)calloc(n1, sizeof(int64_t));
+    if (!s->free_ || !s->ex || !s->res || !s->ht || !s->ht2 || !s->ein) { skin_free(s); return ORC_E_NOMEM; }
+    for (int k = 1; k <= m - 1; k++)
+        for (int y = 0; y < h; y++)
+            for (int x = 0; x < w; x++)
+                s->free_[sk_node(s, x, y, k)] = k > lo[y * w + x] && k <= hi[y * w + x];
+    for (int k = 1; k <= m - 1; k++)
+        for (int y = 0; y < h; y++)
+            for (int x = 0; x < w; x++) {
+                size_t v = sk_node(s, x, y, k);
+                if (!s->free_[v]) continue;
+                if (k == 1) s->ex[v] += cost[(size_t)y * w + x];                         /* s -> v_1 */
+                if (k == m - 1) s->ex[v] -= cost[((size_t)(m - 1) * h + y) * w + x];    /* v_{m-1} -> t */
+                for (int d = 0; d < 14; d++) {
+                    int k2 = k + NB[d][0], y2 = y + NB[d][1], x2 = x + NB[d][2];
+                    if (x2 < 0 || x2 >= w || y2 < 0 || y2 >= h) continue;
+                    if (k2 < 1 || k2 > m - 1) continue;        /* the terminals: above */
+                    int64_t cout = arc_cap(cost, w, h, x, y, k, d, pen_h, inh_h, pen_v, inh_v);
+                    int64_t cin = d == 0 ? ORC_INF
+                                : d == 1 ? cost[((size_t)(k - 1) * h + y) * w + x]
+                                : arc_cap(cost, w, h, x2, y2, k2, nb_opposite(d), pen_h, inh_h,
+                                          pen_v, inh_v);
+                    if (k2 <= lo[y2 * w + x2]) s->ex[v] += cin;         /* from a forced-source level */
+                    else if (k2 > hi[y2 * w + x2]) s->ex[v] -= cout;    /* into a forced-sink level */
+                    else s->res[v * 14 + d] = cout;
+                }
+            }
+    return ORC_OK;
+}
+
+/* Exact residual distance of every free node to the nearest node with a
+ * deficit (which sit at 1), by breadth-first search backwards over residual
+ * arcs; ORC_INF where no deficit is reachable.  `in_block` (optional)
+ * restricts the search to arcs between nodes of one block id. */
+static int skin_distances(const skin_t *s, int64_t *dist, const int32_t *block_of, int32_t block,
+                          const size_t *members, size_t nmem)
+{
+    size_t count = members ? nmem : s->nn;
+    size_t *q = (size_t *)malloc((count ? count : 1) * sizeof(size_t));
+    if (!q) return ORC_E_NOMEM;
+    size_t qh = 0, qt = 0;
+    for (size_t i = 0; i < count; i++) {
+        size_t v = members ? members[i] : i;
+        dist[v] = ORC_INF;
+        if (s->free_[v] && s->ex[v] < 0) { dist[v] = 1; q[qt++] = v; }
+    }
+    while (qh < qt) {
+        size_t v = q[qh++];
+        for (int d = 0; d < 14; d++) {
+            int64_t u = sk_nbr(s, v, d);
+            if (u < 0) continue;
+            if (block_of && block_of[u] != block) continue;
+            if (dist[u] != ORC_INF) continue;
+            /* arc u -> v is the neighbour's arc in the opposite direction */
+            if (s->res[(size_t)u * 14 + nb_opposite(d)] > 0) { dist[u] = dist[v] + 1; q[qt++] = (size_t)u; }
+        }
+    }
+    free(q);
+    return ORC_OK;
+}
+
+/* One synchronous push / relabel step over the given nodes (all free nodes
+ * when members is NULL), using the arcs to nodes of the same block only
+ * when block_of is given. */
+static void skin_step(skin_t *s, int64_t *ht, const int32_t *block_of, int32_t block,
+                      const size_t *members, size_t nmem)
+{
+    size_t count = members ? nmem : s->nn;
+    /* push: heights of the step's start, arcs in direction order */
+    for (size_t i = 0; i < count; i++) s->ein[members ? members[i] : i] = 0;
+    for (size_t i = 0; i < count; i++) {
+        size_t v = members ? members[i] : i;
+        if (!s->free_[v] || s->ex[v] <= 0 || ht[v] >= ORC_INF) continue;
+        int64_t e = s->ex[v];
+        for (int d = 0; d < 14 && e > 0; d++) {
+            int64_t u = sk_nbr(s, v, d);
+            if (u < 0 || (block_of && block_of[u] != block)) continue;
+            int64_t r = s->res[v * 14 + d];
+            if (r > 0 && ht[u] == ht[v] - 1) {
+                int64_t delta = e < r ? e : r;
+                s->res[v * 14 + d] -= delta;
+                s->res[(size_t)u * 14 + nb_opposite(d)] += delta;
+                s->ein[u] += delta;
+                e -= delta;
+            }
+        }
+        s->ex[v] = e;
+    }
+    for (size_t i = 0; i < count; i++) {
+        size_t v = members ? members[i] : i;
+        s->ex[v] += s->ein[v];
+    }
+    /* relabel: neighbours' heights of the step's start */
+    for (size_t i = 0; i < count; i++) {
+        size_t v = members ? members[i] : i;
+        s->ht2[v] = ht[v];
+        if (!s->free_[v] || s->ex[v] <= 0 || ht[v] >= ORC_INF) continue;
+        int64_t hmin = ORC_INF;
+        for (int d = 0; d < 14; d++) {
+            int64_t u = sk_nbr(s, v, d);
+            if (u < 0 || (block_of && block_of[u] != block)) continue;
+            if (s->res[v * 14 + d] > 0 && ht[u] < hmin) hmin = ht[u];
+        }
+        int64_t nh = hmin >= ORC_INF ? ORC_INF : hmin + 1;
+        if (nh > ht[v]) s->ht2[v] = nh;
+    }
+    for (size_t i = 0; i < count; i++) {
+        size_t v = members ? members[i] : i;
+        ht[v] = s->ht2[v];
+    }
+}
+
+/* Maximal source side of the current state: labels X_v = lo + number of
+ * free levels of the column from which no residual path reaches a node with
+ * an unfilled deficit.  Those levels form a prefix of the column. */
+static int skin_labels_max_side(const skin_t *s, int32_t *labels)
+{
+    int rc = skin_distances(s, s->ht2, NULL, 0, NULL, 0);
+    if (rc != ORC_OK) return rc;
+    for (int y = 0; y < s->h; y++)
+        for (int x = 0; x < s->w; x++) {
+            int X = s->lo[y * s->w + x], seen_sink = 0;
+            for (int k = s->lo[y * s->w + x] + 1; k <= s->hi[y * s->w + x]; k++) {
+                int src = s->ht2[sk_node(s, x, y, k)] >= ORC_INF;
+                if (src) {
+                    if (seen_sink) return ORC_E_PREFIX;
+                    X = k;
+                } else {
+                    seen_sink = 1;
+                }
+            }
+            labels[y * s->w + x] = X;
+        }
+    return ORC_OK;
+}
+
+/* Push-relabel loop of every block on its own (rounds of exact in-block
+ * distances and 2n synchronous steps).  Returns ORC_E_TOO_BIG if a block
+ * needs more than max_rounds rounds. */
+static int skin_blocks(skin_t *s, int b, int max_rounds, int64_t *rounds_out)
+{
+    int w = s->w, h = s->h, m = s->m;
+    int wc = (w + b - 1) / b, hc = (h + b - 1) / b, gc = (m - 1) / b + 1;
+    size_t n1 = s->nn ? s->nn : 1;
+    int32_t *block_of = (int32_t *)malloc(n1 * sizeof(int32_t));
+    int64_t *bh = (int64_t *)malloc(n1 * sizeof(int64_t));
+    size_t *mem = (size_t *)malloc((size_t)b * b * b * sizeof(size_t));
+    if (!block_of || !bh || !mem) { free(block_of); free(bh); free(mem); return ORC_E_NOMEM; }
+    for (size_t v = 0; v < s->nn; v++) {
+        int k = (int)(v / s->ns) + 1;
+        int y = (int)((v % s->ns) / w), x = (int)(v % w);
+        block_of[v] = s->free_[v] ? (int32_t)(((k / b) * hc + y / b) * wc + x / b) : -1;
+        bh[v] = ORC_INF;
+    }
+    int rc = ORC_OK;
+    int64_t rounds_total = 0;
+    for (int G = 0; G < gc && rc == ORC_OK; G++)
+        for (int Y = 0; Y < hc && rc == ORC_OK; Y++)
+            for (int X = 0; X < wc && rc == ORC_OK; X++) {
+                int32_t id = (G * hc + Y) * wc + X;
+                size_t n = 0;
+                for (int k = G * b; k < G * b + b && k <= m - 1; k++) {
+                    if (k < 1) continue;
+                    for (int y = Y * b; y < Y * b + b && y < h; y++)
+                        for (int x = X * b; x < X * b + b && x < w; x++) {
+                            size_t v = sk_node(s, x, y, k);
+                            if (s->free_[v]) mem[n++] = v;
+                        }
+                }
+                if (n == 0) continue;
+                int round = 0;
+                for (;; round++) {
+                    if (round >= max_rounds) { rc = ORC_E_TOO_BIG; break; }
+                    if ((rc = skin_distances(s, bh, block_of, id, mem, n)) != ORC_OK) break;
+                    int active = 0;
+                    for (size_t i = 0; i < n; i++)
+                        if (s->ex[mem[i]] > 0 && bh[mem[i]] < ORC_INF) active = 1;
+                    if (!active) break;
+                    for (size_t t = 0; t < 2 * n; t++) skin_step(s, bh, block_of, id, mem, n);
+                }
+                rounds_total += round;
+            }
+    if (rounds_out) *rounds_out = rounds_total;
+    free(block_of); free(bh); free(mem);
+    return rc;
+}
+
+/* Level-2 cut inside given windows: the initialisation, wave_steps synchronous wave
+ * steps, then (if blocks) the block-separate push-relabel loops, then the
+ * read-out.  excess_out / height_out (optional, full-layout node arrays)
+ * receive the state after the wave and before the blocks; rounds_out the
+ * total number of block rounds. */
+int orc_level2_skin(const int32_t *cost, int w, int h, int m, int pen_h, int inh_h, int pen_v,
+                    int inh_v, const int32_t *lo, const int32_t *hi, int b, int wave_steps,
+                    int blocks, int32_t *labels, int64_t *excess_out, int64_t *height_out,
+                    int64_t *rounds_out)
+{
+    if (b < 1 || m < 2 || wave_steps < 0 || w < 0 || h < 0) return ORC_E_ARG;
+    for (int i = 0; i < w * h; i++)
+        if (lo[i] < 0 || hi[i] > m - 1 || lo[i] > hi[i]) return ORC_E_ARG;
+    skin_t s;
+    int rc = skin_build(&s, cost, w, h, m, pen_h, inh_h, pen_v, inh_v, lo, hi);
+    if (rc != ORC_OK) return rc;
+    rc = skin_distances(&s, s.ht, NULL, 0, NULL, 0);               /* initialisation */
+    for (int t = 1; t <= wave_steps && rc == ORC_OK; t++)            /* wave steps */
+        skin_step(&s, s.ht, NULL, 0, NULL, 0);
+    if (rc == ORC_OK && excess_out) memcpy(excess_out, s.ex, s.nn * sizeof(int64_t));
+    if (rc == ORC_OK && height_out) memcpy(height_out, s.ht, s.nn * sizeof(int64_t));
+    if (rounds_out) *rounds_out = 0;
+    if (rc == ORC_OK && blocks) rc = skin_blocks(&s, b, 4096, rounds_out);
+    if (rc == ORC_OK) rc = skin_labels_max_side(&s, labels);
+    skin_free(&s);
+    return rc;
+}
+
+/* Level-2 approximation: the coarse cut of level 1, its skin windows, then
+ * the level-2 cut inside them.  coarse_labels (optional) receives the first
+ * cut. */
 int orc_approx_level2(const int32_t *cost, int w, int h, int m, int pen_h, int inh_h,
-                      int pen_v, int inh_v, int b, int32_t *labels, int64_t *energy,
-                      int32_t *coarse_labels)
+                      int pen_v, int inh_v, int b, int wave_steps, int32_t *labels,
+                      int64_t *energy, int32_t *coarse_labels)
 {
     if (b < 1 || m < 2) return ORC_E_ARG;
     int wc = (w + b - 1) / b, hc = (h + b - 1) / b, mc = (m + b - 1) / b;
-    size_t ns = (size_t)w * h, nn = ns * (size_t)(m - 1);
+    size_t ns = (size_t)w * h;
     int32_t *cc = (int32_t *)malloc(((size_t)mc * wc * hc + 1) * sizeof(int32_t));
     int32_t *cl = (int32_t *)malloc(((size_t)wc * hc + 1) * sizeof(int32_t));
     int32_t *lo = (int32_t *)malloc((ns + 1) * sizeof(int32_t));
     int32_t *hi = (int32_t *)malloc((ns + 1) * sizeof(int32_t));
-    int64_t *bal = (int64_t *)calloc(nn + 1, sizeof(int64_t));
-    int64_t *res = (int64_t *)calloc(nn * 14 + 1, sizeof(int64_t));
-    uint8_t *in_s = (uint8_t *)calloc(nn + 1, 1);
     int rc = ORC_E_NOMEM;
-    if (!cc || !cl || !lo || !hi || !bal || !res || !in_s) goto done;
-    {
+    if (cc && cl && lo && hi) {
         int64_t f, e;
         rc = orc_coarse_cost(cost, w, h, m, b, cc);
         if (rc == ORC_OK)
             rc = orc_solve(cc, wc, hc, mc, b * b * pen_h, inh_h, b * b * pen_v, inh_v, 1, cl, &f, &e);
         if (rc == ORC_OK) rc = orc_skin_windows(cl, w, h, m, b, lo, hi);
-        if (rc != ORC_OK) goto done;
+        if (rc == ORC_OK)
+            rc = orc_level2_skin(cost, w, h, m, pen_h, inh_h, pen_v, inh_v, lo, hi, b, wave_steps, 1,
+                                 labels, NULL, NULL, NULL);
+        if (rc == ORC_OK) *energy = orc_energy(cost, labels, w, h, m, pen_h, inh_h, pen_v, inh_v);
+        if (rc == ORC_OK && coarse_labels) memcpy(coarse_labels, cl, (size_t)wc * hc * sizeof(int32_t));
     }
-#define NODE(x, y, k) ((((size_t)(k) - 1) * h + (y)) * w + (x))
-#define FREE(x, y, k) ((k) > lo[(y) * w + (x)] && (k) <= hi[(y) * w + (x)])
-    /* folded skin: balances and free-to-free residuals */
-    for (int k = 1; k <= m - 1; k++)
-        for (int y = 0; y < h; y++)
-            for (int x = 0; x < w; x++) {
-                if (!FREE(x, y, k)) continue;
-                size_t v = NODE(x, y, k);
-                for (int d = 0; d < 14; d++) {
-                    int k2 = k + NB[d][0], y2 = y + NB[d][1], x2 = x + NB[d][2];
-                    if (x2 < 0 || x2 >= w || y2 < 0 || y2 >= h) continue;
-                    int lat = NB[d][1] != 0 || NB[d][2] != 0;
-                    if (lat && (k2 < 1 || k2 > m - 1)) continue;     /* no lateral arc to s or t */
-                    int64_t cout = arc_cap(cost, w, h, x, y, k, d, pen_h, inh_h, pen_v, inh_v);
-                    /* capacity of the arc back from the neighbour */
-                    int64_t cin;
-                    if (d == 0) cin = ORC_INF;
-                    else if (d == 1) cin = cost[((int64_t)(k - 1) * h + y) * w + x];
-                    else cin = arc_cap(cost, w, h, x2, y2, k2, d ^ ((d >= 2 && d <= 5) ? 1 : 0),
-                                       pen_h, inh_h, pen_v, inh_v);
-                    if (d >= 6) {
-                        /* opposite of a diagonal: one level the other way */
-                        int up = NB[d][0] < 0;
-                        int horiz = NB[d][1] == 0;
-                        cin = up ? 0 : (horiz ? inh_h : inh_v);
-                    }
-                    int src = k2 <= (k2 >= 1 && k2 <= m - 1 ? lo[y2 * w + x2] : 0) || k2 == 0;
-                    int snk = k2 == m || (k2 >= 1 && k2 <= m - 1 && k2 > hi[y2 * w + x2]);
-                    if (src) bal[v] += cin;
-                    else if (snk) bal[v] -= cout;
-                    else res[v * 14 + d] = cout;
-                }
-            }
-    /* wave front: one pass down every column of the skin */
-    for (int y = 0; y < h; y++)
-        for (int x = 0; x < w; x++)
-            for (int k = lo[y * w + x] + 1; k < hi[y * w + x]; k++) {
-                size_t v = NODE(x, y, k), u = NODE(x, y, k + 1);
-                int64_t d = bal[v] < res[v * 14 + 0] ? bal[v] : res[v * 14 + 0];
-                if (d <= 0) continue;
-                bal[v] -= d; bal[u] += d;
-                res[v * 14 + 0] -= d;
-                /* the reverse (upward) arc is unbounded either way */
-            }
-    /* every block on its own */
-    {
-        int cap_nodes = b * b * (m - 1) + 2;
-        int64_t *C = (int64_t *)malloc(sizeof(int64_t) * cap_nodes * cap_nodes);
-        uint8_t *side = (uint8_t *)malloc(cap_nodes);
-        size_t *ids = (size_t *)malloc(sizeof(size_t) * cap_nodes);
-        int *kx = (int *)malloc(sizeof(int) * cap_nodes * 3);
-        if (!C || !side || !ids || !kx) { free(C); free(side); free(ids); free(kx); rc = ORC_E_NOMEM; goto done; }
-        for (int Y = 0; Y < hc; Y++)
-            for (int X = 0; X < wc; X++) {
-                int n = 0;
-                for (int k = 1; k <= m - 1; k++)
-                    for (int y = Y * b; y < Y * b + b && y < h; y++)
-                        for (int x = X * b; x < X * b + b && x < w; x++)
-                            if (FREE(x, y, k)) {
-                                ids[n] = NODE(x, y, k);
-                                kx[3 * n] = k; kx[3 * n + 1] = y; kx[3 * n + 2] = x;
-                                n++;
-                            }
-                if (n == 0) continue;
-                int N2 = n + 2, S = n, T = n + 1;
-                memset(C, 0, sizeof(int64_t) * N2 * N2);
-                for (int i = 0; i < n; i++) {
-                    size_t v = ids[i];
-                    if (bal[v] > 0) C[(int64_t)S * N2 + i] = bal[v];
-                    if (bal[v] < 0) C[(int64_t)i * N2 + T] = -bal[v];
-                    for (int d = 0; d < 14; d++) {
-                        int k2 = kx[3 * i] + NB[d][0], y2 = kx[3 * i + 1] + NB[d][1],
-                            x2 = kx[3 * i + 2] + NB[d][2];
-                        for (int j2 = 0; j2 < n; j2++)
-                            if (kx[3 * j2] == k2 && kx[3 * j2 + 1] == y2 && kx[3 * j2 + 2] == x2) {
-                                int64_t r = d == 1 ? ORC_INF : res[v * 14 + d];
-                                C[(int64_t)i * N2 + j2] += r;
-                            }
-                    }
-                }
-                ek_maxflow(N2, C, S, T, side);
-                for (int i = 0; i < n; i++) in_s[ids[i]] = side[i];
-            }
-        free(C); free(side); free(ids); free(kx);
-    }
-    /* deepest source-side node of every column */
-    for (int y = 0; y < h; y++)
-        for (int x = 0; x < w; x++) {
-            int X = lo[y * w + x];
-            for (int k = lo[y * w + x] + 1; k <= hi[y * w + x]; k++)
-                if (in_s[NODE(x, y, k)]) X = k;
-            labels[y * w + x] = X;
-        }
-#undef NODE
-#undef FREE
-    *energy = orc_energy(cost, labels, w, h, m, pen_h, inh_h, pen_v, inh_v);
-    if (coarse_labels) memcpy(coarse_labels, cl, (size_t)wc * hc * sizeof(int32_t));
-    rc = ORC_OK;
-done:
-    free(cc); free(cl); free(lo); free(hi); free(bal); free(res); free(in_s);
+    free(cc); free(cl); free(lo); free(hi);
+    return rc;
+}
+
+/* Back-most minimiser of E inside per-site windows: the maximal source side
+ * of a maximum flow (Dinic) on the windowed graph. */
+int orc_solve_window_max_side(const int32_t *cost, int w, int h, int m, int pen_h, int inh_h,
+                              int pen_v, int inh_v, const int32_t *lo, const int32_t *hi,
+                              int32_t *labels, int64_t *flow)
+{
+    orc_graph *g = orc_graph_build_window(cost, w, h, m, pen_h, inh_h, pen_v, inh_v, lo, hi);
+    if (!g) return ORC_E_NOMEM;
+    int rc = orc_maxflow_dinic(g, flow);
+    if (rc == ORC_OK) rc = orc_labels_max_side(g, labels);
+    orc_graph_free(g);
     return rc;
 }
 

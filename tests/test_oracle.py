@@ -301,6 +301,28 @@ def test_two_maxflow_algorithms_agree_and_flows_are_feasible(orc, seed):
     assert g1.cut_capacity(l1) == f1
 
 
+def test_flow_checker_rejects_infeasible_flows(orc):
+    """The feasibility check is fed flows that break it: an arc pushed past
+    its capacity (negative residual) and a unit moved along a residual arc
+    with the node balances left as they were (conservation)."""
+    p = sg.make_pair(sg.TINY, (1, 0))
+    cost = orc.cost_volume(p.left, p.right, 8, 20)
+    g = orc.Graph(cost, 1, 1023)
+    g.maxflow_dinic()
+    assert g.check_flow() == 0
+    # same-level arc between two grid nodes (capacity = penalty 1 each way)
+    a = g.find_arc(g.node(5, 7, 3), g.node(6, 7, 3))
+    assert a >= 0
+    g.push(a, 1)                      # within [0, 2] either way: still a pair flow
+    assert g.check_flow() == 4        # ... but two nodes now have a net balance
+    g.push(a, -1)
+    assert g.check_flow() == 0
+    g.push(a, 3)                      # 3 > the pair total of 2: a negative residual
+    assert g.check_flow() == 3
+    g.push(a, -3)
+    assert g.check_flow() == 0
+
+
 def test_reconstruction_without_noise(orc):
     """sigma = 0, lambda = 1: on fronto-parallel textured scenes the exact cut
     recovers the true depth numbers (pinned for these seeds: a coincidental
