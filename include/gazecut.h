@@ -232,6 +232,23 @@ int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *stats, vo
 int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *labels,
                    int64_t *result, void *stream);
 
+/* Copies a graph's state out in a documented layout, for checking it
+ * independently of the library (e.g. the certificate of a maximum preflow:
+ * capacity bounds, conservation against the build, no residual path from an
+ * excess to a deficit).  excess: DEVICE int32 [labels-1][height][width], the
+ * node balances with the terminal arcs folded in as in Sec. 4.4 (v_1 starts
+ * at +g(0), v_{m-1} at -g(m-1)).  words: DEVICE int32
+ * [7][labels-1][height][width], the stored residual of one arc of each arc
+ * pair, in this order (E = x+1, S = y+1; pair totals in brackets):
+ *   0 v_k -> v_{k+1}  (reverse unbounded)   1 v_k -> E_k   (2 penalty_h)
+ *   2 v_k -> S_k      (2 penalty_v)         3 v_k -> E_{k-1} (inhibit_h)
+ *   4 v_k -> E_{k+1}  (inhibit_h)           5 v_k -> S_{k-1} (inhibit_v)
+ *   6 v_k -> S_{k+1}  (inhibit_v)
+ * Words of arcs that do not exist (image border, k out of range) are 0.  For
+ * a thin-skin graph the levels outside the windows are inert and their
+ * entries carry no meaning.  Errors: GC_E_ARG, GC_E_HIP. */
+int gc_graph_state(const gc_graph *g, int32_t *excess, int32_t *words, void *stream);
+
 /* ------------------------------------------------------------------------
  * Hierarchical approximation, level 1 (Sec. 4.5).  b x b x b neighbouring
  * cross points form one delegate point; a first exact cut on the delegate
@@ -273,24 +290,38 @@ int graph_build_window(const gc_problem *p, const int32_t *cost, const int32_t *
                        int32_t block, void *ws, size_t ws_bytes, gc_graph *g_out, void *stream);
 
 /* Level-2 approximation (Sec. 4.5) on a thin-skin graph from
- * graph_build_window (block size b = skin->window_block, 1 <= b <= 3): the
- * wave-front pass covers the whole skin and the push-relabel loop cuts every
- * block separately.  Readings (the paper omits the details): the wave front
- * is one pass down every column of the skin in which each free node hands
- * the chain arc below it as much of its excess as the arc allows; a block is
- * the b x b sites of one delegate point over the full depth of their skin,
- * so only the arcs between delegate points go unused; each block is cut
- * exactly, read off as its minimal source side; a site's label is the
- * deepest source-side node of its column.  Used instead of maxflow_solve +
- * extract_labels on the skin.
- * cost:   DEVICE int32 [labels][height][width], the full data term.
- * labels: DEVICE int32 [height][width], written.
- * result: DEVICE int64[2], written: result[0] = E(labels) from its
- *         definition, result[1] = -1 (no global cut value exists).
- * The skin's state is consumed.  Errors: GC_E_ARG (not a thin-skin graph or
- * b > 3), GC_E_NOT_CONVERGED, GC_E_HIP. */
-int approx_level2_cut(gc_graph *skin, const int32_t *cost, int32_t *labels, int64_t *result,
-                      void *stream);
+ * graph_build_window (block size b = skin->window_block, 1 <= b <= 4): the
+ * wave-front pre-phase covers the whole skin and the push-relabel loop cuts
+ * every block separately.  Readings (the paper omits the details):
+ *   - the wave front is an initialisation (exact residual distances to the
+ *     deficits) and `wave_steps` synchronous steps over the skin: every node
+ *     with excess and a finite height pushes, arc by arc in a fixed order,
+ *     to neighbours exactly one below, then every node holding excess is
+ *     lifted to one above its lowest residual neighbour (heights of the
+ *     step's start: the result does not depend on the schedule);
+ *   - a block is the b x b x b cross points of one delegate point: the free
+ *     levels k with k / b equal to one label group, over the b x b sites of
+ *     the delegate point; its push-relabel loop uses only the arcs between
+ *     its own nodes and runs rounds (exact in-block distances, then 2n
+ *     synchronous steps of the same rule, n its nodes) until no node with
+ *     excess reaches an in-block deficit;
+ *   - the cut is read as the maximal source side of the final state: a
+ *     level is on the sink side iff a residual path leads from it to an
+ *     unfilled deficit.
+ * With a wave long enough to reach a maximum preflow the result is the
+ * back-most minimum of E inside the windows.
+ * cost:          DEVICE int32 [labels][height][width], the full data term.
+ * coarse_labels: DEVICE int32 [ceil(h/b)][ceil(w/b)], the delegate labels
+ *                the skin was built from.
+ * wave_steps:    A-1 >= 0 (64 recommended; see the benchmark record).
+ * labels:        DEVICE int32 [height][width], written.
+ * result:        DEVICE int64[2], written: result[0] = E(labels) from its
+ *                definition, result[1] = -1 (no global cut value exists).
+ * The skin's state is consumed.  Errors: GC_E_ARG (not a thin-skin graph,
+ * b^3 > 64, wave_steps < 0), GC_E_NOT_CONVERGED (a block needed more than
+ * 4096 rounds), GC_E_PREFIX, GC_E_HIP. */
+int approx_level2_cut(gc_graph *skin, const int32_t *cost, const int32_t *coarse_labels,
+                      int32_t wave_steps, int32_t *labels, int64_t *result, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batched solve.  Many graphs of any sizes (full or thin-skin) are solved

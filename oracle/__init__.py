@@ -104,6 +104,10 @@ def _load():
     lib.orc_graph_push.restype = None
     lib.orc_graph_find_arc.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.orc_graph_find_arc.restype = I64
+    lib.orc_certify_state.argtypes = [P, I, I, I, I, I, I, I, P, P, P, P, P]
+    lib.orc_certify_state.restype = I
+    lib.orc_graph_export_state.argtypes = [P, P, P, P]
+    lib.orc_graph_export_state.restype = I
     _lib = lib
     return lib
 
@@ -228,6 +232,16 @@ class Graph:
     def node(self, x: int, y: int, k: int) -> int:
         """Node id of level k (1..m-1) of site (x, y); 0 is s, 1 is t."""
         return 2 + ((k - 1) * self.h + y) * self.w + x
+
+    def export_state(self, excess: np.ndarray | None = None):
+        """(balances int32 [m-1][h][w], words int32 [7][m-1][h][w]) of the
+        current flow or preflow in the overflow form (see certify_state)."""
+        ex = np.zeros((self.m - 1, self.h, self.w), dtype=np.int32)
+        words = np.zeros((7, self.m - 1, self.h, self.w), dtype=np.int32)
+        exa = None if excess is None else np.ascontiguousarray(excess, dtype=np.int64)
+        _check(self._lib.orc_graph_export_state(self._g, None if exa is None else _ptr(exa),
+                                                _ptr(ex), _ptr(words)), "export_state")
+        return ex, words
 
     def check_flow(self, excess: np.ndarray | None = None) -> int:
         if excess is None:
@@ -391,3 +405,30 @@ def solve_window_max_side(cost: np.ndarray, lo: np.ndarray, hi: np.ndarray, pen_
                                              *_params(pen_h, inh_h, pen_v, inh_v), _ptr(lo),
                                              _ptr(hi), _ptr(lab), _ptr(f)), "solve_window_max_side")
     return lab, int(f[0])
+
+
+CERT_CODES = {0: "ok", 1: "residual out of bounds", 2: "conservation", 3: "not a maximum preflow",
+              4: "labels differ from the minimal source side", 5: "flow value differs from E(labels)"}
+
+
+def certify_state(cost: np.ndarray, ex: np.ndarray, words: np.ndarray, labels: np.ndarray,
+                  pen_h: int, inh_h: int, pen_v: int | None = None, inh_v: int | None = None):
+    """Independent certificate of a solved full graph given in the library's
+    exported layout (balances [m-1][h][w], pair words [7][m-1][h][w]).
+    Returns (code, flow, energy); code 0 means: capacity bounds and
+    conservation hold, no excess reaches a deficit, the labels are the
+    minimal source side and max-flow = E(labels)."""
+    cost = np.ascontiguousarray(cost, dtype=np.int32)
+    m, h, w = cost.shape
+    ex = np.ascontiguousarray(ex, dtype=np.int32)
+    words = np.ascontiguousarray(words, dtype=np.int32)
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    if ex.size != (m - 1) * h * w or words.size != 7 * ex.size or labels.size != h * w:
+        raise ValueError("state arrays do not match the cost volume's shape")
+    f = np.zeros(1, dtype=np.int64)
+    e = np.zeros(1, dtype=np.int64)
+    rc = _load().orc_certify_state(_ptr(cost), w, h, m, *_params(pen_h, inh_h, pen_v, inh_v),
+                                   _ptr(ex), _ptr(words), _ptr(labels), _ptr(f), _ptr(e))
+    if rc < 0:
+        raise RuntimeError(f"oracle certify_state failed with status {rc}")
+    return rc, int(f[0]), int(e[0])

@@ -1257,3 +1257,203 @@ int orc_scanline_dp(const int32_t *cost, int w, int m, int pen, int inh,
     *min_energy = emin;
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Certificate of a solved state in the library's exported layout.           */
+/*                                                                          */
+/* The state of a full graph (no windows) is given as the balance of every  */
+/* node, ex[(k-1)][y][x], and seven stored pair words per node, each an     */
+/* int32 [m-1][h][w] array, in this order:                                   */
+/*   0 rd   residual of v_k -> v_{k+1} (the data chain; its reverse is      */
+/*          unbounded)                                                       */
+/*   1 re   residual of v_k -> E_k     (pair total 2 * penalty_h)            */
+/*   2 rs   residual of v_k -> S_k     (pair total 2 * penalty_v)            */
+/*   3 rem  residual of v_k -> E_{k-1} (pair total inhibit_h; capacity)     */
+/*   4 rep  residual of v_k -> E_{k+1} (pair total inhibit_h; capacity 0)   */
+/*   5 rsm  residual of v_k -> S_{k-1} (pair total inhibit_v; capacity)     */
+/*   6 rsp  residual of v_k -> S_{k+1} (pair total inhibit_v; capacity 0)   */
+/* E = (x+1, y), S = (x, y+1).  The terminal arcs are folded into balances  */
+/* as in Sec. 4.4: v_1 starts at +g(0), v_{m-1} at -g(m-1).  Everything is    */
+/* recomputed here from the definition of the layered graph (Sec. 3,        */
+/* Fig. 4); nothing is taken from the solver but the state itself.           */
+/* ------------------------------------------------------------------------ */
+
+#define CERT_OK 0
+#define CERT_E_BOUNDS 1        /* a residual outside [0, pair total]              */
+#define CERT_E_CONSERVATION 2  /* a balance differs from build + net inflow       */
+#define CERT_E_NOT_MAXIMUM 3   /* a residual path joins an excess to a deficit    */
+#define CERT_E_LABELS 4        /* labels differ from the minimal source side      */
+#define CERT_E_VALUE 5         /* flow value differs from E(labels)               */
+
+/* Out-residual of v_k (site x, y) towards its neighbour in direction d (NB
+ * order), or -1 when the arc does not exist.  INF for the chain's upward arc. */
+static int64_t cert_residual(const int32_t *const *wd, int w, int h, int m, int x, int y, int k,
+                             int d, int pen_h, int inh_h, int pen_v, int inh_v)
+{
+    int k2 = k + NB[d][0], y2 = y + NB[d][1], x2 = x + NB[d][2];
+    if (x2 < 0 || x2 >= w || y2 < 0 || y2 >= h || k2 < 1 || k2 > m - 1) return -1;
+    size_t here = (((size_t)k - 1) * h + y) * w + x;
+    size_t there = (((size_t)k2 - 1) * h + y2) * w + x2;
+    switch (d) {
+    case 0: return wd[0][here];                        /* down the chain */
+    case 1: return ORC_INF;                            /* up the chain */
+    case 2: return wd[1][here];                        /* E */
+    case 3: return 2 * (int64_t)pen_h - wd[1][there];  /* W: the pair is stored at W */
+    case 4: return wd[2][here];                        /* S */
+    case 5: return 2 * (int64_t)pen_v - wd[2][there];  /* N */
+    case 6: return wd[3][here];                        /* E one level up */
+    case 7: return wd[4][here];                        /* E one level down */
+    case 8: return (int64_t)inh_h - wd[4][there];      /* W one up: stored at W_{k-1} as its E_{k} */
+    case 9: return (int64_t)inh_h - wd[3][there];      /* W one down: stored at W_{k+1} as its E_{k} */
+    case 10: return wd[5][here];                       /* S one level up */
+    case 11: return wd[6][here];                       /* S one level down */
+    case 12: return (int64_t)inh_v - wd[6][there];     /* N one up: stored at N_{k-1} as its S_{k} */
+    default: return (int64_t)inh_v - wd[5][there];     /* N one down: stored at N_{k+1} as its S_{k} */
+    }
+}
+
+/* Checks, in order: (1) every stored word lies in [0, pair total] (the
+ * chain word only >= 0: its reverse is unbounded); (2) every balance equals
+ * the terminal-arc balance of the build plus the net inflow implied by the
+ * words (flow on an arc = capacity - residual); (3) no residual path leads
+ * from a node with excess to a node with a deficit (so the preflow is a
+ * maximum one); (4) the labels equal the minimal source side (residual
+ * reachability from the excess nodes) and (5) the flow value, the sink-arc
+ * capacity minus the unfilled deficits, equals E(labels).  flow_out and
+ * energy_out receive the recomputed values (when not NULL).  Returns
+ * CERT_OK or the number of the first failed check. */
+int orc_certify_state(const int32_t *cost, int w, int h, int m, int pen_h, int inh_h, int pen_v,
+                      int inh_v, const int32_t *ex, const int32_t *words, const int32_t *labels,
+                      int64_t *flow_out, int64_t *energy_out)
+{
+    if (m < 2 || w < 1 || h < 1) return ORC_E_ARG;
+    size_t ns = (size_t)w * h, nn = ns * (size_t)(m - 1);
+    const int32_t *wd[7];
+    for (int i = 0; i < 7; i++) wd[i] = words + (size_t)i * nn;
+    const int64_t total[7] = {-1, 2 * (int64_t)pen_h, 2 * (int64_t)pen_v, inh_h, inh_h, inh_v, inh_v};
+    /* (1) bounds; a word of an arc that does not exist is not looked at */
+    for (int k = 1; k <= m - 1; k++)
+        for (int y = 0; y < h; y++)
+            for (int x = 0; x < w; x++) {
+                size_t v = (((size_t)k - 1) * h + y) * w + x;
+                const int exists[7] = {k + 1 <= m - 1, x + 1 < w, y + 1 < h, x + 1 < w && k >= 2,
+                                       x + 1 < w && k + 1 <= m - 1, y + 1 < h && k >= 2,
+                                       y + 1 < h && k + 1 <= m - 1};
+                for (int i = 0; i < 7; i++) {
+                    if (!exists[i]) continue;
+                    if (wd[i][v] < 0) return CERT_E_BOUNDS;
+                    if (total[i] >= 0 && wd[i][v] > total[i]) return CERT_E_BOUNDS;
+                }
+            }
+    /* (2) conservation: balance = build balance + inflow - outflow; each
+     * arc pair's flow is counted once, from the end that stores its word */
+    int64_t *net = (int64_t *)calloc(nn ? nn : 1, sizeof(int64_t));
+    if (!net) return ORC_E_NOMEM;
+    int64_t sink_cap = 0;
+    for (int y = 0; y < h; y++)
+        for (int x = 0; x < w; x++) {
+            net[((size_t)0 * h + y) * w + x] += cost[(size_t)y * w + x];
+            int64_t gt = cost[((size_t)(m - 1) * h + y) * w + x];
+            net[(((size_t)m - 2) * h + y) * w + x] -= gt;
+            sink_cap += gt;
+        }
+    for (int k = 1; k <= m - 1; k++)
+        for (int y = 0; y < h; y++)
+            for (int x = 0; x < w; x++) {
+                size_t v = (((size_t)k - 1) * h + y) * w + x;
+                /* stored words: (direction, capacity from v) */
+                const int dirs[7] = {0, 2, 4, 6, 7, 10, 11};
+                for (int i = 0; i < 7; i++) {
+                    int d = dirs[i];
+                    int k2 = k + NB[d][0], y2 = y + NB[d][1], x2 = x + NB[d][2];
+                    if (x2 < 0 || x2 >= w || y2 < 0 || y2 >= h || k2 < 1 || k2 > m - 1) continue;
+                    size_t u = (((size_t)k2 - 1) * h + y2) * w + x2;
+                    int64_t cap = d == 0 ? cost[((size_t)k * h + y) * w + x]
+                                : d == 2 ? pen_h : d == 4 ? pen_v
+                                : d == 6 ? inh_h : d == 10 ? inh_v : 0;
+                    int64_t flow = cap - wd[i][v];     /* from v to u (negative: u to v) */
+                    net[v] -= flow;
+                    net[u] += flow;
+                }
+            }
+    for (size_t v = 0; v < nn; v++)
+        if (net[v] != ex[v]) { free(net); return CERT_E_CONSERVATION; }
+    free(net);
+    /* (3) + (4): residual reachability from the excess nodes */
+    uint8_t *mark = (uint8_t *)calloc(nn ? nn : 1, 1);
+    size_t *q = (size_t *)malloc((nn ? nn : 1) * sizeof(size_t));
+    if (!mark || !q) { free(mark); free(q); return ORC_E_NOMEM; }
+    size_t qh = 0, qt = 0;
+    for (size_t v = 0; v < nn; v++)
+        if (ex[v] > 0) { mark[v] = 1; q[qt++] = v; }
+    int rc = CERT_OK;
+    while (qh < qt && rc == CERT_OK) {
+        size_t v = q[qh++];
+        if (ex[v] < 0) { rc = CERT_E_NOT_MAXIMUM; break; }
+        int k = (int)(v / ns) + 1, y = (int)((v % ns) / w), x = (int)(v % w);
+        for (int d = 0; d < 14; d++) {
+            int64_t r = cert_residual(wd, w, h, m, x, y, k, d, pen_h, inh_h, pen_v, inh_v);
+            if (r <= 0) continue;
+            size_t u = (((size_t)(k + NB[d][0]) - 1) * h + (y + NB[d][1])) * w + (x + NB[d][2]);
+            if (!mark[u]) { mark[u] = 1; q[qt++] = u; }
+        }
+    }
+    if (rc == CERT_OK)
+        for (int y = 0; y < h && rc == CERT_OK; y++)
+            for (int x = 0; x < w; x++) {
+                int X = 0;
+                while (X < m - 1 && mark[(((size_t)X) * h + y) * w + x]) X++;
+                for (int k = X + 2; k <= m - 1; k++)          /* the rest must be off */
+                    if (mark[(((size_t)k - 1) * h + y) * w + x]) rc = CERT_E_LABELS;
+                if (labels[(size_t)y * w + x] != X) rc = CERT_E_LABELS;
+            }
+    free(mark); free(q);
+    if (rc != CERT_OK) return rc;
+    /* (5) max-flow value = min-cut value */
+    int64_t unfilled = 0;
+    for (size_t v = 0; v < nn; v++) if (ex[v] < 0) unfilled -= ex[v];
+    int64_t flow = sink_cap - unfilled;
+    int64_t e = orc_energy(cost, labels, w, h, m, pen_h, inh_h, pen_v, inh_v);
+    if (flow_out) *flow_out = flow;
+    if (energy_out) *energy_out = e;
+    return flow == e ? CERT_OK : CERT_E_VALUE;
+}
+
+/* The state of the oracle's own graph in the layout above: the residuals of
+ * the grid arcs, and as balances the residuals left on the terminal arcs
+ * (s -> v_1 positive, v_{m-1} -> t negative) plus the excess a preflow holds
+ * at grid nodes (`excess`, indexed by graph node, NULL for a flow), which is
+ * the same preflow in the overflow form of Sec. 4.4. */
+int orc_graph_export_state(const orc_graph *g, const int64_t *excess, int32_t *ex, int32_t *words)
+{
+    if (g->lo || g->m < 2) return ORC_E_ARG;
+    int w = g->w, h = g->h, m = g->m;
+    size_t nn = (size_t)w * h * (size_t)(m - 1);
+    memset(ex, 0, nn * sizeof(int32_t));
+    memset(words, 0, 7 * nn * sizeof(int32_t));
+    const int dirs[7] = {0, 2, 4, 6, 7, 10, 11};
+    for (int k = 1; k <= m - 1; k++)
+        for (int y = 0; y < h; y++)
+            for (int x = 0; x < w; x++) {
+                size_t v = (((size_t)k - 1) * h + y) * w + x;
+                int32_t id = node_id(w, h, x, y, k);
+                if (excess) ex[v] += (int32_t)excess[id];
+                if (k == 1) {
+                    int64_t a = orc_graph_find_arc(g, 0, id);
+                    ex[v] += (int32_t)g->res[a];
+                }
+                if (k == m - 1) {
+                    int64_t a = orc_graph_find_arc(g, id, 1);
+                    ex[v] -= (int32_t)g->res[a];
+                }
+                for (int i = 0; i < 7; i++) {
+                    int d = dirs[i];
+                    int k2 = k + NB[d][0], y2 = y + NB[d][1], x2 = x + NB[d][2];
+                    if (x2 < 0 || x2 >= w || y2 < 0 || y2 >= h || k2 < 1 || k2 > m - 1) continue;
+                    int64_t a = orc_graph_find_arc(g, id, node_id(w, h, x2, y2, k2));
+                    if (a < 0) return ORC_E_ARG;
+                    words[(size_t)i * nn + v] = (int32_t)g->res[a];
+                }
+            }
+    return ORC_OK;
+}

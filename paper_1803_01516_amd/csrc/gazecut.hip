@@ -1075,11 +1075,14 @@ __global__ void k_zero_result(int64_t *r, DevHeader *h)
     if (threadIdx.x == 0) { r[0] = 0; r[1] = 0; if (h) h->prefix_err = 0; }
 }
 
-// Labels from the reachability values: X = source-side nodes in the column,
-// which must form the prefix v_1..v_X.  In a thin-skin graph the levels at
-// or above the window's top are source side by construction.
+// Labels: X = source-side nodes in the column, which must form the prefix
+// v_1..v_X.  from_aux: a node is on the source side when the reachability
+// relaxation reached it (aux == 0, minimal source side); otherwise when no
+// deficit is reachable from it (infinite distance in ht, maximal source
+// side).  In a thin-skin graph the levels at or above the window's top are
+// source side by construction.
 __global__ void __launch_bounds__(kBlock)
-k_labels(Graph s, int32_t *__restrict__ labels)
+k_labels(Graph s, int32_t *__restrict__ labels, int from_aux)
 {
     int64_t site = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (site >= s.plane) return;
@@ -1087,7 +1090,8 @@ k_labels(Graph s, int32_t *__restrict__ labels)
     int X = lo;
     bool gap = false, bad = false;
     for (int j = lo; j < hi; ++j) {
-        bool in = s.aux[(int64_t)j * s.plane + site] == 0;
+        const int64_t n = (int64_t)j * s.plane + site;
+        bool in = from_aux ? s.aux[n] == 0 : s.ht[n] >= kInf;
         if (in) { if (gap) bad = true; ++X; }
         else gap = true;
     }
@@ -1219,11 +1223,11 @@ k_batch_gather(BatchDev *T, int what)
 }
 
 // ---------------------------------------------------------------------------
-// Level-2 approximation (Sec. 4.5): wave-front pass over the skin, then every
-// block (one delegate point's sites over the skin depth) cut on its own.
+// Wave-front passes (Sec. 4.4 runs one before its push-relabel loop; the
+// paper omits the details) and the level-2 approximation (Sec. 4.5).
 // ---------------------------------------------------------------------------
 
-// Wave front (Sec. 4.4): one pass along every column, from the source end
+// Column pass of the exact solve (GC_OPT_WAVE_FIRST): one pass along every column, from the source end
 // towards the sink end over the free levels; each node hands the chain arc
 // towards the sink as much of its excess (its own plus what the pass brought
 // from below) as the arc's residual allows.  Heights are ignored, so a
@@ -1264,171 +1268,222 @@ k_wave(Src src)
     });
 }
 
-constexpr int32_t kUpRes = 1 << 29;     // residual of an unbounded arc inside a block
-constexpr int kBlockLanes = 128;        // b x b sites x up to 3b-1 skin levels, b <= 3
-
-// Exact cut of one block: the b x b sites of one delegate point over the
-// full depth of their skin (they share one window), with the arcs that leave
-// the block unused.  One 128-lane workgroup, one lane per node, state in LDS.
-// Synchronous push-relabel with exact in-block BFS heights until no node
-// with excess reaches a deficit, then the block's minimal source side
-// (reachability from the remaining excess) goes to aux (0 = source side).
-__global__ void __launch_bounds__(kBlockLanes)
-k_block_cut(Graph s, int b, int max_outer)
+// Level 2, wave step (push half): every node with excess and a finite
+// height pushes, arc by arc in direction order, min(excess, residual) to the
+// neighbours exactly one below it.  Heights come from `hc` and are not
+// written here, so along an arc pair at most one end is admissible and each
+// pair word has one writer; inflow is summed into ein (integer atomics,
+// order-free), so the step's result does not depend on the schedule.
+// Forced levels of the skin have infinite height and are never admissible.
+__global__ void __launch_bounds__(kBlock)
+k_wave_push(Graph s, const int32_t *__restrict__ hc)
 {
-    __shared__ int32_t e[kBlockLanes], hgt[kBlockLanes], ein[kBlockLanes];
-    __shared__ int32_t res[kBlockLanes][14];
-    __shared__ int s_part[kBlockLanes];
-    __shared__ int s_flag;
-    const int l = threadIdx.x;
-    const int64_t site0 = (int64_t)(blockIdx.y * b) * s.W + blockIdx.x * b;
-    const int lo = s.wlo[site0], depth = s.whi[site0] - lo;     // free levels lo+1 .. hi
-    const int nb = b * b * depth;
-    const int lx = l % b, ly = (l / b) % b, lk = l / (b * b);
-    const int x = blockIdx.x * b + lx, y = blockIdx.y * b + ly, j = lo + lk;   // node v_{lo+1+lk}
-    bool part = false;
-    int64_t n = 0;
-    if (l < nb && x < s.W && y < s.H) {
-        part = true;
-        n = (int64_t)j * s.plane + (int64_t)y * s.W + x;
+    const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= s.N) return;
+    int32_t e = s.ex[n];
+    const int32_t h = hc[n];
+    if (e <= 0 || h >= kInf) return;
+    int j, y, x;
+    decode(s, n, j, y, x);
+    const unsigned ex_mask = arc_exists(s, j, y, x);
+    int32_t hv[14];
+#pragma unroll
+    for (int d = 0; d < 14; ++d) {
+        const bool ok = (ex_mask >> d) & 1u;
+        hv[d] = ok ? hc[nbr(s, n, d)] : kInf;
     }
-    // local index of the neighbour in direction d, or -1 outside the block
+#pragma unroll
+    for (int d = 0; d < 14; ++d) {
+        if (e <= 0 || hv[d] != h - 1) continue;
+        const int32_t w = *word_ptr(s, n, d);
+        const int32_t r = res_from_word(s, d, w);
+        if (r <= 0) continue;
+        const int32_t delta = e < r ? e : r;
+        *word_ptr(s, n, d) = word_is_forward(d) ? w - delta : w + delta;
+        atomicAdd(&s.ein[nbr(s, n, d)], delta);
+        e -= delta;
+    }
+    s.ex[n] = e;
+}
+
+// Level 2, wave step (relabel half): merges the inflow, then lifts every node
+// holding excess to one above its lowest residual neighbour when that is
+// higher.  Neighbour heights are read from `hc` and the new ones written to
+// `hn` (every node, so `hn` is the whole next height field): a Jacobi step.
+__global__ void __launch_bounds__(kBlock)
+k_wave_relabel(Graph s, const int32_t *__restrict__ hc, int32_t *__restrict__ hn)
+{
+    const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (n >= s.N) return;
+    const int32_t in = s.ein[n];
+    const int32_t e = s.ex[n] + in;
+    int32_t h = hc[n];
+    if (in != 0) {
+        s.ex[n] = e;
+        s.ein[n] = 0;
+    }
+    if (e > 0 && h < kInf) {
+        int j, y, x;
+        decode(s, n, j, y, x);
+        const unsigned ex_mask = arc_exists(s, j, y, x);
+        int32_t w[14], hv[14];
+#pragma unroll
+        for (int d = 0; d < 14; ++d) {
+            const bool ok = (ex_mask >> d) & 1u;
+            w[d] = load_word(s, n, d, ok);
+            hv[d] = ok ? hc[nbr(s, n, d)] : kInf;
+        }
+        int32_t hmin = kInf;
+#pragma unroll
+        for (int d = 0; d < 14; ++d)
+            if (((ex_mask >> d) & 1u) && res_from_word(s, d, w[d]) > 0)
+                hmin = hv[d] < hmin ? hv[d] : hmin;
+        const int32_t nh = hmin >= kInf ? kInf : hmin + 1;
+        h = nh > h ? nh : h;
+    }
+    hn[n] = h;
+}
+
+// Opposite arc direction (the arc from the neighbour back).
+__host__ __device__ constexpr int dir_opposite(int d)
+{
+    return d <= D_N ? (d ^ 1)
+         : d == D_EM ? D_WP : d == D_WP ? D_EM : d == D_EP ? D_WM : d == D_WM ? D_EP
+         : d == D_SM ? D_NP : d == D_NP ? D_SM : d == D_SP ? D_NM : D_SP;
+}
+
+constexpr int kCutLanes = 64;        // one wavefront per block: b^3 <= 64 nodes
+constexpr int kCutMaxRounds = 4096;
+
+// Level 2, the push-relabel loop of one block: the free nodes of the b x b
+// sites of one delegate point whose level k lies in label group k / b, with
+// only the arcs between them.  One lane per node, state in LDS.  Rounds:
+// exact in-block distances to the block's deficits (1 at a deficit), stop
+// when no node with excess has a finite one, else 2n synchronous steps of
+// the wave rule (push along arcs to a neighbour exactly one below, merge the
+// inflow, Jacobi relabel), n the block's node count.  The block's final
+// excess and the pair words of its inner arcs are written back.
+// Grid: (delegate x, delegate y, group offset 0..2 from the delegate label - 1).
+__global__ void __launch_bounds__(kCutLanes)
+k_block_cut(Graph s, const int32_t *__restrict__ coarse_labels, int b)
+{
+    __shared__ int32_t e[kCutLanes], hgt[kCutLanes], hnew[kCutLanes], ein[kCutLanes];
+    __shared__ int32_t res[kCutLanes][14];
+    __shared__ uint8_t member[kCutLanes];
+    const int l = threadIdx.x;
+    const int wc = (s.W + b - 1) / b;
+    const int Sc = coarse_labels[(int64_t)blockIdx.y * wc + blockIdx.x];
+    const int G = Sc - 1 + (int)blockIdx.z;                   // label group of the block
+    if (G < 0) return;                                         // uniform: whole workgroup
+    const int lx = l % b, ly = (l / b) % b, lk = l / (b * b);
+    const int x = blockIdx.x * b + lx, y = blockIdx.y * b + ly, k = G * b + lk;
+    bool mem = false;
+    int64_t n = 0;
+    if (lk < b && x < s.W && y < s.H && k >= 1 && k <= s.J) {
+        const int64_t site = (int64_t)y * s.W + x;
+        mem = k > s.wlo[site] && k <= s.whi[site];
+        n = (int64_t)(k - 1) * s.plane + site;
+    }
+    member[l] = mem ? 1 : 0;
+    __syncthreads();
+    const int nb = __syncthreads_count(mem);
+    if (nb == 0) return;
     auto lnb = [&](int d) -> int {
         const int nx = lx + dir_dx(d), ny = ly + dir_dy(d), nk = lk + dir_dj(d);
-        if (nx < 0 || nx >= b || ny < 0 || ny >= b || nk < 0 || nk >= depth) return -1;
-        return (nk * b + ny) * b + nx;
+        if (nx < 0 || nx >= b || ny < 0 || ny >= b || nk < 0 || nk >= b) return -1;
+        const int q = (nk * b + ny) * b + nx;
+        return member[q] ? q : -1;
     };
-    e[l] = 0; ein[l] = 0; hgt[l] = kInf;
-    s_part[l] = part ? 1 : 0;
+    e[l] = 0; ein[l] = 0;
 #pragma unroll
     for (int d = 0; d < 14; ++d) res[l][d] = 0;
-    __syncthreads();
-    if (part) {
+    if (mem) {
         int j_, y_, x_;
         decode(s, n, j_, y_, x_);
         const unsigned ex_mask = arc_exists(s, j_, y_, x_);
         e[l] = s.ex[n];
 #pragma unroll
-        for (int d = 0; d < 14; ++d) {
-            if (!((ex_mask >> d) & 1u)) continue;
-            const int q = lnb(d);
-            if (q < 0 || !s_part[q]) continue;      // only arcs between free nodes of the block
-            res[l][d] = d == D_UP ? kUpRes : res_from_word(s, d, *word_ptr(s, n, d));
-        }
+        for (int d = 0; d < 14; ++d)
+            if (((ex_mask >> d) & 1u) && lnb(d) >= 0)
+                res[l][d] = res_from_word(s, d, *word_ptr(s, n, d));
     }
     __syncthreads();
-    int outer = 0;
-    for (; outer < max_outer; ++outer) {
-        // exact in-block distance to a deficit
-        hgt[l] = (part && e[l] < 0) ? 1 : kInf;
+    int round = 0;
+    for (;; ++round) {
+        if (round >= kCutMaxRounds) {
+            if (l == 0) atomicOr(&s.hdr->prefix_err, 2);
+            break;
+        }
+        // exact in-block distances (synchronous relaxation to the fixpoint)
+        hgt[l] = (mem && e[l] < 0) ? 1 : kInf;
         __syncthreads();
-        for (int r = 0; r < nb; ++r) {
-            if (l == 0) s_flag = 0;
-            __syncthreads();
-            if (part && e[l] >= 0) {
-                int32_t best = hgt[l];
+        for (;;) {
+            int32_t best = hgt[l];
+            if (mem && e[l] >= 0) {
 #pragma unroll
                 for (int d = 0; d < 14; ++d) {
                     const int q = lnb(d);
-                    if (q >= 0 && res[l][d] > 0) {
-                        const int32_t c = hgt[q] + 1;
-                        best = c < best ? c : best;
-                    }
+                    if (q >= 0 && res[l][d] > 0 && hgt[q] + 1 < best) best = hgt[q] + 1;
                 }
-                if (best < hgt[l]) { hgt[l] = best; s_flag = 1; }
             }
             __syncthreads();
-            const int f = s_flag;
-            __syncthreads();
-            if (!f) break;
+            const bool ch = best < hgt[l];
+            if (ch) hgt[l] = best;
+            if (!__syncthreads_or(ch)) break;
         }
-        if (l == 0) s_flag = 0;
-        __syncthreads();
-        if (part && e[l] > 0 && hgt[l] < kInf) s_flag = 1;
-        __syncthreads();
-        const int any = s_flag;
-        __syncthreads();
-        if (!any) break;
-        for (int sweep = 0; sweep < 2 * nb; ++sweep) {
-            // push: heights are read-only, one writer per arc pair
-            if (part && e[l] > 0 && hgt[l] < kInf) {
+        if (!__syncthreads_or(mem && e[l] > 0 && hgt[l] < kInf)) break;
+        for (int t = 0; t < 2 * nb; ++t) {
+            // push: heights read only
+            if (mem && e[l] > 0 && hgt[l] < kInf) {
                 int32_t ev = e[l];
 #pragma unroll
                 for (int d = 0; d < 14; ++d) {
                     const int q = lnb(d);
-                    if (ev == 0 || q < 0) continue;
+                    if (ev <= 0 || q < 0 || hgt[q] != hgt[l] - 1) continue;
                     const int32_t r = res[l][d];
-                    if (r > 0 && hgt[q] == hgt[l] - 1) {
-                        const int32_t dl = ev < r ? ev : r;
-                        res[l][d] = r - dl;
-                        const int od = d <= D_N ? (d ^ 1) : (d == D_EM ? D_WP : d == D_WP ? D_EM :
-                                       d == D_EP ? D_WM : d == D_WM ? D_EP : d == D_SM ? D_NP :
-                                       d == D_NP ? D_SM : d == D_SP ? D_NM : D_SP);
-                        atomicAdd(&res[q][od], dl);
-                        atomicAdd(&ein[q], dl);
-                        ev -= dl;
-                    }
+                    if (r <= 0) continue;
+                    const int32_t dl = ev < r ? ev : r;
+                    res[l][d] = r - dl;
+                    atomicAdd(&res[q][dir_opposite(d)], dl);
+                    atomicAdd(&ein[q], dl);
+                    ev -= dl;
                 }
                 e[l] = ev;
             }
             __syncthreads();
-            // relabel
-            if (part) {
+            if (mem) {
                 e[l] += ein[l];
                 ein[l] = 0;
             }
             __syncthreads();
-            if (part && e[l] > 0 && hgt[l] < kInf) {
+            // relabel: neighbours' heights of the step's start
+            int32_t nh = hgt[l];
+            if (mem && e[l] > 0 && hgt[l] < kInf) {
                 int32_t hmin = kInf;
 #pragma unroll
                 for (int d = 0; d < 14; ++d) {
                     const int q = lnb(d);
-                    if (q >= 0 && res[l][d] > 0) hmin = hgt[q] < hmin ? hgt[q] : hmin;
+                    if (q >= 0 && res[l][d] > 0 && hgt[q] < hmin) hmin = hgt[q];
                 }
-                const int32_t nh = hmin >= kInf ? kInf : hmin + 1;
-                if (nh > hgt[l]) hgt[l] = nh;
+                const int32_t c = hmin >= kInf ? kInf : hmin + 1;
+                nh = c > nh ? c : nh;
             }
+            hnew[l] = nh;
+            __syncthreads();
+            hgt[l] = hnew[l];
             __syncthreads();
         }
     }
-    // minimal source side of the block: reachable from the remaining excess
-    hgt[l] = (part && e[l] > 0) ? 0 : kInf;
-    __syncthreads();
-    for (int r = 0; r < nb; ++r) {
-        if (l == 0) s_flag = 0;
-        __syncthreads();
-        if (part && hgt[l] != 0) {
+    if (mem) {
+        s.ex[n] = e[l];
+        int j_, y_, x_;
+        decode(s, n, j_, y_, x_);
+        const unsigned ex_mask = arc_exists(s, j_, y_, x_);
 #pragma unroll
-            for (int d = 0; d < 14; ++d) {
-                const int q = lnb(d);
-                if (q < 0) continue;
-                const int od = d <= D_N ? (d ^ 1) : (d == D_EM ? D_WP : d == D_WP ? D_EM :
-                               d == D_EP ? D_WM : d == D_WM ? D_EP : d == D_SM ? D_NP :
-                               d == D_NP ? D_SM : d == D_SP ? D_NM : D_SP);
-                if (hgt[q] == 0 && res[q][od] > 0) { hgt[l] = 0; s_flag = 1; }
-            }
-        }
-        __syncthreads();
-        const int f = s_flag;
-        __syncthreads();
-        if (!f) break;
+        for (int d = 0; d < 14; ++d)
+            if (word_is_forward(d) && ((ex_mask >> d) & 1u) && lnb(d) >= 0)
+                *word_ptr(s, n, d) = res[l][d];
     }
-    if (part) s.aux[n] = hgt[l] == 0 ? 0 : kInf;
-    if (l == 0 && outer >= max_outer) atomicOr(&s.hdr->prefix_err, 2);
-}
-
-// Label = deepest source-side node of the column (everything above it is on
-// the source side through the unbounded upward chain arcs).
-__global__ void __launch_bounds__(kBlock)
-k_labels_closure(Graph s, int32_t *__restrict__ labels)
-{
-    int64_t site = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (site >= s.plane) return;
-    const int lo = s.wlo[site], hi = s.whi[site];
-    int X = lo;
-    for (int k = lo + 1; k <= hi; ++k)
-        if (s.aux[(int64_t)(k - 1) * s.plane + site] == 0) X = k;
-    labels[site] = X;
 }
 
 // ---------------------------------------------------------------------------
@@ -2017,42 +2072,70 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
     return status;
 }
 
+__global__ void __launch_bounds__(kBlock)
+k_zero_i32(int32_t *p, int64_t n)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 __global__ void k_set_i64(int64_t *p, long long v)
 {
     if (threadIdx.x == 0) *p = v;
 }
 
-GC_API int approx_level2_cut(gc_graph *skin, const int32_t *cost, int32_t *labels,
-                             int64_t *result, void *stream)
+GC_API int approx_level2_cut(gc_graph *skin, const int32_t *cost, const int32_t *coarse_labels,
+                             int32_t wave_steps, int32_t *labels, int64_t *result, void *stream)
 {
     int rc = graph_check(skin);
     if (rc != GC_OK) return rc;
-    if (!cost || !labels || !result) return GC_E_ARG;
+    if (!cost || !coarse_labels || !labels || !result || wave_steps < 0) return GC_E_ARG;
     const int b = skin->window_block;
-    if (b < 1 || b > 3) return GC_E_ARG;
+    if (b < 1 || b * b * b > kCutLanes) return GC_E_ARG;
     Graph s = view(skin);
     hipStream_t st = (hipStream_t)stream;
     const gc_problem &p = skin->p;
+    Opts opt = resolve(nullptr);
+    Launcher L{st, false, {}};
+    int passes = 0;
     hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(64), 0, st, result, s.hdr);
-    hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 2);
     if (s.N > 0) {
-        hipLaunchKernelGGL(k_wave<Graph>, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s);
-        dim3 grid((unsigned)((s.W + b - 1) / b), (unsigned)((s.H + b - 1) / b), 1);
-        hipLaunchKernelGGL(k_block_cut, grid, dim3(kBlockLanes), 0, st, s, b, 64 + 24 * b * b * b);
-        hipLaunchKernelGGL(k_labels_closure, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
-    } else if (s.plane > 0) {
-        hipLaunchKernelGGL(k_labels, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
+        const unsigned grid = grid_for(s.N);
+        // initialisation: exact residual distances to the deficits
+        hipLaunchKernelGGL(k_mask<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 0);
+        hipLaunchKernelGGL(k_seed<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 0);
+        if (!hip_ok(hipGetLastError())) return GC_E_HIP;
+        if ((rc = relax_to_fixpoint(s, 0, opt, L, &passes)) != GC_OK) return rc;
+        // wave steps over the whole skin; heights alternate between ht and aux
+        hipLaunchKernelGGL(k_zero_i32, dim3(grid), dim3(kBlock), 0, st, s.ein, s.N);
+        int32_t *hc = s.ht, *hn = s.aux;
+        for (int t = 0; t < wave_steps; ++t) {
+            hipLaunchKernelGGL(k_wave_push, dim3(grid), dim3(kBlock), 0, st, s, hc);
+            hipLaunchKernelGGL(k_wave_relabel, dim3(grid), dim3(kBlock), 0, st, s, hc, hn);
+            std::swap(hc, hn);
+        }
+        // every block's push-relabel loop on its own
+        const dim3 bgrid((unsigned)((s.W + b - 1) / b), (unsigned)((s.H + b - 1) / b), 3);
+        hipLaunchKernelGGL(k_block_cut, bgrid, dim3(kCutLanes), 0, st, s, coarse_labels, b);
+        // read-out: distances to the unfilled deficits; unreachable = source side
+        hipLaunchKernelGGL(k_mask<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 0);
+        hipLaunchKernelGGL(k_seed<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 0);
+        if (!hip_ok(hipGetLastError())) return GC_E_HIP;
+        if ((rc = relax_to_fixpoint(s, 0, opt, L, &passes)) != GC_OK) return rc;
     }
-    if (s.plane > 0)
+    hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 2);
+    if (s.plane > 0) {
+        hipLaunchKernelGGL(k_labels, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels, 0);
         hipLaunchKernelGGL(k_energy, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, cost, labels,
                            p.width, p.height, p.labels, p.penalty_h, p.inhibit_h, p.penalty_v,
                            p.inhibit_v, s.slots);
+    }
     hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, s.slots, s.hdr, 2, result);
     hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, st, result + 1, -1LL);
     if (!hip_ok(hipGetLastError())) return GC_E_HIP;
     int32_t perr = 0;
     if ((rc = read_i32(&s.hdr->prefix_err, &perr, st)) != GC_OK) return rc;
-    return (perr & 2) ? GC_E_NOT_CONVERGED : GC_OK;
+    return (perr & 2) ? GC_E_NOT_CONVERGED : (perr & 1) ? GC_E_PREFIX : GC_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -2457,6 +2540,23 @@ GC_API int maxflow_solve_batch(gc_graph *const *gs, int32_t n, void *dev_table, 
     return solve_batch_lanes(gs, n, o, stats, stream);
 }
 
+GC_API int gc_graph_state(const gc_graph *g, int32_t *excess, int32_t *words, void *stream)
+{
+    int rc = graph_check(g);
+    if (rc != GC_OK) return rc;
+    if (!excess || !words) return GC_E_ARG;
+    const Graph s = view(g);
+    if (s.N == 0) return GC_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = (size_t)s.N * sizeof(int32_t);
+    if (!hip_ok(hipMemcpyAsync(excess, s.ex, bytes, hipMemcpyDeviceToDevice, st))) return GC_E_HIP;
+    const int32_t *src[7] = {s.rd, s.re, s.rs, s.rem, s.rep, s.rsm, s.rsp};
+    for (int i = 0; i < 7; ++i)
+        if (!hip_ok(hipMemcpyAsync(words + (size_t)i * s.N, src[i], bytes, hipMemcpyDeviceToDevice, st)))
+            return GC_E_HIP;
+    return GC_OK;
+}
+
 GC_API int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *labels,
                           int64_t *result, void *stream)
 {
@@ -2479,7 +2579,7 @@ GC_API int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *label
     hipLaunchKernelGGL(k_zero_result, dim3(1), dim3(64), 0, st, result, s.hdr);
     hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 2);
     if (s.plane > 0) {
-        hipLaunchKernelGGL(k_labels, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels);
+        hipLaunchKernelGGL(k_labels, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, labels, 1);
         hipLaunchKernelGGL(k_energy, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, cost, labels,
                            p.width, p.height, p.labels, p.penalty_h, p.inhibit_h, p.penalty_v,
                            p.inhibit_v, s.slots);

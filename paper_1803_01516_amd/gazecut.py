@@ -66,7 +66,7 @@ class GcSolveStats(ctypes.Structure):
 
 EXPORTS = ("gc_status_str", "gc_last_hip_error", "gc_problem_check", "gc_graph_footprint_bytes",
            "stereo_cost_volume", "stereo_cost_volume_rgb", "graph_build", "maxflow_solve",
-           "extract_labels",
+           "extract_labels", "gc_graph_state",
            "gc_coarse_problem", "coarse_cost_volume", "graph_build_window", "approx_level2_cut",
            "gc_batch_footprint_bytes", "gc_batch_create", "gc_batch_destroy", "gc_batch_members",
            "gc_batch_add", "gc_batch_round", "maxflow_solve_batch")
@@ -114,6 +114,8 @@ def load(path: str = LIB_PATH):
     lib.maxflow_solve.restype = ctypes.c_int
     lib.extract_labels.argtypes = [ctypes.POINTER(GcGraph), P, P, P, P]
     lib.extract_labels.restype = ctypes.c_int
+    lib.gc_graph_state.argtypes = [ctypes.POINTER(GcGraph), P, P, P]
+    lib.gc_graph_state.restype = ctypes.c_int
     lib.gc_coarse_problem.argtypes = [ctypes.POINTER(GcProblem), ctypes.c_int32,
                                       ctypes.POINTER(GcProblem)]
     lib.gc_coarse_problem.restype = ctypes.c_int
@@ -122,7 +124,7 @@ def load(path: str = LIB_PATH):
     lib.graph_build_window.argtypes = [ctypes.POINTER(GcProblem), P, P, ctypes.c_int32, P,
                                        ctypes.c_size_t, ctypes.POINTER(GcGraph), P]
     lib.graph_build_window.restype = ctypes.c_int
-    lib.approx_level2_cut.argtypes = [ctypes.POINTER(GcGraph), P, P, P, P]
+    lib.approx_level2_cut.argtypes = [ctypes.POINTER(GcGraph), P, P, ctypes.c_int32, P, P, P]
     lib.approx_level2_cut.restype = ctypes.c_int
     lib.gc_batch_footprint_bytes.argtypes = []
     lib.gc_batch_footprint_bytes.restype = ctypes.c_size_t
@@ -222,6 +224,19 @@ def extract_labels(graph: Graph, cost, labels, result, stream=None):
                                  _stream_ptr(stream)), "extract_labels")
 
 
+def graph_state(graph: Graph, stream=None):
+    """Exports the graph's state: (balances int32 [m-1][h][w], pair words int32
+    [7][m-1][h][w]) as CUDA tensors (layout in gazecut.h)."""
+    import torch
+    p = graph.handle.p
+    dev = graph.ws.device
+    ex = torch.empty((max(p.labels - 1, 0), p.height, p.width), dtype=torch.int32, device=dev)
+    words = torch.empty((7, max(p.labels - 1, 0), p.height, p.width), dtype=torch.int32, device=dev)
+    _check(load().gc_graph_state(ctypes.byref(graph.handle), ctypes.c_void_p(ex.data_ptr()),
+                                 ctypes.c_void_p(words.data_ptr()), _stream_ptr(stream)), "gc_graph_state")
+    return ex, words
+
+
 def alloc_workspace(p: GcProblem, device="cuda"):
     import torch
     nbytes = footprint_bytes(p)
@@ -278,8 +293,18 @@ def graph_build_window(p: GcProblem, cost, coarse_labels, block: int, ws, stream
     return Graph(g, ws)
 
 
-def approx_level2_cut(skin: Graph, cost, labels, result, stream=None):
+# Wave steps (A - 1) of the level-2 cut when the caller gives none: on the
+# 384x288x16 pairs 24-32 steps already reach the level-1 labels' quality, the
+# 64-label pairs with textureless regions need about 64 (measured on the
+# oracle: fewer steps leave whole regions whose flow has not yet reached the
+# cut, and the read-out then places them at the window's top).
+LEVEL2_WAVE_STEPS = 64
+
+
+def approx_level2_cut(skin: Graph, cost, coarse_labels, labels, result, stream=None,
+                      wave_steps: int = LEVEL2_WAVE_STEPS):
     _check(load().approx_level2_cut(ctypes.byref(skin.handle), ctypes.c_void_p(cost.data_ptr()),
+                                    ctypes.c_void_p(coarse_labels.data_ptr()), int(wave_steps),
                                     ctypes.c_void_p(labels.data_ptr()),
                                     ctypes.c_void_p(result.data_ptr()), _stream_ptr(stream)),
            "approx_level2_cut")
@@ -294,7 +319,7 @@ APPROX_RELABEL_PERIOD = 32
 
 
 def approx_level1(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, stream=None,
-                  ws=None, ws_coarse=None, level: int = 1):
+                  ws=None, ws_coarse=None, level: int = 1, wave_steps: int = LEVEL2_WAVE_STEPS):
     """Delegate-point cut, then the cut inside the thin skin: exact (level 1)
     or block by block after a wave-front pass (level 2).  Returns (labels,
     energy, flow, coarse labels, (coarse stats, fine stats)); level 2 has
@@ -323,14 +348,15 @@ def approx_level1(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = Non
         extract_labels(gfine, cost, labels, res, stream)
     else:
         st_f = None
-        approx_level2_cut(gfine, cost, labels, res, stream)
+        approx_level2_cut(gfine, cost, clab, labels, res, stream, wave_steps)
     r = res.cpu()
     return labels, int(r[0]), int(r[1]), clab, (st_c, st_f)
 
 
 def approx_level2(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, stream=None,
-                  ws=None, ws_coarse=None):
-    return approx_level1(p, cost, block, opts, stream, ws, ws_coarse, level=2)
+                  ws=None, ws_coarse=None, wave_steps: int = LEVEL2_WAVE_STEPS):
+    return approx_level1(p, cost, block, opts, stream, ws, ws_coarse, level=2,
+                         wave_steps=wave_steps)
 
 
 # ---------------------------------------------------------------------------

@@ -17,3 +17,23 @@ def orc():
     import oracle
     oracle._load()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def certify(orc):
+    """certify(graph, cost_np, labels_np, params) reads a solved graph's state
+    back (gc_graph_state) and runs the oracle's certificate on it: capacity
+    bounds, conservation against the build, no residual path from an excess
+    to a deficit, labels = minimal source side, flow value = E(labels).
+    Returns the recomputed (flow, energy)."""
+    def run(graph, cost_np, labels_np, params):
+        import torch
+        from paper_1803_01516_amd import gazecut as gc
+        ex, words = gc.graph_state(graph)
+        torch.cuda.synchronize()
+        ex_np, words_np = ex.cpu().numpy(), words.cpu().numpy()
+        del ex, words
+        code, flow, energy = orc.certify_state(cost_np, ex_np, words_np, labels_np, *params)
+        assert code == 0, orc.CERT_CODES[code]
+        return flow, energy
+    return run

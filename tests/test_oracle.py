@@ -323,6 +323,74 @@ def test_flow_checker_rejects_infeasible_flows(orc):
     assert g.check_flow() == 0
 
 
+_CERT_CASES = [("tiny", None, (1, 1023, 1, 1023)), ("ragged", (9, 6, 7, 25), (2, 5, 1, 3)),
+               ("soft", (8, 8, 5, 10), (0, 0, 2, 1023)), ("two-label", (11, 4, 2, 30), (1, 1023, 1, 1023))]
+
+
+def _cert_cost(orc, case):
+    name, shape, params = case
+    if shape is None:
+        p = sg.make_pair(sg.TINY, (1, 2))
+        return orc.cost_volume(p.left, p.right, 8, 20), params
+    w, h, m, top = shape
+    rng = np.random.default_rng(sum(shape))
+    return rng.integers(0, top, (m, h, w)).astype(np.int32), params
+
+
+@pytest.mark.parametrize("case", _CERT_CASES, ids=[c[0] for c in _CERT_CASES])
+def test_certificate_accepts_maximum_flows(orc, case):
+    """The state certificate (used on the GPU's final states) against the
+    oracle's two max-flow algorithms: a Dinic flow and a push-relabel
+    preflow, put into the exported layout, pass every check, with the
+    minimal-source-side labels and flow = energy."""
+    cost, params = _cert_cost(orc, case)
+    g = orc.Graph(cost, *params)
+    flow = g.maxflow_dinic()
+    lab = g.labels_after_flow()
+    ex, words = g.export_state()
+    assert orc.certify_state(cost, ex, words, lab, *params) == (0, flow, flow)
+    g2 = orc.Graph(cost, *params)
+    f2, exc = g2.maxflow_pushrelabel()
+    lab2 = g2.labels_after_preflow(exc)
+    ex2, words2 = g2.export_state(exc)
+    assert (ex2 > 0).any() or f2 == 0           # a preflow: excess left at grid nodes
+    assert orc.certify_state(cost, ex2, words2, lab2, *params) == (0, f2, f2)
+    assert f2 == flow and (lab2 == lab).all()
+
+
+@pytest.mark.parametrize("case", _CERT_CASES[:2], ids=[c[0] for c in _CERT_CASES[:2]])
+def test_certificate_rejects_broken_states(orc, case):
+    """Each check fails on a state broken in the way it guards against."""
+    cost, params = _cert_cost(orc, case)
+    g = orc.Graph(cost, *params)
+    g.maxflow_dinic()
+    lab = g.labels_after_flow()
+    ex, words = g.export_state()
+    m, h, w = cost.shape
+    # the built graph before any flow: excess can still reach the deficits
+    e0, w0 = orc.Graph(cost, *params).export_state()
+    assert orc.certify_state(cost, e0, w0, np.zeros_like(lab), *params)[0] == 3
+    # a same-level pair word out of [0, 2*penalty]
+    bad = words.copy()
+    bad[1, 0, 0, 0] = 2 * params[0] + 1
+    assert orc.certify_state(cost, ex, bad, lab, *params)[0] == 1
+    bad[1, 0, 0, 0] = -1
+    assert orc.certify_state(cost, ex, bad, lab, *params)[0] == 1
+    # one unit more down a chain arc, balances untouched
+    bad = words.copy()
+    y, x = h // 2, w // 2
+    bad[0, 0, y, x] -= 1 if bad[0, 0, y, x] > 0 else -1
+    assert orc.certify_state(cost, ex, bad, lab, *params)[0] == 2
+    # a balance changed alone
+    bad_ex = ex.copy()
+    bad_ex[m - 2, y, x] -= 1
+    assert orc.certify_state(cost, bad_ex, words, lab, *params)[0] == 2
+    # labels one off at one site
+    bad_lab = lab.copy()
+    bad_lab[y, x] = lab[y, x] + 1 if lab[y, x] < m - 1 else lab[y, x] - 1
+    assert orc.certify_state(cost, ex, words, bad_lab, *params)[0] == 4
+
+
 def test_reconstruction_without_noise(orc):
     """sigma = 0, lambda = 1: on fronto-parallel textured scenes the exact cut
     recovers the true depth numbers (pinned for these seeds: a coincidental

@@ -188,44 +188,46 @@ def test_large_parity_full_size(torch_cuda, orc):
 
 
 @pytest.mark.parametrize("shape", [(1280, 720, 128), (640, 480, 64)], ids=["1280x720x128", "640x480x64"])
-def test_full_size_certificates(torch_cuda, orc, shape):
-    """The largest serving and batch shapes, too large for the oracle's
-    max-flow: the cost volume is compared whole; the solve is checked by
-    properties that hold at any size.  Flow = energy certifies a minimum cut
-    (every cut bounds every flow).  For sampled sites, moving one label down
-    must raise the energy strictly (the labelling is the pointwise-minimal
-    optimum, so no optimum lies below it) and moving it up must not lower it;
-    the energy change is taken from the oracle's energy on the 3x3 crop
-    around the site, which holds every term the site enters."""
+def test_full_size_certificates(torch_cuda, orc, certify, shape):
+    """The largest serving and batch shapes.  The cost volume is compared
+    whole with the oracle's; the solved state is read back and certified on
+    the host, independently of the flow value the GPU reports: every
+    residual within its pair total, conservation against the build, no
+    residual path from an excess to a deficit (a maximum preflow), labels =
+    its minimal source side, and the recomputed flow value = E(labels).  The
+    640x480x64 pair is also compared with the oracle's own cut (stored by
+    tests/golden/make_golden.py)."""
+    torch = torch_cuda
     w, h, m = shape
     spec = sg.spec_like(sg.MID, w, h, m)
     pr = sg.make_pair(spec, (5, 2, 0))
     p = gc.problem(w, h, m, spec.cap, 1, 1023)
-    L = torch_cuda.from_numpy(pr.left).cuda()
-    R = torch_cuda.from_numpy(pr.right).cuda()
-    labels, cost, energy, flow, st = gc.solve_pair(L, R, p)
-    assert st.active_last == 0
-    assert energy == flow
+    print(f"full-size certificate {w}x{h}x{m}", flush=True)
+    L = torch.from_numpy(pr.left).cuda()
+    R = torch.from_numpy(pr.right).cuda()
+    cost = torch.empty((m, h, w), dtype=torch.int32, device="cuda")
+    gc.stereo_cost_volume(L, R, p, cost)
+    ws = gc.alloc_workspace(p)
+    g = gc.graph_build(p, cost, ws)
+    st = gc.maxflow_solve(g)
+    labels = torch.empty((h, w), dtype=torch.int32, device="cuda")
+    result = torch.zeros(2, dtype=torch.int64, device="cuda")
+    gc.extract_labels(g, cost, labels, result)
+    energy, flow = (int(v) for v in result.cpu())
+    assert st.active_last == 0 and energy == flow
     cost_np = cost.cpu().numpy()
     del cost
     assert (cost_np == orc.cost_volume(pr.left, pr.right, m, spec.cap)).all()
     lab = labels.cpu().numpy()
-    assert lab.min() >= 0 and lab.max() < m
-    assert orc.energy(cost_np, lab, 1, 1023) == energy
-    rng = np.random.default_rng(11)
-    for y, x in zip(rng.integers(0, h, 48), rng.integers(0, w, 48)):
-        y0, y1, x0, x1 = max(0, y - 1), min(h, y + 2), max(0, x - 1), min(w, x + 2)
-        cc = np.ascontiguousarray(cost_np[:, y0:y1, x0:x1])
-        cl = np.ascontiguousarray(lab[y0:y1, x0:x1])
-        base = orc.energy(cc, cl, 1, 1023)
-        a = int(cl[y - y0, x - x0])
-        for l in range(m):
-            if l == a:
-                continue
-            cl[y - y0, x - x0] = l
-            e2 = orc.energy(cc, cl, 1, 1023)
-            assert e2 > base if l < a else e2 >= base, (y, x, a, l, base, e2)
-        cl[y - y0, x - x0] = a
+    f_host, e_host = certify(g, cost_np, lab, (1, 1023, 1, 1023))
+    assert f_host == e_host == energy == flow
+    del g, ws
+    torch.cuda.empty_cache()
+    gold_path = os.path.join(GOLDEN, f"mid_{w}x{h}x{m}_seed5-2-0_lam1.npz")
+    if os.path.exists(gold_path):
+        gold = np.load(gold_path)
+        assert flow == int(gold["flow"]) and energy == int(gold["energy"])
+        assert (lab == gold["labels"].astype(np.int32)).all()
 
 
 def test_repeat_solves_identical(torch_cuda, orc):
@@ -330,26 +332,63 @@ def test_approx_level1_mid_full_size(torch_cuda, orc, b):
 
 
 @pytest.mark.parametrize("b", [2, 3])
+@pytest.mark.parametrize("steps", [0, 5, 64])
 @pytest.mark.parametrize("spec,seed", [(sg.TINY, (1, 0)), (sg.spec_like(sg.MID, 70, 33, 9), (9, 8)),
                                        (sg.MID, (2, 0))])
-def test_approx_level2_parity(torch_cuda, orc, b, spec, seed):
+def test_approx_level2_parity(torch_cuda, orc, b, steps, spec, seed):
+    """Level 2 (skin-wide wave, b x b x b blocks, maximal source side) bit
+    for bit against the oracle; with 0 or 5 wave steps the blocks' push-
+    relabel loops do most of the work."""
+    if spec is sg.MID and steps != 64 and b == 2:
+        pytest.skip("the full-size pair runs at the default wave length and b = 3")
     pr = sg.make_pair(spec, seed)
     cost_np = orc.cost_volume(pr.left, pr.right, spec.m, spec.cap)
     p = gc.problem(spec.w, spec.h, spec.m, spec.cap, 1, 1023)
     cost = torch_cuda.from_numpy(cost_np).cuda()
-    labels, energy, flow, clab, _ = gc.approx_level2(p, cost, b)
-    ref_lab, ref_e, ref_cl = orc.approx_level2(cost_np, b, 1, 1023)
+    print(f"level2 {spec.name} b={b} steps={steps}", flush=True)
+    labels, energy, flow, clab, _ = gc.approx_level2(p, cost, b, wave_steps=steps)
+    ref_lab, ref_e, ref_cl = orc.approx_level2(cost_np, b, 1, 1023, wave_steps=steps)
     assert (clab.cpu().numpy() == ref_cl).all()
     assert energy == ref_e and flow == -1
     assert (labels.cpu().numpy() == ref_lab).all()
 
 
-def test_approx_level2_single_block_exact(torch_cuda, orc):
-    rng = np.random.default_rng(11)
-    p = gc.problem(3, 3, 4, 30, 1, 5)
+@pytest.mark.parametrize("b,steps,seed", [(2, 0, 0), (2, 3, 1), (3, 0, 2), (3, 7, 3), (3, 64, 4)])
+def test_approx_level2_arbitrary_windows(torch_cuda, orc, b, steps, seed):
+    """The level-2 cut on skins built from random delegate labels (large
+    label jumps between neighbouring delegate points, ragged edges, soft
+    inhibit) against the oracle's level-2 cut inside the same windows."""
+    rng = np.random.default_rng(700 + seed)
+    w, h, m = 29 + seed, 17 + 2 * seed, 12 + 3 * seed
+    pen_h, inh_h, pen_v, inh_v = [(1, 1023, 1, 1023), (2, 7, 1, 3), (3, 5, 0, 0)][seed % 3]
+    cost_np = rng.integers(0, 30, (m, h, w)).astype(np.int32)
+    cl_np = rng.integers(0, -(-m // b), (-(-h // b), -(-w // b))).astype(np.int32)
+    lo, hi = orc.skin_windows(cl_np, w, h, m, b)
+    ref_lab, *_ = orc.level2_skin(cost_np, lo, hi, b, steps, pen_h, inh_h, pen_v, inh_v)
+    p = gc.problem(w, h, m, 30, pen_h, inh_h, pen_v, inh_v)
+    cost = torch_cuda.from_numpy(cost_np).cuda()
+    cl = torch_cuda.from_numpy(cl_np).cuda()
+    ws = gc.alloc_workspace(p)
+    labels = torch_cuda.empty((h, w), dtype=torch_cuda.int32, device="cuda")
+    res = torch_cuda.zeros(2, dtype=torch_cuda.int64, device="cuda")
+    print(f"level2 windows {w}x{h}x{m} b={b} steps={steps}", flush=True)
+    g = gc.graph_build_window(p, cost, cl, b, ws)
+    gc.approx_level2_cut(g, cost, cl, labels, res, wave_steps=steps)
+    got = labels.cpu().numpy()
+    assert (got == ref_lab).all()
+    assert int(res.cpu()[0]) == orc.energy(cost_np, ref_lab, pen_h, inh_h, pen_v, inh_v)
+
+
+@pytest.mark.parametrize("b", [2, 3])
+def test_approx_level2_blocks_alone_are_exact(torch_cuda, orc, b):
+    """m <= b and b x b sites: the skin is one block, so with no wave step
+    the block's push-relabel loop alone must reach the back-most minimum
+    (pointwise maximum of all minimisers, by brute force)."""
+    rng = np.random.default_rng(11 + b)
+    p = gc.problem(b, b, b, 30, 1, 5)
     for _ in range(5):
-        cost_np = rng.integers(0, 20, (4, 3, 3)).astype(np.int32)
+        cost_np = rng.integers(0, 20, (b, b, b)).astype(np.int32)
         cost = torch_cuda.from_numpy(cost_np).cuda()
-        labels, energy, _, _, _ = gc.approx_level2(p, cost, 3)
-        emin, _, lo, _ = orc.brute_force(cost_np, 1, 5)
-        assert energy == emin and (labels.cpu().numpy() == lo).all()
+        labels, energy, _, _, _ = gc.approx_level2(p, cost, b, wave_steps=0)
+        emin, _, _, back = orc.brute_force(cost_np, 1, 5)
+        assert energy == emin and (labels.cpu().numpy() == back).all()

@@ -109,13 +109,15 @@ def test_autotune_picks_a_candidate():
 
 
 @pytest.mark.gpu
-def test_batched_full_mix_certificates(orc):
+def test_batched_full_mix_certificates(orc, certify):
     """The benchmark's batched workload at its full size: the seeded 64-pair
     mix over 320x240x16, 384x288x16, 450x375x64 and 640x480x64, solved by
-    maxflow_solve_batch with default options (concurrent lanes).  Every pair
-    carries the optimality certificate energy = flow, its labels' energy
-    recomputed on the host from the oracle's cost volume equals it, and the
-    first pair of each 16-label shape equals the oracle's cut bit for bit."""
+    maxflow_solve_batch with default options (concurrent lanes).  Every pair's
+    solved state is read back and certified on the host (capacity bounds,
+    conservation, no residual path from an excess to a deficit, labels = its
+    minimal source side, recomputed flow = E(labels) = the GPU's energy and
+    flow), and the first pair of each 16-label shape equals the oracle's cut
+    bit for bit."""
     import torch
     mix = rt.batch_mix(64, sg.BATCH_SHAPES, seed=4)
     items = [rt.make_item(i, s, p) for i, (s, p) in enumerate(mix)]
@@ -127,7 +129,8 @@ def test_batched_full_mix_certificates(orc):
         lab = it.labels.cpu().numpy()
         assert lab.min() >= 0 and lab.max() < spec.m
         cost = orc.cost_volume(pair.left, pair.right, spec.m, spec.cap)
-        assert orc.energy(cost, lab, 1, spec.inhibit) == it.energy
+        f_host, e_host = certify(it.graph, cost, lab, (1, spec.inhibit, 1, spec.inhibit))
+        assert f_host == e_host == it.energy
         if spec.m == 16 and (spec.w, spec.h) not in checked:
             checked.add((spec.w, spec.h))
             ref_lab, ref_flow, ref_e = orc.solve(cost, 1, spec.inhibit)
