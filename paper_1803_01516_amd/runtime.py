@@ -257,6 +257,7 @@ class Lane:
         self.batch = gc.Batch.on_device(opts, f"cuda:{self.device}")
         self.cv = threading.Condition()
         self.inbox = []
+        self.preparing = 0          # taken from the inbox, not yet in the batch
         self.live = {}
         self.rounds = 0
         self.closing = False
@@ -273,9 +274,22 @@ class Lane:
             self.cv.notify()
 
     def pending(self):
-        """Requests submitted to this lane and not finished."""
+        """Requests submitted to this lane and not finished: waiting in the
+        inbox, being prepared, or in the batch."""
         with self.cv:
-            return len(self.inbox) + len(self.live)
+            return len(self.inbox) + self.preparing + len(self.live)
+
+    def _take_inbox(self):
+        """Moves the inbox to the lane's preparation (still counted by pending)."""
+        with self.cv:
+            new, self.inbox = self.inbox, []
+            self.preparing += len(new)
+        return new
+
+    def _went_live(self, req):
+        with self.cv:
+            self.preparing -= 1
+            self.live[req.rid] = req
 
     def close(self):
         with self.cv:
@@ -295,12 +309,10 @@ class Lane:
                             self.cv.wait()
                         if self.closing and not self.inbox and not self.live:
                             return
-                        new, self.inbox = self.inbox, []
-                    for req in new:
+                    for req in self._take_inbox():
                         prepare(req.item, self.stream)
                         self.batch.add(req.item.graph, req.rid)
-                        with self.cv:
-                            self.live[req.rid] = req
+                        self._went_live(req)
                     self.server._members()
                     for tag, st in self.batch.round(self.stream):
                         with self.cv:

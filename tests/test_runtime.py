@@ -42,6 +42,38 @@ def _alone(spec, pair, lam=1):
     return lab.cpu().numpy(), e, f
 
 
+def test_admission_counts_requests_being_prepared():
+    """A lane's requests count against its member limit from submission to
+    completion, also while the lane prepares them (taken from the inbox,
+    not yet in the batch); the server admits no request beyond the limit.
+    Host logic only: the lane and server are driven without a GPU."""
+    import threading
+    from types import SimpleNamespace
+    lane = object.__new__(rt.Lane)
+    lane.cv = threading.Condition()
+    lane.inbox, lane.live, lane.preparing = [], {}, 0
+    lane.limit, lane.max_members = None, 2
+    srv = object.__new__(rt.Server)
+    srv.lock = threading.Condition()
+    srv.budget, srv.used, srv.peak_used, srv.lanes = 1 << 40, 0, 0, [lane]
+    item = SimpleNamespace(footprint=1 << 20)
+    reqs = [SimpleNamespace(rid=i) for i in range(3)]
+    assert srv.fits(item)
+    lane.submit(reqs[0])
+    lane.submit(reqs[1])
+    assert lane.pending() == 2 and not srv.fits(item)
+    taken = lane._take_inbox()                 # the lane thread starts preparing them
+    assert len(taken) == 2 and lane.inbox == []
+    assert lane.pending() == 2 and not srv.fits(item)
+    lane._went_live(taken[0])
+    assert lane.pending() == 2 and not srv.fits(item)
+    lane._went_live(taken[1])
+    assert lane.pending() == 2 and not srv.fits(item)
+    with lane.cv:
+        lane.live.pop(0)                         # a member finishes
+    assert lane.pending() == 1 and srv.fits(item)
+
+
 @pytest.mark.gpu
 @pytest.mark.parametrize("budget_mb,lanes", [(4096, ((None, 256),)), (6, ((None, 256),)),
                                              (4096, ((2 << 20, 256), (None, 1)))],
