@@ -52,43 +52,63 @@ def parse():
     ap.add_argument("--serve-low-requests", type=int, default=24)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 5 plain 256 MiB device copies (reference for HBM counters)")
-    return ap.parse_args()
+    ap.add_argument("--sections", default="all",
+                    help="comma list of the parts to run besides the timed headline steps: "
+                         "variants, rgb, approx, larger, batch, serving, cpu (default all)")
+    ap.add_argument("--larger-pairs", type=int, default=3,
+                    help="seeded pairs of each larger DRAM-resident configuration")
+    ap.add_argument("--larger-shapes", default="450x375x64,640x480x64",
+                    help="which larger configurations the 'larger' section runs")
+    args = ap.parse_args()
+    every = {"variants", "rgb", "approx", "larger", "batch", "serving", "cpu"}
+    sec = every if args.sections == "all" else {x for x in args.sections.split(",") if x}
+    if not sec <= every:
+        ap.error(f"unknown sections {sorted(sec - every)}")
+    if args.no_approx:
+        sec -= {"variants", "rgb", "approx", "larger"}
+    if args.batch_pairs <= 0:
+        sec.discard("batch")
+    if args.serve_requests <= 0:
+        sec.discard("serving")
+    if args.no_cpu_baseline:
+        sec.discard("cpu")
+    args.sec = sec
+    return args
 
 
-def algorithmic_bytes(kind: str, nodes: int, active_mean: float) -> float:
-    """Bytes a launch must move, per the kernel's own definition.
+BYTES_PER_VISIT = 72.0     # one node's 9-word record read and written per sweep
 
-    relax:   one tiled BFS pass reads every node's 16-bit arc mask and 32-bit
-             value and writes the value back: 10 B per node.
-    push:    reads excess and height of every node (8 B); an active node also
-             reads its 7 stored residual words, the 7 words its neighbours
-             store for it and 14 neighbour heights, and writes excess plus
-             up to 7 words: counted as 36 B read + 36 B written per active
-             node on top of the 8 B.
-    relabel: reads inflow, excess and height (12 B per node); an active node
-             also reads 14 residuals and 14 heights (112 B) and writes 4 B.
+
+def algorithmic_bytes(kind: str, nodes: int, visits_per_sweep: float) -> float:
+    """Algorithmic bytes of one launch.
+
+    push / relabel / fused sweep: a sweep reads and writes the 9-word record
+    (excess, height, 7 stored pair words: 36 B) of every node it finds with
+    excess and a finite height, 72 B per such visit.  The visits are counted
+    on the device by the push (or fused) sweep; inactive nodes cost nothing
+    algorithmically (their 64-node groups are skipped by a flag test).
+    relax: one tiled BFS pass reads every node's 16-bit arc mask and 32-bit
+    value and writes the value back: 10 B per node (an upper bound: tiles
+    whose neighbourhood did not change are skipped).
     """
     if kind == "relax":
         return 10.0 * nodes
-    if kind == "push":
-        return 8.0 * nodes + 72.0 * active_mean
-    if kind == "relabel":
-        return 12.0 * nodes + 116.0 * active_mean
-    return 0.0
+    return BYTES_PER_VISIT * visits_per_sweep
 
 
 PROFILES = os.path.join(ROOT, "profiles")
 HIP_SOURCE = os.path.join(ROOT, "paper_1803_01516_amd", "csrc", "gazecut.hip")
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the ratio
-    the same counter shows on a plain device copy of known size), or None when
-    no summary covers the kernel or the HIP source has changed since the
-    counters were taken (the summary records the source's SHA-1)."""
+def measured_traffic(kernel: str, shape: str):
+    """HBM bytes per launch of `kernel` on the workload `shape` (WxHxM) from
+    the committed rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE per
+    dispatch, each scaled by the ratio the same counter shows on a plain
+    device copy of known size), or None when no summary covers the kernel or
+    the HIP source has changed since the counters were taken (the summary
+    records the source's SHA-1)."""
     import hashlib
-    path = os.path.join(PROFILES, f"{kernel}_384x288x16_traffic.md")
+    path = os.path.join(PROFILES, f"{kernel}_{shape}_traffic.md")
     if not os.path.exists(path):
         return None
     rec = None
@@ -102,6 +122,44 @@ def measured_traffic(kernel: str):
         if hashlib.sha1(f.read()).hexdigest() != rec.get("source_sha1"):
             return None
     return 1024.0 * (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"])
+
+
+KERNEL_NAMES = {"relax": "k_relax", "push": "k_push", "relabel": "k_relabel"}
+
+
+def roofline_block(stats, nodes, shape, fused, state_bytes, steps):
+    """Roofline entry of the dominant kernel class over a list of solve
+    statistics (GC_OPT_TIME_KERNELS): algorithmic bytes of its average launch
+    over that launch's average device time (sampled HIP events on the solve
+    stream), against MI355X's 8 TB/s."""
+    tot = {k: sum(s[f"{k}_ms"] for s in stats) for k in ("push", "relabel", "relax")}
+    launches = {k: sum(s[f"{k}_launches"] for s in stats) for k in ("push", "relabel", "relax")}
+    kind = max(tot, key=tot.get)
+    sweeps = max(1, sum(s["sweeps"] for s in stats))
+    visits = sum(s["active_visits"] for s in stats)
+    per_launch_ms = tot[kind] / max(1, launches[kind])
+    bytes_launch = algorithmic_bytes(kind, nodes, visits / sweeps)
+    achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
+    kname = "k_sweep" if (kind == "push" and fused) else KERNEL_NAMES[kind]
+    traffic = measured_traffic(kname, shape)
+    resident = state_bytes < 256e6
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else int(traffic),
+            "traffic_over_algorithmic": None if traffic is None else round(traffic / bytes_launch, 3),
+            "traffic_GBs": None if traffic is None else round(traffic / (per_launch_ms * 1e-3) / 1e9, 1),
+            "kernel": kname, "workload": shape,
+            "state_mb": round(state_bytes / 1e6, 1),
+            "measure": ("effective algorithmic bandwidth: the state fits the 256 MB Infinity "
+                        "Cache, so these bytes are not DRAM traffic" if resident else
+                        "algorithmic bytes of a DRAM-resident state (larger than the 256 MB "
+                        "Infinity Cache)"),
+            "avg_launch_us": round(per_launch_ms * 1e3, 2),
+            "active_visits_per_sweep": round(visits / sweeps, 1),
+            "bytes_per_visit": BYTES_PER_VISIT,
+            "launches_per_solve": round(launches[kind] / steps, 1),
+            "bytes_per_launch": int(bytes_launch),
+            "device_ms_per_solve": {k: round(v / steps, 3) for k, v in tot.items()}}
 
 
 def _log(msg):
@@ -176,6 +234,50 @@ def bench_batch(args, gc, sg, torch):
                                     "split" if best.flags & gc.GC_OPT_SPLIT_SWEEP else "by depth"),
                           "tuning_s": round(tune_s, 2), "candidates": len(trials)},
             "identical_results": same}
+
+
+def bench_larger(args, gc, torch, sg, lspec, seed0, stream, dev):
+    """Exact solves of seeded pairs of one larger configuration, with the
+    roofline entry of their dominant kernel."""
+    lp = gc.problem(lspec.w, lspec.h, lspec.m, lspec.cap, 1, lspec.inhibit)
+    lws = gc.alloc_workspace(lp, dev)
+    lpairs = [sg.make_pair(lspec, (seed0, i)) for i in range(args.larger_pairs)]
+    ll = [torch.from_numpy(q.left).to(dev) for q in lpairs]
+    lr = [torch.from_numpy(q.right).to(dev) for q in lpairs]
+    opts = gc.GcSolveOpts(flags=0 if args.no_timing else gc.GC_OPT_TIME_KERNELS)
+    gc.solve_pair(ll[0], lr[0], lp, None, stream, lws)          # warm-up
+    lat, stats, errs, pcts, exact = [], [], [], [], True
+    for k in range(len(lpairs)):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        lab, _, e, f, st = gc.solve_pair(ll[k], lr[k], lp, opts, stream, lws)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - a)
+        exact = exact and e == f                     # min-cut energy = max flow
+        stats.append(st.as_dict())
+        er, pc = sg.eq2_error(lpairs[k].gt, lab.cpu().numpy())
+        errs.append(er)
+        pcts.append(pc)
+    nodes = lspec.w * lspec.h * (lspec.m - 1)
+    out = {"workload": f"{lspec.w}x{lspec.h} grayscale pairs, {lspec.m} depth numbers, "
+                       f"{lspec.planes[0]}-{lspec.planes[1]} slanted planes, "
+                       f"{int(round(100 * lspec.textureless))} % textureless, sigma {lspec.sigma:g}, "
+                       f"cap {lspec.cap}, penalty 1, inhibit {lspec.inhibit}, "
+                       f"seeds ({seed0}, 0..{args.larger_pairs - 1})",
+           "nodes": nodes,
+           "ms_per_pair": round(1e3 * float(np.median(lat)), 3),
+           "ms_per_pair_all": [round(1e3 * x, 2) for x in lat],
+           "sweeps_per_pair": round(float(np.mean([s["sweeps"] for s in stats])), 1),
+           "global_relabels_per_pair": round(float(np.mean([s["global_relabels"] for s in stats])), 2),
+           "bfs_passes_per_pair": round(float(np.mean([s["bfs_passes"] for s in stats])), 1),
+           "eq2_error_mean": round(float(np.mean(errs)), 1),
+           "pct_exact_mean": round(float(np.mean(pcts)), 1),
+           "energy_equals_flow": exact}
+    if not args.no_timing:
+        out["roofline"] = roofline_block(stats, nodes, f"{lspec.w}x{lspec.h}x{lspec.m}",
+                                         lspec.m - 1 >= 32, gc.footprint_bytes(lp), len(stats))
+    del lws, ll, lr
+    return out
 
 
 def bench_serving(args, gc, sg, torch, rate, n_req):
@@ -276,34 +378,14 @@ def main():
 
     roof = None
     if not args.no_timing:
-        tot = {k: sum(s[f"{k}_ms"] for s in stats) for k in ("push", "relabel", "relax")}
-        launches = {k: sum(s[f"{k}_launches"] for s in stats) for k in ("push", "relabel", "relax")}
-        kind = max(tot, key=tot.get)
-        # mean active nodes per sweep is not recorded; bound it by pushes per sweep
-        sweeps = max(1, sum(s["sweeps"] for s in stats))
-        active_mean = min(float(nodes), pushes / sweeps)
-        per_launch_ms = tot[kind] / max(1, launches[kind])
-        bytes_launch = algorithmic_bytes(kind, nodes, active_mean)
-        achieved = bytes_launch / (per_launch_ms * 1e-3) / 1e9
-        kname = {"relax": "k_relax", "push": "k_push", "relabel": "k_relabel"}[kind]
-        traffic = measured_traffic(kname)
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else int(traffic),
-                "traffic_over_algorithmic": None if traffic is None else round(traffic / bytes_launch, 3),
-                # measured memory-side bytes per launch over the same launch time
-                "traffic_GBs": None if traffic is None else round(traffic / (per_launch_ms * 1e-3) / 1e9, 1),
-                "kernel": kname,
-                "avg_launch_us": round(per_launch_ms * 1e3, 2),
-                "launches_per_step": round(launches[kind] / args.steps, 1),
-                "bytes_per_launch": int(bytes_launch),
-                "device_ms_per_step": {k: round(v / args.steps, 3) for k, v in tot.items()}}
+        roof = roofline_block(stats, nodes, f"{spec.w}x{spec.h}x{spec.m}", spec.m - 1 >= 32,
+                              gc.footprint_bytes(p), args.steps)
 
     # pairwise-term variants on the same pairs (Fig. 6 compares inhibit 0 and
     # 1023; the vertical pairs' inhibit is a reading of Sec. 3): exact cuts,
     # quality by eq. (2) against the generated truth
     variants = {}
-    if not args.no_approx:
+    if "variants" in args.sec:
         for name, (pen, inh_h, inh_v) in (("inhibit_1023", (args.lam, 1023, 1023)),
                                           ("inhibit_0", (args.lam, 0, 0)),
                                           ("inhibit_horizontal_only", (args.lam, 1023, 0))):
@@ -334,7 +416,7 @@ def main():
     # RGB sum of absolute differences, inhibit 1023, a penalty sweep around
     # the paper's 14 and its inhibit-0 comparison (Fig. 6 analogue)
     rgb = {}
-    if not args.no_approx:
+    if "rgb" in args.sec:
         rspec = sg.MID_RGB
         rpairs = [sg.make_pair(rspec, (2, i)) for i in range(args.pairs)]
         rl = [torch.from_numpy(q.left).to(dev) for q in rpairs]
@@ -364,7 +446,7 @@ def main():
 
     # the paper's approximate cuts (Sec. 4.5) on the same pairs, timed the same way
     approx = {}
-    if not args.no_approx:
+    if "approx" in args.sec:
         best_e = {}
         for variant, level, b in (("level1_b2", 1, 2), ("level1_b3", 1, 3), ("level2_b3", 2, 3)):
             c = gc.coarse_problem(p, b)
@@ -398,43 +480,26 @@ def main():
                                    [best_e[k] for k in best_e])), 6),
                                "eq2_error_mean": round(float(np.mean(errs)), 1),
                                "pct_exact_mean": round(float(np.mean(pcts)), 1)}
+        if "level2_b3" in approx and "level1_b3" in approx:
+            # Table 2 of the paper: eq. (2) error 21294 at level 2 b=3 against
+            # 20657 at level 1 b=3 on its own pair (ratio 1.031)
+            approx["level2_over_level1_b3_eq2"] = round(
+                approx["level2_b3"]["eq2_error_mean"] / approx["level1_b3"]["eq2_error_mean"], 4)
+            approx["paper_table2_level2_over_level1_b3_eq2"] = round(21294 / 20657, 4)
 
-    # the larger configuration: 450x375 pairs with 64 depth numbers (12
-    # slanted planes, 10 % textureless), exact solve, default options
-    large = None
-    if not args.no_approx:
-        lspec = sg.LARGE
-        lp = gc.problem(lspec.w, lspec.h, lspec.m, lspec.cap, 1, lspec.inhibit)
-        lws = gc.alloc_workspace(lp, dev)
-        lpairs = [sg.make_pair(lspec, (3, i)) for i in range(3)]
-        ll = [torch.from_numpy(q.left).to(dev) for q in lpairs]
-        lr = [torch.from_numpy(q.right).to(dev) for q in lpairs]
-        gc.solve_pair(ll[0], lr[0], lp, None, stream, lws)          # warm-up
-        lat_l, sw_l, rl_l, ps_l, errs, pcts, exact = [], [], [], [], [], [], True
-        for k in range(len(lpairs)):
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            lab_l, _, e_l, f_l, st_l = gc.solve_pair(ll[k], lr[k], lp, None, stream, lws)
-            torch.cuda.synchronize()
-            lat_l.append(time.perf_counter() - a)
-            exact = exact and e_l == f_l                     # min-cut energy = max flow
-            sw_l.append(st_l.sweeps); rl_l.append(st_l.global_relabels); ps_l.append(st_l.bfs_passes)
-            er, pc = sg.eq2_error(lpairs[k].gt, lab_l.cpu().numpy())
-            errs.append(er)
-            pcts.append(pc)
-        large = {"workload": "450x375 grayscale pairs, 64 depth numbers, 12 slanted planes, 10 % "
-                             "textureless, sigma 2, cap 30, penalty 1, inhibit 1023, seeds (3, 0..2)",
-                 "nodes": lspec.w * lspec.h * (lspec.m - 1),
-                 "ms_per_pair": round(1e3 * float(np.median(lat_l)), 3),
-                 "ms_per_pair_all": [round(1e3 * x, 2) for x in lat_l],
-                 "sweeps_per_pair": round(float(np.mean(sw_l)), 1),
-                 "global_relabels_per_pair": round(float(np.mean(rl_l)), 2),
-                 "bfs_passes_per_pair": round(float(np.mean(ps_l)), 1),
-                 "eq2_error_mean": round(float(np.mean(errs)), 1),
-                 "pct_exact_mean": round(float(np.mean(pcts)), 1),
-                 "energy_equals_flow": exact}
-        _log(f"larger pair 450x375x64: {large['ms_per_pair']} ms/pair")
-        del lws, ll, lr
+    # the larger configurations, whose state does not fit the Infinity Cache:
+    # 450x375 pairs with 64 depth numbers (12 slanted planes, 10 % textureless)
+    # and the 640x480x64 class of the batched mix; exact solves, default
+    # options, kernel time sampled as in the headline steps
+    larger = {}
+    if "larger" in args.sec:
+        for key, lspec, seed0 in (("450x375x64", sg.LARGE, 3),
+                                  ("640x480x64", sg.spec_like(sg.MID, 640, 480, 64), 5)):
+            if key not in args.larger_shapes.split(","):
+                continue
+            larger[key] = bench_larger(args, gc, torch, sg, lspec, seed0, stream, dev)
+            _log(f"larger pair {key}: {larger[key]['ms_per_pair']} ms/pair")
+        torch.cuda.empty_cache()
 
     calib = None
     if args.copy_calibration:
@@ -448,9 +513,9 @@ def main():
         calib = {"copy_bytes": src.numel() * 4, "copies": 5}
         del src, dst
 
-    batch = bench_batch(args, gc, sg, torch) if args.batch_pairs > 0 else None
+    batch = bench_batch(args, gc, sg, torch) if "batch" in args.sec else None
     serving = serving_low = None
-    if args.serve_requests > 0:
+    if "serving" in args.sec:
         serving = bench_serving(args, gc, sg, torch, args.serve_rate, args.serve_requests)
         if args.serve_low_rate > 0:
             serving_low = bench_serving(args, gc, sg, torch, args.serve_low_rate,
@@ -458,7 +523,7 @@ def main():
 
     cpu = None
     parity = None
-    if not args.no_cpu_baseline:
+    if "cpu" in args.sec:
         import oracle
         n = max(1, args.cpu_sample)
         t = 0.0
@@ -519,7 +584,8 @@ def main():
         "eq2_error_last": err, "pct_exact_last": pct,
         "approx": approx or None,
         "pairwise_variants": variants or None,
-        "larger_pair": large,
+        "larger_pair": larger.get("450x375x64"),
+        "larger_640x480x64": larger.get("640x480x64"),
         "rgb_sad": ({"workload": "384x288 colour pairs, 16 depth numbers, RGB sum of absolute "
                                  "differences (untruncated), seeds (2, 0..7)", **rgb} if rgb else None),
         "copy_calibration": calib,

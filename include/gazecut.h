@@ -53,8 +53,9 @@ typedef enum {
     GC_E_ARG = -1,            /* NULL pointer or invalid option value        */
     GC_E_SHAPE = -2,          /* negative sizes, labels < 1, too many nodes  */
     GC_E_WORKSPACE = -3,      /* workspace smaller than gc_graph_footprint_bytes */
-    GC_E_CAP_OVERFLOW = -4,   /* sites*cap + largest pair capacity >= 2^30:
-                                 int32 excess/residuals could overflow        */
+    GC_E_CAP_OVERFLOW = -4,   /* sites*cap + largest pair capacity >= 2^30, or
+                                 a data term outside [0, cap] reached the
+                                 build: int32 excess/residuals could overflow */
     GC_E_NOT_CONVERGED = -5,  /* iteration cap of gc_solve_opts reached       */
     GC_E_HIP = -6,            /* a HIP runtime call failed (see gc_last_hip_error) */
     GC_E_PREFIX = -7          /* a cut column was not a prefix (internal check) */
@@ -152,6 +153,8 @@ typedef struct {
     int32_t kernel_launches[GC_K_CLASSES];  /* with GC_OPT_TIME_KERNELS only */
     double kernel_ms[GC_K_CLASSES];         /* estimated device time per class */
     double done_ms;           /* maxflow_solve_batch: host ms from its start to this graph's end */
+    int64_t active_visits;    /* nodes with excess and a finite height met by the
+                                 push (split) or fused sweeps, summed over sweeps */
 } gc_solve_stats;
 
 /* Largest number of graphs one batch holds at a time. */
@@ -197,8 +200,12 @@ int stereo_cost_volume_rgb(const uint8_t *left, const uint8_t *right, const gc_p
  * u_{k+1} -> v_k of capacity inhibit between 4-neighbours.  The terminal
  * arcs are folded into node overflows as in Sec. 4.4: v_1 starts with excess
  * g(0) and v_{m-1} with deficit g(m-1).
- * cost: DEVICE int32 [labels][height][width] from stereo_cost_volume (or any
- *       non-negative data term of the same layout); read only.
+ * cost: DEVICE int32 [labels][height][width] from stereo_cost_volume, or any
+ *       data term of the same layout whose values lie in [0, p->cap]; read
+ *       only.  The int32 bounds on flow and excess rest on that range: the
+ *       build flags a value outside it on the device, and maxflow_solve,
+ *       extract_labels and approx_level2_cut on the graph then return
+ *       GC_E_CAP_OVERFLOW (graph_build itself does not wait for the device).
  * ws:   DEVICE workspace of at least gc_graph_footprint_bytes(p) bytes,
  *       256-byte aligned; fully (re)initialised, so a graph can be rebuilt
  *       in place.
@@ -214,7 +221,8 @@ int graph_build(const gc_problem *p, const int32_t *cost, void *ws, size_t ws_by
  * the workspace is what extract_labels reads.
  * o: host options or NULL for defaults; stats: host struct or NULL.
  * Errors: GC_E_ARG, GC_E_NOT_CONVERGED (state is a valid preflow but not a
- * maximum one), GC_E_HIP. */
+ * maximum one), GC_E_CAP_OVERFLOW (the graph was built from a data term
+ * outside [0, cap]; found at the first global relabel), GC_E_HIP. */
 int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *stats, void *stream);
 
 /* Reads the minimum cut off a solved graph.  The source side is every node
@@ -228,7 +236,8 @@ int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *stats, vo
  * result: DEVICE int64[2], written: result[0] = E(labels) evaluated from its
  *         definition, result[1] = value of the maximum flow.  The two are
  *         equal when the solve finished (max-flow = min-cut).
- * Errors: GC_E_ARG, GC_E_PREFIX, GC_E_HIP. */
+ * Errors: GC_E_ARG, GC_E_PREFIX, GC_E_CAP_OVERFLOW (data term outside
+ * [0, cap] at the build), GC_E_HIP. */
 int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *labels,
                    int64_t *result, void *stream);
 
@@ -289,6 +298,28 @@ int coarse_cost_volume(const gc_problem *p, const int32_t *cost, int32_t block,
 int graph_build_window(const gc_problem *p, const int32_t *cost, const int32_t *coarse_labels,
                        int32_t block, void *ws, size_t ws_bytes, gc_graph *g_out, void *stream);
 
+/* Coarse-to-fine warm start of the exact solve (our design next to the
+ * hierarchy of Sec. 4.5): seeds a freshly built full graph `g` with the
+ * state of a thin-skin graph `skin` of the same problem and data term that
+ * maxflow_solve has solved.  Free skin nodes keep their excess and the pair
+ * words of their arcs; the arcs the skin folded into overflows (from
+ * forced-source levels into the skin, from the skin into forced-sink levels)
+ * carry their capacity in the full graph, so forced-source nodes start with
+ * the deficit and forced-sink nodes with the excess of what they exchanged;
+ * every other arc keeps the build's value.  The result is a pseudoflow
+ * (capacities respected, nodes may hold a deficit anywhere), which the
+ * solver handles as it handles the sink deficits: maxflow_solve on `g` then
+ * ends in the same maximum flow value and extract_labels in the same minimal
+ * minimum cut as from the cold build (the minimal source side is unique).
+ * g:    built by graph_build (not a skin) on the same gc_problem;
+ * skin: built by graph_build_window and solved; read only;
+ * cost: DEVICE int32 [labels][height][width], the data term of both.
+ * Waits for the device (one 8-byte read-back).
+ * Errors: GC_E_ARG (wrong graph kinds or problems), GC_E_CAP_OVERFLOW (the
+ * seeded excess totals 2^30 or more, beyond the int32 bound of one node's
+ * excess), GC_E_HIP. */
+int graph_warm_start(gc_graph *g, const gc_graph *skin, const int32_t *cost, void *stream);
+
 /* Level-2 approximation (Sec. 4.5) on a thin-skin graph from
  * graph_build_window (block size b = skin->window_block, 1 <= b <= 4): the
  * wave-front pre-phase covers the whole skin and the push-relabel loop cuts
@@ -319,7 +350,8 @@ int graph_build_window(const gc_problem *p, const int32_t *cost, const int32_t *
  *                definition, result[1] = -1 (no global cut value exists).
  * The skin's state is consumed.  Errors: GC_E_ARG (not a thin-skin graph,
  * b^3 > 64, wave_steps < 0), GC_E_NOT_CONVERGED (a block needed more than
- * 4096 rounds), GC_E_PREFIX, GC_E_HIP. */
+ * 4096 rounds), GC_E_PREFIX, GC_E_CAP_OVERFLOW (data term outside [0, cap]
+ * at the build), GC_E_HIP. */
 int approx_level2_cut(gc_graph *skin, const int32_t *cost, const int32_t *coarse_labels,
                       int32_t wave_steps, int32_t *labels, int64_t *result, void *stream);
 

@@ -78,6 +78,11 @@ __host__ __device__ constexpr int dir_dx(int d)
     return (d == D_E || d == D_EM || d == D_EP) ? 1 : (d == D_W || d == D_WM || d == D_WP) ? -1 : 0;
 }
 
+// Bits of DevHeader::prefix_err: 1 a column's source side is not a prefix,
+// 2 a level-2 block loop hit its round cap, kCostErr a data term outside
+// [0, cap] reached graph_build.
+constexpr int32_t kCostErr = 4;
+
 struct DevHeader {
     int32_t flags[kMaxFlags];
     int32_t active;
@@ -85,9 +90,11 @@ struct DevHeader {
     int32_t max_height;       // largest height of an active node at the last count
     int32_t pad[13];
     unsigned long long pushes;
+    unsigned long long visits;  // active nodes visited by the push (or fused) sweeps
     long long tcap;           // capacity of all arcs into the sink side
     long long c0;             // capacity of arcs from forced-source to forced-sink nodes
-    unsigned long long pad2[13];
+    long long seeded;         // total positive excess of a warm-started state
+    unsigned long long pad2[11];
 };
 static_assert(sizeof(DevHeader) == 256, "header must stay 256 bytes");
 
@@ -99,7 +106,8 @@ struct Slot {
     int32_t active;
     int32_t max_height;
     long long tcap, c0;
-    long long pad2[2];
+    unsigned long long visits;
+    long long pad2[1];
 };
 static_assert(sizeof(Slot) == 64, "one slot per cache line");
 constexpr int kSlots = 256;
@@ -457,6 +465,28 @@ __device__ inline int32_t load_height(const Graph &s, int64_t n, int d, bool ok)
     return s.ht[ok ? nbr(s, n, d) : n];
 }
 
+// Capacities of the arc from node (j, site) to its neighbour in direction d
+// (cout) and of the arc back (cin), Sec. 3 / Fig. 4: data chain g(k) down,
+// same-level penalty both ways, inhibit on u_{k+1} -> v_k.  The unbounded
+// chain reverse is reported as 0: it never meets a forced partner of a free
+// node, and a forced node only uses the capacity towards a free one.
+__device__ inline void arc_caps(const Graph &s, const int32_t *__restrict__ cost, int d, int64_t site,
+                                int j, int ph, int pv, int32_t &cout, int32_t &cin)
+{
+    cout = 0;
+    cin = 0;
+    switch (d) {
+    case D_DOWN: cout = cost[(int64_t)(j + 1) * s.plane + site]; break;
+    case D_UP:   cin = cost[(int64_t)j * s.plane + site]; break;
+    case D_E: case D_W: cout = cin = ph; break;
+    case D_S: case D_N: cout = cin = pv; break;
+    case D_EM: case D_WM: cout = s.ie; break;
+    case D_EP: case D_WP: cin = s.ie; break;
+    case D_SM: case D_NM: cout = s.is; break;
+    default: cin = s.is; break;                  // D_SP, D_NP
+    }
+}
+
 // Graph initialisation.  Terminal arcs are folded into node overflows: the
 // arc from s into v_1 is pre-saturated (excess g(0)) and the arc from
 // v_{m-1} to t becomes a deficit g(m-1).  For a thin-skin graph (kWindow) the
@@ -468,7 +498,7 @@ __device__ inline int32_t load_height(const Graph &s, int64_t n, int d, bool ok)
 // straight from forced-source to forced-sink nodes (cut by every labelling).
 template <bool kWindow>
 __global__ void __launch_bounds__(kBlock)
-k_build(Graph s, const int32_t *__restrict__ cost, int m)
+k_build(Graph s, const int32_t *__restrict__ cost, int m, int cap)
 {
     int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     long long tsum = 0, c0 = 0;
@@ -477,6 +507,11 @@ k_build(Graph s, const int32_t *__restrict__ cost, int m)
         decode(s, n, j, y, x);
         const int64_t site = (int64_t)y * s.W + x;
         const int k = j + 1;
+        // the int32 bounds on flow and excess assume every data term lies in
+        // [0, cap]: node j checks cost layer j + 1, the first layer also layer 0
+        const int32_t ck = cost[(int64_t)k * s.plane + site];
+        const int32_t c0v = j == 0 ? cost[site] : 0;
+        if (ck < 0 || ck > cap || c0v < 0 || c0v > cap) atomicOr(&s.hdr->prefix_err, kCostErr);
         const bool hasE = x + 1 < s.W, hasS = y + 1 < s.H;
         if (!kWindow) {
             int32_t e = 0;
@@ -509,19 +544,8 @@ k_build(Graph s, const int32_t *__restrict__ cost, int m)
                 const int64_t psite = site + dy * (int64_t)s.W + dx;
                 const int cp = (dx == 0 && dy == 0) ? node_class(k + dir_dj(d), lo, hi)
                                                     : node_class(k + dir_dj(d), s.wlo[psite], s.whi[psite]);
-                // capacities of n -> partner and partner -> n; the unbounded
-                // chain reverse never meets a forced partner of a free node
-                int32_t cout = 0, cin = 0;
-                switch (d) {
-                case D_DOWN: cout = cost[(int64_t)k * s.plane + site]; break;
-                case D_UP:   cin = cost[(int64_t)j * s.plane + site]; break;
-                case D_E: case D_W: cout = cin = ph; break;
-                case D_S: case D_N: cout = cin = pv; break;
-                case D_EM: case D_WM: cout = s.ie; break;
-                case D_EP: case D_WP: cin = s.ie; break;
-                case D_SM: case D_NM: cout = s.is; break;
-                default: cin = s.is; break;                  // D_SP, D_NP
-                }
+                int32_t cout, cin;
+                arc_caps(s, cost, d, site, j, ph, pv, cout, cin);
                 if (cn == FREE) {
                     if (cp == FSRC) e += cin;
                     else if (cp == FSNK) { e -= cout; tsum += cout; }
@@ -616,11 +640,12 @@ k_push(Src src)
     const int64_t g = group_of(lb);
     if (!s.bact[g]) return;                   // no active node in this wavefront's group
     int64_t n = lb * kBlock + threadIdx.x;
-    int cnt = 0;
+    int cnt = 0, vis = 0;
     if (n < s.N) {
         int32_t e = s.ex[n];
         const int32_t h = s.ht[n];
         if (e > 0 && h < kInf) {
+            vis = 1;
             int j, y, x;
             decode(s, n, j, y, x);
             const unsigned ex_mask = arc_exists(s, j, y, x);
@@ -653,7 +678,9 @@ k_push(Src src)
         }
     }
     cnt = wave_sum(cnt);                      // no barrier: the wavefront finishes alone
+    vis = wave_sum(vis);
     if (lane0() && cnt) atomicAdd(&my_slot(s.slots, g).pushes, (unsigned long long)cnt);
+    if (lane0() && vis) atomicAdd(&my_slot(s.slots, g).visits, (unsigned long long)vis);
     });
 }
 
@@ -734,7 +761,7 @@ k_sweep(Src src)
     if (inflow && lane0()) s.binf[g] = 0;
     const int64_t n = lb * kBlock + threadIdx.x;
     bool active = false;
-    int cnt = 0;
+    int cnt = 0, vis = 0;
     if (n < s.N) {
         int32_t e = s.ex[n];
         const int32_t in = s.ein[n];
@@ -742,6 +769,7 @@ k_sweep(Src src)
         const int32_t e0 = e;
         if (in != 0) e += atomicExch(&s.ein[n], 0);
         if (e > 0 && h < kInf) {
+            vis = 1;
             int j, y, x;
             decode(s, n, j, y, x);
             const unsigned ex_mask = arc_exists(s, j, y, x);
@@ -784,9 +812,11 @@ k_sweep(Src src)
     }
     const bool any = wave_any(active);        // no barrier: the wavefront finishes alone
     cnt = wave_sum(cnt);
+    vis = wave_sum(vis);
     if (lane0()) {
         if (any != (was_active != 0)) s.bact[g] = any;
         if (cnt) atomicAdd(&my_slot(s.slots, g).pushes, (unsigned long long)cnt);
+        if (vis) atomicAdd(&my_slot(s.slots, g).visits, (unsigned long long)vis);
     }
     });
 }
@@ -1055,7 +1085,7 @@ __global__ void k_zero_header(DevHeader *h, int what)
     int i = threadIdx.x;
     if (what == 0) {                 // everything
         if (i < kMaxFlags) h->flags[i] = 0;
-        if (i == 0) { h->active = 0; h->prefix_err = 0; h->pushes = 0; }
+        if (i == 0) { h->active = 0; h->prefix_err = 0; h->pushes = 0; h->visits = 0; }
     } else if (what == 1) {          // relaxation flags
         if (i < kMaxFlags) h->flags[i] = 0;
     } else if (what == 2) {          // active counter
@@ -1070,9 +1100,11 @@ __global__ void k_zero_flags(DevHeader *h, int first, int count)
     if (i < count) h->flags[(first + i) % kMaxFlags] = 0;
 }
 
+// Clears the result and the read-out error bits; a data term outside
+// [0, cap] seen by the build stays flagged until the graph is rebuilt.
 __global__ void k_zero_result(int64_t *r, DevHeader *h)
 {
-    if (threadIdx.x == 0) { r[0] = 0; r[1] = 0; if (h) h->prefix_err = 0; }
+    if (threadIdx.x == 0) { r[0] = 0; r[1] = 0; if (h) h->prefix_err &= kCostErr; }
 }
 
 // Labels: X = source-side nodes in the column, which must form the prefix
@@ -1148,7 +1180,8 @@ k_zero_slots(Slot *slots, int what)
 {
     Slot &sl = slots[threadIdx.x];
     if (what == 0) {
-        sl.pushes = 0; sl.active = 0; sl.max_height = 0; sl.e0 = 0; sl.e1 = 0; sl.tcap = 0; sl.c0 = 0;
+        sl.pushes = 0; sl.visits = 0; sl.active = 0; sl.max_height = 0; sl.e0 = 0; sl.e1 = 0;
+        sl.tcap = 0; sl.c0 = 0;
     }
     else if (what == 1) { sl.active = 0; sl.max_height = 0; }
     else { sl.e0 = 0; sl.e1 = 0; }
@@ -1169,17 +1202,22 @@ k_fold_slots(const Slot *slots, DevHeader *hdr, int what, int64_t *result)
         if (threadIdx.x == 0) { hdr->active = a; hdr->max_height = m; }
     } else if (what == 1) {
         unsigned long long p = block_sum(sl.pushes);
-        if (threadIdx.x == 0) hdr->pushes = p;
+        __syncthreads();
+        unsigned long long v = block_sum(sl.visits);
+        if (threadIdx.x == 0) { hdr->pushes = p; hdr->visits = v; }
     } else if (what == 2) {
         long long e0 = block_sum(sl.e0);
         __syncthreads();
         long long e1 = block_sum(sl.e1);
         if (threadIdx.x == 0) { result[0] = e0; result[1] = e1 + hdr->tcap + hdr->c0; }
-    } else {
+    } else if (what == 3) {
         long long t = block_sum(sl.tcap);
         __syncthreads();
         long long c = block_sum(sl.c0);
         if (threadIdx.x == 0) { hdr->tcap = t; hdr->c0 = c; }
+    } else {
+        long long e0 = block_sum(sl.e0);
+        if (threadIdx.x == 0) hdr->seeded = e0;
     }
 }
 
@@ -1213,12 +1251,17 @@ k_batch_gather(BatchDev *T, int what)
     const int a = block_sum(s.slots[t].active);
     __syncthreads();
     const unsigned long long pu = block_sum(s.slots[t].pushes);
+    __syncthreads();
+    const unsigned long long vi = block_sum(s.slots[t].visits);
     if (t == 0) {
         s.hdr->active = a;
         s.hdr->pushes = pu;
+        s.hdr->visits = vi;
         T->gathered[g][0] = a;
         T->gathered[g][1] = (int32_t)(pu & 0x7fffffffULL);
         T->gathered[g][2] = (int32_t)(pu >> 31);
+        T->gathered[g][3] = (int32_t)(vi & 0x7fffffffULL);
+        T->gathered[g][4] = (int32_t)(vi >> 31);
     }
 }
 
@@ -1616,11 +1659,14 @@ inline bool timed_launch(int klass, int k)
 
 thread_local uint32_t t_class_launches[GC_K_CLASSES];
 
+struct HeaderRead;
+
 struct Launcher {
     hipStream_t st;
     bool timing;
     std::vector<int> cls;
     int launched[GC_K_CLASSES] = {};
+    HeaderRead *rb = nullptr;          // read-back landing buffer; null: the thread's pinned one
 
     hipEvent_t event(size_t i)
     {
@@ -1679,6 +1725,7 @@ struct HeaderRead {
     int32_t max_height;
     int32_t pad[13];
     unsigned long long pushes;
+    unsigned long long visits;
 };
 static_assert(sizeof(HeaderRead) == offsetof(DevHeader, tcap), "header prefix layout");
 
@@ -1727,7 +1774,7 @@ int relax_to_fixpoint(const Graph &s, int mode, const Opts &o, Launcher &L, int 
     if (tiles <= 0 && !count_active) return GC_OK;
     const int max_passes = 1 << 22;
     const unsigned grid = grid_for(s.N);
-    HeaderRead *h = header_buffer();
+    HeaderRead *h = L.rb ? L.rb : header_buffer();
     int passes = 0;
     int batch = first_batch < 1 ? 1 : first_batch > kMaxFlags - 1 ? kMaxFlags - 1 : first_batch;
     for (;;) {
@@ -1933,7 +1980,7 @@ GC_API int graph_build(const gc_problem *p, const int32_t *cost, void *ws, size_
     hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 0);
     if (s.N > 0)
         hipLaunchKernelGGL(k_build<false>, dim3(grid_for(s.N)), dim3(kBlock), 0, st, s, cost,
-                           p->labels);
+                           p->labels, p->cap);
     hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, s.slots, s.hdr, 3, nullptr);
     return hip_ok(hipGetLastError()) ? GC_OK : GC_E_HIP;
 }
@@ -1993,7 +2040,7 @@ GC_API int graph_build_window(const gc_problem *p, const int32_t *cost,
                            block, p->labels);
     if (s.N > 0)
         hipLaunchKernelGGL(k_build<true>, dim3(grid_for(s.N)), dim3(kBlock), 0, st, s, cost,
-                           p->labels);
+                           p->labels, p->cap);
     hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, s.slots, s.hdr, 3, nullptr);
     return hip_ok(hipGetLastError()) ? GC_OK : GC_E_HIP;
 }
@@ -2007,21 +2054,21 @@ static int graph_check(const gc_graph *g)
     return GC_OK;
 }
 
-GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *stats, void *stream)
+// The exact solve of maxflow_solve.  rb: read-back landing buffer (null: the
+// calling thread's pinned one).
+static int solve_graph(gc_graph *g, const Opts &opt, gc_solve_stats *stats, hipStream_t st,
+                       HeaderRead *rb)
 {
-    int rc = graph_check(g);
-    if (rc != GC_OK) return rc;
-    Opts opt = resolve(o);
-    if ((rc = check_opts(opt)) != GC_OK) return rc;
+    int rc;
     gc_solve_stats st_local;
     memset(&st_local, 0, sizeof(st_local));
     Graph s = view(g);
-    hipStream_t st = (hipStream_t)stream;
     if (s.N == 0) {
         if (stats) *stats = st_local;
         return GC_OK;
     }
     Launcher L{st, (opt.flags & GC_OPT_TIME_KERNELS) != 0, {}};
+    L.rb = rb;
     const unsigned grid = grid_for(s.N);
     const bool fused = sweep_fused(opt, s.J);
     const bool use_graph = st != nullptr && (opt.flags & GC_OPT_SWEEP_GRAPH) != 0 && !L.timing;
@@ -2041,10 +2088,12 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
         const int passes_before = st_local.bfs_passes;
         if ((rc = relax_to_fixpoint(s, 0, opt, L, &st_local.bfs_passes, true, &hr, batch_hint)) != GC_OK)
             return rc;
+        if (hr.prefix_err & kCostErr) return GC_E_CAP_OVERFLOW;
         batch_hint = st_local.bfs_passes - passes_before + 1;
         st_local.global_relabels++;
         st_local.active_last = hr.active;
         st_local.pushes = (int64_t)hr.pushes;
+        st_local.active_visits = (int64_t)hr.visits;
         if (hr.active == 0) break;
         const int period = period_for_round(opt, round, hr.max_height);
         if (st_local.sweeps >= opt.max_sweeps) { status = GC_E_NOT_CONVERGED; break; }
@@ -2072,6 +2121,15 @@ GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *st
     return status;
 }
 
+GC_API int maxflow_solve(gc_graph *g, const gc_solve_opts *o, gc_solve_stats *stats, void *stream)
+{
+    int rc = graph_check(g);
+    if (rc != GC_OK) return rc;
+    Opts opt = resolve(o);
+    if ((rc = check_opts(opt)) != GC_OK) return rc;
+    return solve_graph(g, opt, stats, (hipStream_t)stream, nullptr);
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_zero_i32(int32_t *p, int64_t n)
 {
@@ -2082,6 +2140,82 @@ k_zero_i32(int32_t *p, int64_t n)
 __global__ void k_set_i64(int64_t *p, long long v)
 {
     if (threadIdx.x == 0) *p = v;
+}
+
+// Warm start of an exact solve from a solved thin-skin graph of the same
+// problem and data term.  The skin's build folded every arc between a free
+// and a forced node: arcs from forced-source nodes were taken as saturated
+// (their capacity added to the free node's excess), arcs into forced-sink
+// nodes likewise (their capacity a deficit of the free node), and its stored
+// words already hold those saturations.  The same flows on the full graph
+// give a pseudoflow (capacities respected, imbalance anywhere): free nodes
+// take the skin's excess and the words of their arcs, forced nodes keep the
+// fresh build's words towards forced partners and get the imbalance of the
+// saturated arcs (a forced-source node loses what it sent into the skin, a
+// forced-sink node gains what it received).  Heights restart at 0: the
+// solve begins with an exact global relabel.  Slots' e0 collects the total
+// positive excess, which bounds every node's excess from then on.
+__global__ void __launch_bounds__(kBlock)
+k_warm_start(Graph f, Graph k, const int32_t *__restrict__ cost)
+{
+    const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    long long pos = 0;
+    if (n < f.N) {
+        int j, y, x;
+        decode(f, n, j, y, x);
+        const int64_t site = (int64_t)y * f.W + x;
+        const int kk = j + 1;
+        const int cn = node_class(kk, k.wlo[site], k.whi[site]);
+        const unsigned ex_mask = arc_exists(f, j, y, x);
+        const int ph = f.te / 2, pv = f.ts / 2;
+        int32_t e = 0;
+#pragma unroll
+        for (int d = 0; d < 14; ++d) {
+            if (!((ex_mask >> d) & 1u)) continue;
+            const int64_t psite = site + dir_dy(d) * (int64_t)f.W + dir_dx(d);
+            const int cp = node_class(kk + dir_dj(d), k.wlo[psite], k.whi[psite]);
+            if (word_is_forward(d) && (cn == FREE || cp == FREE))
+                *word_ptr(f, n, d) = *word_ptr(k, n, d);
+            if (cn != FREE && cp == FREE) {
+                int32_t cout, cin;
+                arc_caps(f, cost, d, site, j, ph, pv, cout, cin);
+                e += cn == FSRC ? -cout : cin;
+            }
+        }
+        const int32_t ex = cn == FREE ? k.ex[n] : f.ex[n] + e;
+        f.ex[n] = ex;
+        f.ht[n] = 0;
+        f.ein[n] = 0;
+        pos = ex > 0 ? ex : 0;
+    }
+    pos = block_sum(pos);
+    if (threadIdx.x == 0 && pos) atomicAdd((unsigned long long *)&my_slot(f.slots, blockIdx.x).e0,
+                                           (unsigned long long)pos);
+}
+
+GC_API int graph_warm_start(gc_graph *g, const gc_graph *skin, const int32_t *cost, void *stream)
+{
+    int rc = graph_check(g);
+    if (rc != GC_OK) return rc;
+    if ((rc = graph_check(skin)) != GC_OK) return rc;
+    if (!cost || g->window_block != 0 || skin->window_block < 1) return GC_E_ARG;
+    if (memcmp(&g->p, &skin->p, sizeof(gc_problem)) != 0) return GC_E_ARG;
+    Graph f = view(g), k = view(skin);
+    hipStream_t st = (hipStream_t)stream;
+    if (f.N == 0) return GC_OK;
+    hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, f.slots, 2);
+    hipLaunchKernelGGL(k_warm_start, dim3(grid_for(f.N)), dim3(kBlock), 0, st, f, k, cost);
+    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, f.slots, f.hdr, 4, nullptr);
+    // the relaxation flags and activity flags of the fresh build stay valid:
+    // the solve's first global relabel recomputes every height, and every
+    // 64-node group is marked by its first termination count
+    if (!hip_ok(hipGetLastError())) return GC_E_HIP;
+    long long seeded = 0;
+    if (!hip_ok(hipMemcpyAsync(&seeded, &f.hdr->seeded, sizeof(seeded), hipMemcpyDeviceToHost, st)))
+        return GC_E_HIP;
+    if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
+    // a node's excess never exceeds the total positive excess: keep it in int32
+    return seeded >= (1LL << 30) ? GC_E_CAP_OVERFLOW : GC_OK;
 }
 
 GC_API int approx_level2_cut(gc_graph *skin, const int32_t *cost, const int32_t *coarse_labels,
@@ -2135,7 +2269,8 @@ GC_API int approx_level2_cut(gc_graph *skin, const int32_t *cost, const int32_t 
     if (!hip_ok(hipGetLastError())) return GC_E_HIP;
     int32_t perr = 0;
     if ((rc = read_i32(&s.hdr->prefix_err, &perr, st)) != GC_OK) return rc;
-    return (perr & 2) ? GC_E_NOT_CONVERGED : (perr & 1) ? GC_E_PREFIX : GC_OK;
+    return (perr & kCostErr) ? GC_E_CAP_OVERFLOW : (perr & 2) ? GC_E_NOT_CONVERGED
+         : (perr & 1) ? GC_E_PREFIX : GC_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -2382,6 +2517,7 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
         m.st.global_relabels++;
         m.st.active_last = gv[0];
         m.st.pushes = (int64_t)(uint32_t)gv[1] | ((int64_t)(uint32_t)gv[2] << 31);
+        m.st.active_visits = (int64_t)(uint32_t)gv[3] | ((int64_t)(uint32_t)gv[4] << 31);
         const bool finished = gv[0] == 0 || m.st.sweeps >= o.max_sweeps;
         if (finished && *n_done < max_done) {
             done_tags[*n_done] = m.tag;
@@ -2557,17 +2693,16 @@ GC_API int gc_graph_state(const gc_graph *g, int32_t *excess, int32_t *words, vo
     return GC_OK;
 }
 
-GC_API int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *labels,
-                          int64_t *result, void *stream)
+// The read-out of extract_labels (rb as for solve_graph).
+static int extract_graph(const gc_graph *g, const int32_t *cost, int32_t *labels, int64_t *result,
+                         hipStream_t st, HeaderRead *rb)
 {
-    int rc = graph_check(g);
-    if (rc != GC_OK) return rc;
-    if (!cost || !labels || !result) return GC_E_ARG;
+    int rc;
     Graph s = view(g);
-    hipStream_t st = (hipStream_t)stream;
     const gc_problem &p = g->p;
     Opts opt = resolve(nullptr);
     Launcher L{st, false, {}};
+    L.rb = rb;
     int passes = 0;
     if (s.N > 0) {
         const unsigned grid = grid_for(s.N);
@@ -2590,5 +2725,15 @@ GC_API int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *label
     if (!hip_ok(hipGetLastError())) return GC_E_HIP;
     int32_t perr = 0;
     if ((rc = read_i32(&s.hdr->prefix_err, &perr, st)) != GC_OK) return rc;
-    return perr ? GC_E_PREFIX : GC_OK;
+    return (perr & kCostErr) ? GC_E_CAP_OVERFLOW : perr ? GC_E_PREFIX : GC_OK;
 }
+
+GC_API int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *labels,
+                          int64_t *result, void *stream)
+{
+    int rc = graph_check(g);
+    if (rc != GC_OK) return rc;
+    if (!cost || !labels || !result) return GC_E_ARG;
+    return extract_graph(g, cost, labels, result, (hipStream_t)stream, nullptr);
+}
+

@@ -51,13 +51,14 @@ class GcSolveStats(ctypes.Structure):
     _fields_ = [("pushes", ctypes.c_int64), ("sweeps", ctypes.c_int32),
                 ("global_relabels", ctypes.c_int32), ("bfs_passes", ctypes.c_int32),
                 ("active_last", ctypes.c_int32), ("kernel_launches", ctypes.c_int32 * 4),
-                ("kernel_ms", ctypes.c_double * 4), ("done_ms", ctypes.c_double)]
+                ("kernel_ms", ctypes.c_double * 4), ("done_ms", ctypes.c_double),
+                ("active_visits", ctypes.c_int64)]
 
     def as_dict(self):
         d = {"pushes": int(self.pushes), "sweeps": int(self.sweeps),
              "global_relabels": int(self.global_relabels),
              "bfs_passes": int(self.bfs_passes), "active_last": int(self.active_last),
-             "done_ms": float(self.done_ms)}
+             "done_ms": float(self.done_ms), "active_visits": int(self.active_visits)}
         for i, k in enumerate(KERNEL_CLASSES):
             d[f"{k}_launches"] = int(self.kernel_launches[i])
             d[f"{k}_ms"] = float(self.kernel_ms[i])
@@ -69,7 +70,7 @@ EXPORTS = ("gc_status_str", "gc_last_hip_error", "gc_problem_check", "gc_graph_f
            "extract_labels", "gc_graph_state",
            "gc_coarse_problem", "coarse_cost_volume", "graph_build_window", "approx_level2_cut",
            "gc_batch_footprint_bytes", "gc_batch_create", "gc_batch_destroy", "gc_batch_members",
-           "gc_batch_add", "gc_batch_round", "maxflow_solve_batch")
+           "gc_batch_add", "gc_batch_round", "maxflow_solve_batch", "graph_warm_start")
 
 _lib = None
 
@@ -126,6 +127,8 @@ def load(path: str = LIB_PATH):
     lib.graph_build_window.restype = ctypes.c_int
     lib.approx_level2_cut.argtypes = [ctypes.POINTER(GcGraph), P, P, ctypes.c_int32, P, P, P]
     lib.approx_level2_cut.restype = ctypes.c_int
+    lib.graph_warm_start.argtypes = [ctypes.POINTER(GcGraph), ctypes.POINTER(GcGraph), P, P]
+    lib.graph_warm_start.restype = ctypes.c_int
     lib.gc_batch_footprint_bytes.argtypes = []
     lib.gc_batch_footprint_bytes.restype = ctypes.c_size_t
     lib.gc_batch_create.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(GcSolveOpts), ctypes.POINTER(P)]
@@ -351,6 +354,48 @@ def approx_level1(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = Non
         approx_level2_cut(gfine, cost, clab, labels, res, stream, wave_steps)
     r = res.cpu()
     return labels, int(r[0]), int(r[1]), clab, (st_c, st_f)
+
+
+def graph_warm_start(graph: Graph, skin: Graph, cost, stream=None):
+    _check(load().graph_warm_start(ctypes.byref(graph.handle), ctypes.byref(skin.handle),
+                                   ctypes.c_void_p(cost.data_ptr()), _stream_ptr(stream)),
+           "graph_warm_start")
+
+
+def solve_warm(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, stream=None,
+               ws=None, ws_skin=None, ws_coarse=None, approx_opts: GcSolveOpts | None = None):
+    """Exact cut seeded from the level-1 approximation: delegate-point cut,
+    thin-skin cut, then the full graph warm-started from the skin's state and
+    solved exactly.  Returns (labels, energy, flow, (coarse, skin, full
+    stats), the solved full graph)."""
+    import torch
+    dev = cost.device
+    if approx_opts is None:
+        approx_opts = GcSolveOpts(relabel_period=APPROX_RELABEL_PERIOD)
+    c = coarse_problem(p, block)
+    ccost = torch.empty((c.labels, c.height, c.width), dtype=torch.int32, device=dev)
+    clab = torch.empty((c.height, c.width), dtype=torch.int32, device=dev)
+    cres = torch.zeros(2, dtype=torch.int64, device=dev)
+    if ws_coarse is None:
+        ws_coarse = alloc_workspace(c, dev)
+    if ws_skin is None:
+        ws_skin = alloc_workspace(p, dev)
+    if ws is None:
+        ws = alloc_workspace(p, dev)
+    coarse_cost_volume(p, cost, block, ccost, stream)
+    gcoarse = graph_build(c, ccost, ws_coarse, stream)
+    st_c = maxflow_solve(gcoarse, approx_opts, stream)
+    extract_labels(gcoarse, ccost, clab, cres, stream)
+    gskin = graph_build_window(p, cost, clab, block, ws_skin, stream)
+    st_s = maxflow_solve(gskin, approx_opts, stream)
+    g = graph_build(p, cost, ws, stream)
+    graph_warm_start(g, gskin, cost, stream)
+    st_f = maxflow_solve(g, opts, stream)
+    labels = torch.empty((p.height, p.width), dtype=torch.int32, device=dev)
+    res = torch.zeros(2, dtype=torch.int64, device=dev)
+    extract_labels(g, cost, labels, res, stream)
+    r = res.cpu()
+    return labels, int(r[0]), int(r[1]), (st_c, st_s, st_f), g
 
 
 def approx_level2(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, stream=None,

@@ -157,6 +157,38 @@ def test_empty_problem(torch_cuda):
     assert res.cpu().tolist() == [0, 0]
 
 
+@pytest.mark.parametrize("where,value", [("layer0", 31), ("inner", 10 ** 6), ("last", -1)])
+def test_data_term_outside_cap_rejected(torch_cuda, where, value):
+    """A data term outside [0, cap] would void the int32 bounds on flow and
+    excess: the build flags it and the solve and the read-out refuse the graph;
+    a rebuild from a valid cost clears the flag."""
+    torch = torch_cuda
+    w, h, m, cap = 20, 6, 5, 30
+    rng = np.random.default_rng(11)
+    cost_np = rng.integers(0, cap + 1, size=(m, h, w), dtype=np.int32)
+    bad = cost_np.copy()
+    j = {"layer0": 0, "inner": 2, "last": m - 1}[where]
+    bad[j, 3, 7] = value
+    p = gc.problem(w, h, m, cap, 1, 1023)
+    ws = gc.alloc_workspace(p)
+    lab = torch.empty((h, w), dtype=torch.int32, device="cuda")
+    res = torch.zeros(2, dtype=torch.int64, device="cuda")
+    cbad = torch.from_numpy(bad).cuda()
+    g = gc.graph_build(p, cbad, ws)
+    with pytest.raises(gc.GazecutError) as e1:
+        gc.maxflow_solve(g)
+    assert e1.value.status == -4
+    with pytest.raises(gc.GazecutError) as e2:
+        gc.extract_labels(g, cbad, lab, res)
+    assert e2.value.status == -4
+    cgood = torch.from_numpy(cost_np).cuda()
+    g = gc.graph_build(p, cgood, ws)
+    gc.maxflow_solve(g)
+    gc.extract_labels(g, cgood, lab, res)
+    r = res.cpu().tolist()
+    assert r[0] == r[1]
+
+
 @pytest.mark.parametrize("lam,inh_h,inh_v", [(1, 1023, 1023), (2, 1023, 1023), (1, 0, 0), (1, 1023, 0)],
                          ids=["lam1", "lam2", "inhibit0", "inhibit-h-only"])
 def test_mid_parity_full_size(torch_cuda, orc, lam, inh_h, inh_v):
@@ -392,3 +424,71 @@ def test_approx_level2_blocks_alone_are_exact(torch_cuda, orc, b):
         labels, energy, _, _, _ = gc.approx_level2(p, cost, b, wave_steps=0)
         emin, _, _, back = orc.brute_force(cost_np, 1, 5)
         assert energy == emin and (labels.cpu().numpy() == back).all()
+
+
+_WARM_OPTS = {"default": None,
+              "wave-first": gc.GcSolveOpts(flags=gc.GC_OPT_WAVE_FIRST),
+              "fused": gc.GcSolveOpts(flags=gc.GC_OPT_FUSED_SWEEP),
+              "period-13-split": gc.GcSolveOpts(relabel_period=13, flags=gc.GC_OPT_SPLIT_SWEEP)}
+
+
+@pytest.mark.parametrize("opt", list(_WARM_OPTS))
+@pytest.mark.parametrize("b", [1, 2, 3])
+@pytest.mark.parametrize("spec,seed", [(sg.TINY, (1, 0)), (sg.spec_like(sg.MID, 70, 33, 9), (9, 8)),
+                                       (sg.spec_like(sg.LARGE, 61, 47, 21), (3, 7))],
+                         ids=["tiny", "ragged-70x33x9", "textureless-61x47x21"])
+def test_warm_start_exact_parity(torch_cuda, orc, opt, b, spec, seed):
+    """The exact solve seeded from the level-1 skin's state ends in the
+    oracle's exact cut: same labels (minimal source side), energy and flow."""
+    pr = sg.make_pair(spec, seed)
+    p = gc.problem(spec.w, spec.h, spec.m, spec.cap, spec.lam, spec.inhibit)
+    cost = _cost_gpu(torch_cuda, pr.left, pr.right, p)
+    print(f"warm start {spec.w}x{spec.h}x{spec.m} b={b} opts={opt}", flush=True)
+    labels, energy, flow, sts, _ = gc.solve_warm(p, cost, b, _WARM_OPTS[opt])
+    _check_against_oracle(orc, cost.cpu().numpy(), labels.cpu().numpy(), energy, flow,
+                          (spec.lam, spec.inhibit, spec.lam, spec.inhibit))
+    assert sts[2].active_last == 0
+
+
+@pytest.mark.parametrize("b", [2, 3])
+def test_warm_start_mid_full_size(torch_cuda, orc, certify, b):
+    """384x288x16: the warm-started solve against the oracle, and its final
+    state (a pseudoflow: forced-source levels may end with deficits) through
+    the host certificate."""
+    pr = sg.make_pair(sg.MID, (2, 3))
+    p = gc.problem(sg.MID.w, sg.MID.h, sg.MID.m, sg.MID.cap, 1, 1023)
+    cost = _cost_gpu(torch_cuda, pr.left, pr.right, p)
+    labels, energy, flow, sts, g = gc.solve_warm(p, cost, b)
+    cost_np = cost.cpu().numpy()
+    lab = labels.cpu().numpy()
+    _check_against_oracle(orc, cost_np, lab, energy, flow, (1, 1023, 1, 1023))
+    f_host, e_host = certify(g, cost_np, lab, (1, 1023, 1, 1023))
+    assert f_host == e_host == energy
+
+
+def test_warm_start_large_full_size(torch_cuda):
+    """450x375x64 warm-started from level 1 (b = 3) against the stored oracle
+    cut."""
+    gold = np.load(os.path.join(GOLDEN, "large_450x375x64_seed3-0_lam1.npz"))
+    seed = tuple(int(v) for v in gold["seed"])
+    pr = sg.make_pair(sg.LARGE, seed)
+    p = gc.problem(sg.LARGE.w, sg.LARGE.h, sg.LARGE.m, sg.LARGE.cap, 1, 1023)
+    cost = _cost_gpu(torch_cuda, pr.left, pr.right, p)
+    labels, energy, flow, _, _ = gc.solve_warm(p, cost, 3)
+    assert flow == int(gold["flow"]) and energy == int(gold["energy"])
+    assert (labels.cpu().numpy() == gold["labels"].astype(np.int32)).all()
+
+
+def test_warm_start_rejects_wrong_graphs(torch_cuda):
+    p = gc.problem(20, 10, 6, 30, 1, 1023)
+    q = gc.problem(20, 10, 6, 30, 2, 1023)
+    rng = np.random.default_rng(5)
+    cost = torch_cuda.from_numpy(rng.integers(0, 31, (6, 10, 20)).astype(np.int32)).cuda()
+    cl = torch_cuda.zeros((4, 7), dtype=torch_cuda.int32, device="cuda")
+    full = gc.graph_build(p, cost, gc.alloc_workspace(p))
+    skin = gc.graph_build_window(p, cost, cl, 3, gc.alloc_workspace(p))
+    skin_q = gc.graph_build_window(q, cost, cl, 3, gc.alloc_workspace(q))
+    for a, b_ in ((full, full), (skin, skin), (full, skin_q)):
+        with pytest.raises(gc.GazecutError) as e:
+            gc.graph_warm_start(a, b_, cost)
+        assert e.value.status == -1
