@@ -420,6 +420,43 @@ int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solve_stats
 int maxflow_solve_batch(gc_graph *const *gs, int32_t n, void *dev_table, size_t dev_bytes,
                         const gc_solve_opts *o, gc_solve_stats *stats, void *stream);
 
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc: work recorded under stream capture, tight serving loops,
+ * harnesses that forbid allocation).
+ *
+ * gc_solve_pair_static runs the exact path of one pair, the sequence
+ * stereo_cost_volume -> graph_build -> maxflow_solve -> extract_labels, with
+ * the cost volume and the graph's workspace in a static device array of
+ * GC_STATIC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends (looked up once per device on the first call there).
+ * It calls no hipMalloc, hipFree, hipHostMalloc or other allocating routine;
+ * read-backs land in pageable host memory on the caller's stack.
+ * left, right: DEVICE uint8 [height][width] as for stereo_cost_volume.
+ * o:      host options or NULL; GC_OPT_TIME_KERNELS and GC_OPT_SWEEP_GRAPH
+ *         are refused (GC_E_ARG): they create events or graphs.
+ * labels: DEVICE int32 [height][width], written.
+ * result: DEVICE int64[2], written as by extract_labels.
+ * stats:  host struct or NULL, as for maxflow_solve.
+ * The device whose array is used is the current one; stream must belong to
+ * it.  Every call on one GPU shares that GPU's array, and the array keeps the
+ * last call's contents (the path initialises every byte it reads): calls that
+ * overlap on one GPU, on any streams or host threads, race and must be
+ * serialised by the caller.
+ * Errors: GC_E_WORKSPACE when gc_solve_pair_static_bytes(p) exceeds
+ * GC_STATIC_SCRATCH_BYTES, the errors of the four calls it stands for,
+ * GC_E_HIP when the array's device address cannot be found. */
+#define GC_STATIC_SCRATCH_BYTES (96u << 20)
+
+/* Bytes of the static array one pair of `p` needs (cost volume + graph
+ * workspace, 256-byte aligned); 0 for an invalid problem.  About 83 MB at
+ * 384x288x16. */
+size_t gc_solve_pair_static_bytes(const gc_problem *p);
+
+int gc_solve_pair_static(const uint8_t *left, const uint8_t *right, const gc_problem *p,
+                         const gc_solve_opts *o, int32_t *labels, int64_t *result,
+                         gc_solve_stats *stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

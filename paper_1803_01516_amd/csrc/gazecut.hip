@@ -42,6 +42,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <thread>
@@ -2737,3 +2738,70 @@ GC_API int extract_labels(const gc_graph *g, const int32_t *cost, int32_t *label
     return extract_graph(g, cost, labels, result, (hipStream_t)stream, nullptr);
 }
 
+// ---------------------------------------------------------------------------
+// The path without allocation: the cost volume and the graph live in a
+// file-scope device array.  In host code `scratch` names a host-side stand-in,
+// not device memory: only the address hipGetSymbolAddress returns for the
+// current device may reach a kernel or a copy.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) unsigned char scratch[GC_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void *g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+// Device address of this device's copy of `scratch` (looked up once per
+// device, with that device current), or null when the lookup failed.
+void *scratch_address(int dev)
+{
+    std::call_once(g_scratch_once[dev], [dev] {
+        void *ptr = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? ptr : nullptr;
+    });
+    if (!g_scratch_ptr[dev]) t_last_hip = (int)g_scratch_err[dev];
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+GC_API size_t gc_solve_pair_static_bytes(const gc_problem *p)
+{
+    if (gc_problem_check(p) != GC_OK) return 0;
+    const size_t cost = align256((size_t)p->labels * p->height * p->width * sizeof(int32_t));
+    return cost + gc_graph_footprint_bytes(p);
+}
+
+GC_API int gc_solve_pair_static(const uint8_t *left, const uint8_t *right, const gc_problem *p,
+                                const gc_solve_opts *o, int32_t *labels, int64_t *result,
+                                gc_solve_stats *stats, void *stream)
+{
+    int rc = gc_problem_check(p);
+    if (rc != GC_OK) return rc;
+    if (!left || !right || !labels || !result) return GC_E_ARG;
+    Opts opt = resolve(o);
+    if ((rc = check_opts(opt)) != GC_OK) return rc;
+    // kernel timing creates events, captured sweeps instantiate graphs
+    if (opt.flags & (GC_OPT_TIME_KERNELS | GC_OPT_SWEEP_GRAPH)) return GC_E_ARG;
+    const size_t need = gc_solve_pair_static_bytes(p);
+    if (need > sizeof(scratch)) return GC_E_WORKSPACE;
+    int dev = 0;
+    if (!hip_ok(hipGetDevice(&dev))) return GC_E_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return GC_E_ARG;
+    unsigned char *base = (unsigned char *)scratch_address(dev);
+    if (!base) return GC_E_HIP;
+    hipStream_t st = (hipStream_t)stream;
+    int32_t *cost = (int32_t *)base;
+    const size_t cost_bytes = align256((size_t)p->labels * p->height * p->width * sizeof(int32_t));
+    gc_graph g;
+    if ((rc = stereo_cost_volume(left, right, p, cost, stream)) != GC_OK) return rc;
+    if ((rc = graph_build(p, cost, base + cost_bytes, sizeof(scratch) - cost_bytes, &g, stream)) != GC_OK)
+        return rc;
+    HeaderRead rb;                     // pageable: pinned memory would be an allocation
+    if ((rc = solve_graph(&g, opt, stats, st, &rb)) != GC_OK) return rc;
+    return extract_graph(&g, cost, labels, result, st, &rb);
+}

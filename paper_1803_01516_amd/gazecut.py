@@ -44,6 +44,7 @@ GC_OPT_FIXED_PERIOD = 32
 GC_OPT_BATCH_MERGED = 128
 GC_BATCH_LANES = 4
 GC_BATCH_MAX_GRAPHS = 256
+GC_STATIC_SCRATCH_BYTES = 96 << 20
 KERNEL_CLASSES = ("push", "relabel", "relax", "other")
 
 
@@ -70,7 +71,8 @@ EXPORTS = ("gc_status_str", "gc_last_hip_error", "gc_problem_check", "gc_graph_f
            "extract_labels", "gc_graph_state",
            "gc_coarse_problem", "coarse_cost_volume", "graph_build_window", "approx_level2_cut",
            "gc_batch_footprint_bytes", "gc_batch_create", "gc_batch_destroy", "gc_batch_members",
-           "gc_batch_add", "gc_batch_round", "maxflow_solve_batch", "graph_warm_start")
+           "gc_batch_add", "gc_batch_round", "maxflow_solve_batch",
+           "gc_solve_pair_static_bytes", "gc_solve_pair_static", "graph_warm_start")
 
 _lib = None
 
@@ -146,6 +148,11 @@ def load(path: str = LIB_PATH):
                                         ctypes.c_size_t, ctypes.POINTER(GcSolveOpts),
                                         ctypes.POINTER(GcSolveStats), P]
     lib.maxflow_solve_batch.restype = ctypes.c_int
+    lib.gc_solve_pair_static_bytes.argtypes = [ctypes.POINTER(GcProblem)]
+    lib.gc_solve_pair_static_bytes.restype = ctypes.c_size_t
+    lib.gc_solve_pair_static.argtypes = [P, P, ctypes.POINTER(GcProblem), ctypes.POINTER(GcSolveOpts),
+                                         P, P, ctypes.POINTER(GcSolveStats), P]
+    lib.gc_solve_pair_static.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -216,6 +223,25 @@ def maxflow_solve(graph: Graph, opts: GcSolveOpts | None = None, stream=None,
                               ctypes.byref(st), _stream_ptr(stream))
     if not (allow_not_converged and rc == GC_E_NOT_CONVERGED):
         _check(rc, "maxflow_solve")
+    return st
+
+
+def solve_pair_static_bytes(p: GcProblem) -> int:
+    return int(load().gc_solve_pair_static_bytes(ctypes.byref(p)))
+
+
+def solve_pair_static(left, right, p: GcProblem, labels, result, opts: GcSolveOpts | None = None,
+                      stream=None) -> GcSolveStats:
+    """The whole exact path on one pair with the cost volume and the graph in
+    the library's static device array (no allocation by the library).
+    labels: int32 [h][w], result: int64 [2] CUDA tensors (written)."""
+    st = GcSolveStats()
+    _check(load().gc_solve_pair_static(ctypes.c_void_p(left.data_ptr()),
+                                       ctypes.c_void_p(right.data_ptr()), ctypes.byref(p),
+                                       ctypes.byref(opts) if opts is not None else None,
+                                       ctypes.c_void_p(labels.data_ptr()),
+                                       ctypes.c_void_p(result.data_ptr()), ctypes.byref(st),
+                                       _stream_ptr(stream)), "gc_solve_pair_static")
     return st
 
 
