@@ -136,6 +136,15 @@ typedef struct {
  * Batched merged rounds always run full periods. */
 #define GC_OPT_FIXED_PERIOD 32
 
+/* gc_solve_opts.flags: work-list launches for single graphs.  Every sweep
+ * runs over the 256-node blocks a compaction launch lists as holding an
+ * active node (or inflow), and every relaxation pass over the tiles whose
+ * neighbourhood changed in the pass before, each on a fixed grid of
+ * workgroups.  Off by default (one workgroup per block or tile of the whole
+ * graph): measured slower on single graphs.  The result does not depend on
+ * it. */
+#define GC_OPT_LISTS 256
+
 /* Kernel classes of gc_solve_stats.kernel_ms / kernel_launches. */
 #define GC_K_PUSH 0           /* push sweep, or fused push-relabel sweep       */
 #define GC_K_RELABEL 1        /* relabel sweep (also merges inflow)           */

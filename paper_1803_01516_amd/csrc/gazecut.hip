@@ -89,7 +89,8 @@ struct DevHeader {
     int32_t active;
     int32_t prefix_err;
     int32_t max_height;       // largest height of an active node at the last count
-    int32_t pad[13];
+    int32_t lists[4];         // lengths of the block list (0, 1) and the tile list (2, 3)
+    int32_t pad[9];
     unsigned long long pushes;
     unsigned long long visits;  // active nodes visited by the push (or fused) sweeps
     long long tcap;           // capacity of all arcs into the sink side
@@ -117,6 +118,7 @@ struct Graph {
     int32_t *ex, *ht, *rd, *re, *rs, *rem, *rep, *rsm, *rsp, *ein, *aux;
     uint16_t *mask;
     int32_t *stamps;          // per relaxation tile: last pass that changed it
+    int32_t *blist, *tlist;   // work lists: 256-node blocks of a sweep, tiles of a relaxation pass
     int32_t *wlo, *whi;       // per-site label window of a thin-skin graph
     uint8_t *bact;            // per 64-node group: holds an active node
     uint8_t *binf;            // per 64-node group: received inflow in the last push sweep
@@ -178,7 +180,9 @@ Graph view(const gc_graph *g)
     s.whi = (int32_t *)b; b += align256((size_t)s.plane * 4);
     s.bact = (uint8_t *)b; b += align256(flag_bytes(s.N));
     s.binf = (uint8_t *)b; b += align256(flag_bytes(s.N));
-    s.stamps = (int32_t *)b;
+    s.stamps = (int32_t *)b; b += align256(max_tiles(&p) * 4);
+    s.blist = (int32_t *)b; b += align256((size_t)((s.N + kBlock - 1) / kBlock) * 4);
+    s.tlist = (int32_t *)b;
     s.te = 2 * p.penalty_h; s.ts = 2 * p.penalty_v;
     s.ie = p.inhibit_h; s.is = p.inhibit_v;
     s.win = g->window_block > 0 ? 1 : 0;
@@ -307,6 +311,44 @@ __device__ inline void for_blocks(const Batch &b, int which, F &&f)
     // out that the store aliases the table)
     const Graph g = T->graphs[lo];
     f(g, vb - off[lo]);
+}
+
+// A list-driven launch over one graph: the workgroups of a fixed grid take
+// the ids of a device list in turn (256-node blocks for the sweeps, tiles
+// for a relaxation pass), so a launch costs its listed work and a grid of
+// fixed size instead of one workgroup per block of the whole graph.
+struct Listed {
+    Graph s;
+    const int32_t *ids;
+    const int32_t *count;
+};
+
+template <class F>
+__device__ inline void for_blocks(const Listed &L, int, F &&f)
+{
+    const int n = *L.count;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) f(L.s, (int64_t)L.ids[i]);
+}
+
+// Workgroup-wide compaction: every thread with `want` gets a distinct slot
+// of ids[] (one atomic per workgroup on *count) and stores `id` there.
+__device__ inline void block_append(bool want, int32_t id, int32_t *ids, int32_t *count)
+{
+    __shared__ int wave_n[kBlock / 64], base;
+    const unsigned long long bal = __ballot(want);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) wave_n[w] = __popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int i = 0; i < kBlock / 64; ++i) { const int c = wave_n[i]; wave_n[i] = t; t += c; }
+        base = t ? atomicAdd(count, t) : 0;
+    }
+    __syncthreads();
+    if (want) {
+        const int rank = __popcll(bal & ((1ULL << lane) - 1ULL));
+        ids[base + wave_n[w] + rank] = id;
+    }
 }
 
 // Node counts stay below 2^29 (checked on the host), so 32-bit division is exact.
@@ -633,11 +675,8 @@ k_coarse_cost(const int32_t *__restrict__ cost, int W, int H, int m, int b,
 // words are loaded next (a second round of memory latency that saves most
 // word loads).  Pushes then run in registers and write the new words
 // directly.
-template <class Src>
-__global__ void __launch_bounds__(kBlock)
-k_push(Src src)
+__device__ inline void push_blk(const Graph &s, int64_t lb)
 {
-    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
     const int64_t g = group_of(lb);
     if (!s.bact[g]) return;                   // no active node in this wavefront's group
     int64_t n = lb * kBlock + threadIdx.x;
@@ -682,16 +721,19 @@ k_push(Src src)
     vis = wave_sum(vis);
     if (lane0() && cnt) atomicAdd(&my_slot(s.slots, g).pushes, (unsigned long long)cnt);
     if (lane0() && vis) atomicAdd(&my_slot(s.slots, g).visits, (unsigned long long)vis);
-    });
+}
+
+template <class Src>
+__global__ void __launch_bounds__(kBlock)
+k_push(Src src)
+{
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { push_blk(s, lb); });
 }
 
 // Relabel sweep: merges the inflow of the push sweep, then lifts every
 // active node to one above its lowest residual neighbour.
-template <class Src>
-__global__ void __launch_bounds__(kBlock)
-k_relabel(Src src)
+__device__ inline void relabel_blk(const Graph &s, int64_t lb)
 {
-    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
     // Loads that do not depend on each other are written before the first
     // use or store, so they go out together (the compiler cannot move a load
     // above a store to another of the state arrays: they might alias).
@@ -734,7 +776,13 @@ k_relabel(Src src)
         if (any != (was_active != 0)) s.bact[g] = any;
         if (got_inflow) s.binf[g] = 0;
     }
-    });
+}
+
+template <class Src>
+__global__ void __launch_bounds__(kBlock)
+k_relabel(Src src)
+{
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { relabel_blk(s, lb); });
 }
 
 // Fused sweep: one kernel per push-relabel step.  Every node of a 64-node
@@ -747,11 +795,8 @@ k_relabel(Src src)
 // word every residual stays within [0, pair total] whatever the order.  The
 // labelling may lose validity between global relabels; only the exact global
 // relabel decides termination, so the final state is the same max preflow.
-template <class Src>
-__global__ void __launch_bounds__(kBlock)
-k_sweep(Src src)
+__device__ inline void sweep_blk(const Graph &s, int64_t lb)
 {
-    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
     const int64_t g = group_of(lb);
     const uint8_t inflow = s.binf[g], was_active = s.bact[g];
     if (!inflow && !was_active) return;
@@ -819,18 +864,21 @@ k_sweep(Src src)
         if (cnt) atomicAdd(&my_slot(s.slots, g).pushes, (unsigned long long)cnt);
         if (vis) atomicAdd(&my_slot(s.slots, g).visits, (unsigned long long)vis);
     }
-    });
+}
+
+template <class Src>
+__global__ void __launch_bounds__(kBlock)
+k_sweep(Src src)
+{
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { sweep_blk(s, lb); });
 }
 
 // Merges the inflow left by the last fused sweep into the excess.  Every
 // node is visited: a group's inflow flag is cleared and set by different
 // wavefronts of one sweep without ordering, so it may read 0 while inflow is
 // pending.
-template <class Src>
-__global__ void __launch_bounds__(kBlock)
-k_merge(Src src)
+__device__ inline void merge_blk(const Graph &s, int64_t lb)
 {
-    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
     const int64_t n = lb * kBlock + threadIdx.x;
     if (n >= s.N) return;
     const int32_t in = s.ein[n];
@@ -838,7 +886,59 @@ k_merge(Src src)
         s.ex[n] += in;
         s.ein[n] = 0;
     }
-    });
+}
+
+template <class Src>
+__global__ void __launch_bounds__(kBlock)
+k_merge(Src src)
+{
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { merge_blk(s, lb); });
+}
+
+// Work list of the next sweep: the 256-node blocks that hold a group with an
+// active node (which 1: push sweeps) or with an active node or inflow
+// (which 0: fused and relabel sweeps).  The list's length is counted in
+// lists[par], and lists[par ^ 1] is cleared for the next list, whose
+// previous reader has finished (launches on one stream run in order).
+__global__ void __launch_bounds__(kBlock)
+k_list_blocks(Graph s, int par, int which)
+{
+    const int64_t lb = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    const int64_t nb = (s.N + kBlock - 1) / kBlock;
+    bool want = false;
+    if (lb < nb) {
+        const uint32_t a = *(const uint32_t *)(s.bact + 4 * lb);
+        const uint32_t f = which == 0 ? *(const uint32_t *)(s.binf + 4 * lb) : 0u;
+        want = (a | f) != 0u;
+    }
+    block_append(want, (int32_t)lb, s.blist, &s.hdr->lists[par]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) s.hdr->lists[par ^ 1] = 0;
+}
+
+// Work list of relaxation pass `pass`: every tile in pass 1, afterwards the
+// tiles with a tile of their 3x3x3 neighbourhood changed in the pass before
+// (the test k_relax makes for itself).  Counted in lists[2 + par].
+__global__ void __launch_bounds__(kBlock)
+k_list_tiles(Graph s, int pass, int par, int tw, int th, int tj)
+{
+    const int ntx = (s.W + tw - 1) / tw, nty = (s.H + th - 1) / th, ntz = (s.J + tj - 1) / tj;
+    const int64_t nt = (int64_t)ntx * nty * ntz;
+    const int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    bool want = false;
+    if (t < nt) {
+        if (pass == 1) {
+            want = true;
+        } else {
+            const int bx = (int)(t % ntx), by = (int)((t / ntx) % nty), bz = (int)(t / ((int64_t)ntx * nty));
+            for (int q = 0; q < 27 && !want; ++q) {
+                const int tz = bz + q / 9 - 1, ty = by + (q / 3) % 3 - 1, tx = bx + q % 3 - 1;
+                if (tz >= 0 && tz < ntz && ty >= 0 && ty < nty && tx >= 0 && tx < ntx)
+                    want = (s.stamps[(tz * nty + ty) * ntx + tx] >> 1) == pass - 1;
+            }
+        }
+    }
+    block_append(want, (int32_t)t, s.tlist, &s.hdr->lists[2 + par]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) s.hdr->lists[2 + (par ^ 1)] = 0;
 }
 
 __device__ inline bool is_frozen(const Graph &s, int j, int y, int x)
@@ -850,11 +950,8 @@ __device__ inline bool is_frozen(const Graph &s, int j, int y, int x)
 // mode 0: out-arc mask (distance to deficits); mode 1: in-arc mask
 // (reachability from excess).  Forced nodes of a thin-skin graph get no
 // arcs, so relaxation never gives them a finite value.
-template <class Src>
-__global__ void __launch_bounds__(kBlock)
-k_mask(Src src, int mode)
+__device__ inline void mask_blk(const Graph &s, int64_t lb, int mode)
 {
-    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
     int64_t n = lb * kBlock + threadIdx.x;
     if (n >= s.N) return;
     int j, y, x;
@@ -871,16 +968,19 @@ k_mask(Src src, int mode)
         mk |= (((ex_mask >> d) & 1u) && r > 0 ? 1u : 0u) << d;
     }
     s.mask[n] = (uint16_t)mk;
-    });
+}
+
+template <class Src>
+__global__ void __launch_bounds__(kBlock)
+k_mask(Src src, int mode)
+{
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { mask_blk(s, lb, mode); });
 }
 
 // Seeds: mode 0 -> ht = 1 at deficit nodes, INF elsewhere;
 //        mode 1 -> aux = 0 at excess nodes, INF elsewhere.
-template <class Src>
-__global__ void __launch_bounds__(kBlock)
-k_seed(Src src, int mode)
+__device__ inline void seed_blk(const Graph &s, int64_t lb, int mode)
 {
-    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
     int64_t n = lb * kBlock + threadIdx.x;
     if (n >= s.N) return;
     int32_t e = s.ex[n];
@@ -891,7 +991,13 @@ k_seed(Src src, int mode)
     }
     if (mode == 0) s.ht[n] = e < 0 ? 1 : kInf;
     else s.aux[n] = e > 0 ? 0 : kInf;
-    });
+}
+
+template <class Src>
+__global__ void __launch_bounds__(kBlock)
+k_seed(Src src, int mode)
+{
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { seed_blk(s, lb, mode); });
 }
 
 // One tiled min-plus relaxation pass: val(u) = min(val(u), val(w) + step)
@@ -910,9 +1016,8 @@ k_seed(Src src, int mode)
 // less arithmetic but measured 30 % slower: the rounds are bound by barrier
 // and LDS latency, not by the evaluations.)  flags[p % kMaxFlags] <- 1 if
 // any value changed; pass p returns at once when pass p-1 changed nothing.
-template <int TW, int TH, int TJ, class Src>
-__global__ void __launch_bounds__(kBlock)
-k_relax(Src src, int mode, int max_rounds, int pass)
+template <int TW, int TH, int TJ>
+__device__ inline void relax_blk(const Graph &s, int64_t lb, int mode, int max_rounds, int pass)
 {
     constexpr int HW = TW + 2, HH = TH + 2, HJ = TJ + 2;
     constexpr int NH = HW * HH * HJ, NI = TW * TH * TJ;
@@ -920,7 +1025,6 @@ k_relax(Src src, int mode, int max_rounds, int pass)
     constexpr int NPT = NI / kBlock;
     __shared__ int32_t sv[NH];
     __shared__ uint16_t smk[NI];
-    for_blocks(src, 1, [&](const Graph &s, int64_t lb) {
     // mode 0: BFS distance to the deficits in ht; mode 1: reachability in aux
     int32_t *__restrict__ val = mode == 0 ? s.ht : s.aux;
     const int step = mode == 0 ? 1 : 0;
@@ -1051,14 +1155,17 @@ k_relax(Src src, int mode, int max_rounds, int pass)
             stamps[tile] = 0;
         }
     }
-    });
 }
 
-template <class Src>
+template <int TW, int TH, int TJ, class Src>
 __global__ void __launch_bounds__(kBlock)
-k_count_active(Src src)
+k_relax(Src src, int mode, int max_rounds, int pass)
 {
-    for_blocks(src, 0, [&](const Graph &s, int64_t lb) {
+    for_blocks(src, 1, [&](const Graph &s, int64_t lb) { relax_blk<TW, TH, TJ>(s, lb, mode, max_rounds, pass); });
+}
+
+__device__ inline void count_blk(const Graph &s, int64_t lb)
+{
     int64_t n = lb * kBlock + threadIdx.x;
     int a = 0, hmax = 0;
     if (n < s.N) {
@@ -1078,7 +1185,13 @@ k_count_active(Src src)
         atomicAdd(&my_slot(s.slots, lb).active, a);
         atomicMax(&my_slot(s.slots, lb).max_height, hmax);
     }
-    });
+}
+
+template <class Src>
+__global__ void __launch_bounds__(kBlock)
+k_count_active(Src src)
+{
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { count_blk(s, lb); });
 }
 
 __global__ void k_zero_header(DevHeader *h, int what)
@@ -1087,10 +1200,13 @@ __global__ void k_zero_header(DevHeader *h, int what)
     if (what == 0) {                 // everything
         if (i < kMaxFlags) h->flags[i] = 0;
         if (i == 0) { h->active = 0; h->prefix_err = 0; h->pushes = 0; h->visits = 0; }
+        if (i < 4) h->lists[i] = 0;
     } else if (what == 1) {          // relaxation flags
         if (i < kMaxFlags) h->flags[i] = 0;
     } else if (what == 2) {          // active counter
         if (i == 0) h->active = 0;
+    } else if (what == 3) {          // work-list lengths
+        if (i < 4) h->lists[i] = 0;
     }
 }
 
@@ -1592,6 +1708,27 @@ inline bool sweep_fused(const Opts &o, int layers)
     return layers >= kFusedMinLayers;
 }
 
+// Work-list launches (sweeps over the listed blocks, relaxation passes over
+// the listed tiles, each on a fixed grid of kListGrid workgroups) on request.
+// One workgroup per block of the whole graph costs the dispatch of every
+// block even when few hold an active node (about 10 us per sweep at 450x375
+// with 64 depth numbers), but it lets a block that receives flow during a
+// sweep run in that same sweep, since it tests its flags when dispatched;
+// a list fixed before the sweep leaves it for the next one.  Measured on
+// single graphs the lists needed up to 30 % more sweeps and solved 4-25 %
+// slower (384x288x16, 450x375x64, 640x480x64), so they are off by default.
+constexpr unsigned kListGrid = 2048;
+
+inline bool use_lists(const Opts &o, int64_t)
+{
+    return (o.flags & GC_OPT_LISTS) != 0;
+}
+
+inline unsigned list_grid(int64_t items)
+{
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, kListGrid));
+}
+
 // Sweeps until the next global relabel.  The first period is the full
 // relabel period: its sweeps also saturate arcs, which keeps the following
 // BFS small (cutting it short was measured to cost more relaxation passes
@@ -1771,7 +1908,10 @@ int relax_to_fixpoint(const Graph &s, int mode, const Opts &o, Launcher &L, int 
 {
     const int64_t tiles = relax_tiles(s, o);
     RelaxFn<Graph> fn = relax_kernel<Graph>(o.tw, o.th, o.tj);
-    if (!fn) return GC_E_ARG;
+    RelaxFn<Listed> fnl = relax_kernel<Listed>(o.tw, o.th, o.tj);
+    if (!fn || !fnl) return GC_E_ARG;
+    const bool listed = use_lists(o, s.N);
+    if (listed) hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, L.st, s.hdr, 3);
     if (tiles <= 0 && !count_active) return GC_OK;
     const int max_passes = 1 << 22;
     const unsigned grid = grid_for(s.N);
@@ -1780,8 +1920,17 @@ int relax_to_fixpoint(const Graph &s, int mode, const Opts &o, Launcher &L, int 
     int batch = first_batch < 1 ? 1 : first_batch > kMaxFlags - 1 ? kMaxFlags - 1 : first_batch;
     for (;;) {
         hipLaunchKernelGGL(k_zero_flags, dim3(1), dim3(64), 0, L.st, s.hdr, passes + 1, batch);
-        for (int b = 1; b <= batch && tiles > 0; ++b)
-            L.run(GC_K_RELAX, fn, dim3((unsigned)tiles), s, mode, o.local_iters, passes + b);
+        for (int b = 1; b <= batch && tiles > 0; ++b) {
+            const int pass = passes + b;
+            if (listed) {
+                hipLaunchKernelGGL(k_list_tiles, dim3(grid_for(tiles)), dim3(kBlock), 0, L.st, s, pass,
+                                   pass & 1, o.tw, o.th, o.tj);
+                const Listed ls{s, s.tlist, &s.hdr->lists[2 + (pass & 1)]};
+                L.run(GC_K_RELAX, fnl, dim3(list_grid(tiles)), ls, mode, o.local_iters, pass);
+            } else {
+                L.run(GC_K_RELAX, fn, dim3((unsigned)tiles), s, mode, o.local_iters, pass);
+            }
+        }
         if (count_active) {
             hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, L.st, s.slots, 1);
             L.run(GC_K_OTHER, k_count_active<Graph>, dim3(grid), s);
@@ -1813,6 +1962,7 @@ struct SweepCapture {
     Graph key;
     int period = 0;
     bool fused = false;
+    bool listed = false;
     hipGraphExec_t exec = nullptr;
     unsigned long long used = 0;
     ~SweepCapture()
@@ -1822,27 +1972,44 @@ struct SweepCapture {
 };
 constexpr int kSweepCaptures = 8;
 
-void launch_period(const Graph &s, int period, bool fused, hipStream_t st)
+// One relabel period of sweeps.  listed: each sweep kernel runs over the
+// blocks a compaction launch lists just before it (the list lengths restart
+// at zero for the period, so a captured period replays correctly).
+void launch_period(const Graph &s, int period, bool fused, bool listed, Launcher &L)
 {
     const unsigned grid = grid_for(s.N);
+    const unsigned lgrid = list_grid(grid), cgrid = grid_for(grid);
+    int par = 0;
+    auto list = [&](int which) {
+        L.run(GC_K_OTHER, k_list_blocks, dim3(cgrid), s, par, which);
+        const Listed ls{s, s.blist, &s.hdr->lists[par]};
+        par ^= 1;
+        return ls;
+    };
+    if (listed) hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, L.st, s.hdr, 3);
     for (int i = 0; i < period; ++i) {
         if (fused) {
-            hipLaunchKernelGGL(k_sweep<Graph>, dim3(grid), dim3(kBlock), 0, st, s);
+            if (listed) L.run(GC_K_PUSH, k_sweep<Listed>, dim3(lgrid), list(0));
+            else L.run(GC_K_PUSH, k_sweep<Graph>, dim3(grid), s);
+        } else if (listed) {
+            L.run(GC_K_PUSH, k_push<Listed>, dim3(lgrid), list(1));
+            L.run(GC_K_RELABEL, k_relabel<Listed>, dim3(lgrid), list(0));
         } else {
-            hipLaunchKernelGGL(k_push<Graph>, dim3(grid), dim3(kBlock), 0, st, s);
-            hipLaunchKernelGGL(k_relabel<Graph>, dim3(grid), dim3(kBlock), 0, st, s);
+            L.run(GC_K_PUSH, k_push<Graph>, dim3(grid), s);
+            L.run(GC_K_RELABEL, k_relabel<Graph>, dim3(grid), s);
         }
     }
-    if (fused) hipLaunchKernelGGL(k_merge<Graph>, dim3(grid), dim3(kBlock), 0, st, s);
+    if (fused) L.run(GC_K_OTHER, k_merge<Graph>, dim3(grid), s);
 }
 
-int replay_period(const Graph &s, int period, bool fused, hipStream_t st)
+int replay_period(const Graph &s, int period, bool fused, bool listed, hipStream_t st)
 {
     thread_local SweepCapture cache[kSweepCaptures];
     thread_local unsigned long long tick = 0;
     SweepCapture *hit = nullptr, *victim = &cache[0];
     for (SweepCapture &c : cache) {
-        if (c.exec && c.period == period && c.fused == fused && !memcmp(&c.key, &s, sizeof(Graph))) {
+        if (c.exec && c.period == period && c.fused == fused && c.listed == listed &&
+            !memcmp(&c.key, &s, sizeof(Graph))) {
             hit = &c;
             break;
         }
@@ -1853,7 +2020,8 @@ int replay_period(const Graph &s, int period, bool fused, hipStream_t st)
         victim->exec = nullptr;
         hipGraph_t g = nullptr;
         if (!hip_ok(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal))) return GC_E_HIP;
-        launch_period(s, period, fused, st);
+        Launcher Lc{st, false, {}};
+        launch_period(s, period, fused, listed, Lc);
         if (!hip_ok(hipStreamEndCapture(st, &g))) return GC_E_HIP;
         const bool ok = hip_ok(hipGraphInstantiate(&victim->exec, g, nullptr, nullptr, 0));
         (void)hipGraphDestroy(g);
@@ -1861,6 +2029,7 @@ int replay_period(const Graph &s, int period, bool fused, hipStream_t st)
         victim->key = s;
         victim->period = period;
         victim->fused = fused;
+        victim->listed = listed;
         hit = victim;
     }
     hit->used = ++tick;
@@ -1920,7 +2089,7 @@ GC_API size_t gc_graph_footprint_bytes(const gc_problem *p)
     const size_t sites = (size_t)p->width * p->height;
     return align256(sizeof(DevHeader)) + align256(kSlots * sizeof(Slot)) + 11 * align256(n * 4) +
            align256(n * 2) + 2 * align256(sites * 4) + 2 * align256(flag_bytes((int64_t)n)) +
-           align256(max_tiles(p) * 4);
+           2 * align256(max_tiles(p) * 4) + align256((n + kBlock - 1) / kBlock * 4);
 }
 
 GC_API int stereo_cost_volume(const uint8_t *left, const uint8_t *right, const gc_problem *p,
@@ -2072,6 +2241,7 @@ static int solve_graph(gc_graph *g, const Opts &opt, gc_solve_stats *stats, hipS
     L.rb = rb;
     const unsigned grid = grid_for(s.N);
     const bool fused = sweep_fused(opt, s.J);
+    const bool listed = use_lists(opt, s.N);
     const bool use_graph = st != nullptr && (opt.flags & GC_OPT_SWEEP_GRAPH) != 0 && !L.timing;
     int status = GC_OK;
     int batch_hint = 4;
@@ -2099,21 +2269,11 @@ static int solve_graph(gc_graph *g, const Opts &opt, gc_solve_stats *stats, hipS
         const int period = period_for_round(opt, round, hr.max_height);
         if (st_local.sweeps >= opt.max_sweeps) { status = GC_E_NOT_CONVERGED; break; }
         if (use_graph) {
-            if ((rc = replay_period(s, period, fused, st)) != GC_OK) return rc;
-            st_local.sweeps += period;
+            if ((rc = replay_period(s, period, fused, listed, st)) != GC_OK) return rc;
         } else {
-            for (int i = 0; i < period; ++i) {
-                if (fused) {
-                    L.run(GC_K_PUSH, k_sweep<Graph>, dim3(grid), s);
-                } else {
-                    L.run(GC_K_PUSH, k_push<Graph>, dim3(grid), s);
-                    L.run(GC_K_RELABEL, k_relabel<Graph>, dim3(grid), s);
-                }
-                st_local.sweeps++;
-            }
-            if (fused)
-                L.run(GC_K_OTHER, k_merge<Graph>, dim3(grid), s);
+            launch_period(s, period, fused, listed, L);
         }
+        st_local.sweeps += period;
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
     }
     // the last read-back synchronised the stream

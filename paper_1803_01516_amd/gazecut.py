@@ -42,6 +42,7 @@ GC_OPT_FUSED_SWEEP = 16
 GC_OPT_SPLIT_SWEEP = 64
 GC_OPT_FIXED_PERIOD = 32
 GC_OPT_BATCH_MERGED = 128
+GC_OPT_LISTS = 256
 GC_BATCH_LANES = 4
 GC_BATCH_MAX_GRAPHS = 256
 GC_STATIC_SCRATCH_BYTES = 96 << 20

@@ -34,8 +34,9 @@ def test_problem_validation_and_footprint():
     n = 384 * 288 * 15
     fp = gc.footprint_bytes(ok)
     sites = 384 * 288
-    tiles = (384 // 8) * (288 // 4) * ((15 + 3) // 4)     # stamp per 8x4x4 relaxation tile
-    base = 46 * n + 8 * sites + 4 * tiles + 2 * (n // 256)
+    tiles = (384 // 8) * (288 // 4) * ((15 + 3) // 4)     # stamp and list entry per 8x4x4 tile
+    blocks = n // 256                                        # 4 activity bytes x 2, a list entry
+    base = 46 * n + 8 * sites + 8 * tiles + 12 * blocks
     assert base <= fp < base + 64 * 1024
     assert gc.problem_check(gc.problem(4, 4, 0, 30, 1, 1023)) == -2      # labels < 1
     assert gc.problem_check(gc.problem(-1, 4, 4, 30, 1, 1023)) == -2

@@ -205,7 +205,9 @@ def test_mid_parity_full_size(torch_cuda, orc, lam, inh_h, inh_v):
     _check_against_oracle(orc, cost_np, labels.cpu().numpy(), energy, flow, (lam, inh_h, lam, inh_v))
 
 
-def test_large_parity_full_size(torch_cuda, orc):
+@pytest.mark.parametrize("flags", [0, gc.GC_OPT_LISTS, gc.GC_OPT_LISTS | gc.GC_OPT_SPLIT_SWEEP],
+                         ids=["default", "lists", "lists-split"])
+def test_large_parity_full_size(torch_cuda, orc, flags):
     """450x375x64 against the stored oracle result (written by
     tests/golden/make_golden.py, which calls only the oracle)."""
     gold = np.load(os.path.join(GOLDEN, "large_450x375x64_seed3-0_lam1.npz"))
@@ -214,7 +216,7 @@ def test_large_parity_full_size(torch_cuda, orc):
     p = gc.problem(sg.LARGE.w, sg.LARGE.h, sg.LARGE.m, sg.LARGE.cap, 1, 1023)
     L = torch_cuda.from_numpy(pr.left).cuda()
     R = torch_cuda.from_numpy(pr.right).cuda()
-    labels, cost, energy, flow, st = gc.solve_pair(L, R, p)
+    labels, cost, energy, flow, st = gc.solve_pair(L, R, p, gc.GcSolveOpts(flags=flags))
     assert flow == int(gold["flow"]) and energy == int(gold["energy"])
     assert (labels.cpu().numpy() == gold["labels"].astype(np.int32)).all()
 
@@ -283,7 +285,10 @@ def test_repeat_solves_identical(torch_cuda, orc):
 _VARIANTS = {"wave-first": gc.GC_OPT_WAVE_FIRST, "fused": gc.GC_OPT_FUSED_SWEEP,
              "split": gc.GC_OPT_SPLIT_SWEEP, "graph": gc.GC_OPT_SWEEP_GRAPH,
              "fixed-period": gc.GC_OPT_FIXED_PERIOD,
-             "fused-wave-first": gc.GC_OPT_FUSED_SWEEP | gc.GC_OPT_WAVE_FIRST}
+             "fused-wave-first": gc.GC_OPT_FUSED_SWEEP | gc.GC_OPT_WAVE_FIRST,
+             "lists-split": gc.GC_OPT_LISTS | gc.GC_OPT_SPLIT_SWEEP,
+             "lists-fused": gc.GC_OPT_LISTS | gc.GC_OPT_FUSED_SWEEP,
+             "lists-graph": gc.GC_OPT_LISTS | gc.GC_OPT_SWEEP_GRAPH}
 
 
 def _variant_cases():
@@ -304,7 +309,7 @@ def _variant_cases():
 def test_solver_variants_parity(torch_cuda, orc, variant, name, cost, params):
     """The wave-front pass and the fused sweep change the schedule only: the
     canonical cut, energy and flow stay those of the oracle."""
-    stream = torch_cuda.cuda.Stream() if variant == "graph" else None   # capture needs a stream
+    stream = torch_cuda.cuda.Stream() if variant.endswith("graph") else None   # capture needs a stream
     for period in (1, 13, 64):
         o = gc.GcSolveOpts(relabel_period=period, flags=_VARIANTS[variant])
         lab, energy, flow, st = _solve_cost_gpu(torch_cuda, cost, *params, opts=o, stream=stream)
@@ -312,7 +317,7 @@ def test_solver_variants_parity(torch_cuda, orc, variant, name, cost, params):
         assert st.active_last == 0
 
 
-@pytest.mark.parametrize("variant", ["fused", "fused-wave-first"])
+@pytest.mark.parametrize("variant", ["fused", "fused-wave-first", "lists-split", "lists-fused"])
 def test_solver_variants_mid_full_size(torch_cuda, orc, variant):
     pr = sg.make_pair(sg.MID, (2, 1))
     p = gc.problem(sg.MID.w, sg.MID.h, sg.MID.m, sg.MID.cap, 1, 1023)
