@@ -47,9 +47,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=60, help="requests of the serving stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
-    ap.add_argument("--serve-low-rate", type=float, default=2.0,
+    ap.add_argument("--serve-low-rate", type=float, default=4.0,
                     help="second stream below the GPU's capacity (0: skip)")
-    ap.add_argument("--serve-low-requests", type=int, default=24)
+    ap.add_argument("--serve-low-requests", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 5 plain 256 MiB device copies (reference for HBM counters)")
     ap.add_argument("--sections", default="all",
@@ -173,15 +173,16 @@ def _pct(xs, q):
 
 def bench_batch(args, gc, sg, torch):
     """Uneven batch: pairs drawn uniformly from 320x240x16, 384x288x16,
-    450x375x64 and 640x480x64, solved one pair per launch, as one batched
-    solve (maxflow_solve_batch: concurrent lanes, largest first; options
-    autotuned) and in rounds of the merged engine.  Latency of a pair = its
-    completion time from the start of the run."""
+    450x375x64 and 640x480x64, solved three ways: one pair per launch, by the
+    batch engine (every member advancing on the device, each step's launches
+    shared by all members, relabel period and tile autotuned), and by four
+    concurrent lanes (host threads running single solves, options autotuned).
+    Latency of a pair = its completion time from the start of the run."""
     from paper_1803_01516_amd import runtime as rt
     stream = torch.cuda.Stream()
     mix = rt.batch_mix(args.batch_pairs, sg.BATCH_SHAPES, seed=4)
     with torch.cuda.stream(stream):
-        # autotune on one pair of every shape class
+        # autotune on one pair of every shape class, for each engine
         seen, tune = set(), []
         for i, (spec, pair) in enumerate(mix):
             key = (spec.w, spec.h, spec.m)
@@ -189,9 +190,12 @@ def bench_batch(args, gc, sg, torch):
                 seen.add(key)
                 tune.append(rt.make_item(i, spec, pair))
         t = time.perf_counter()
-        best, trials = rt.autotune(tune, stream=stream, use_graph=True)
+        best_lanes, trials_l = rt.autotune(tune, stream=stream, use_graph=True)
+        best_eng, trials_e = rt.autotune(tune, tiles=rt.TILE_CANDIDATES, periods=(16, 24, 32, 48),
+                                         sweeps=(0, gc.GC_OPT_SPLIT_SWEEP), stream=stream,
+                                         extra_flags=gc.GC_OPT_BATCH_MERGED)
         tune_s = time.perf_counter() - t
-        _log(f"batch: autotuned over {len(trials)} candidates in {tune_s:.1f} s")
+        _log(f"batch: autotuned over {len(trials_l) + len(trials_e)} candidates in {tune_s:.1f} s")
         for it in tune:
             rt.release(it)
 
@@ -207,13 +211,10 @@ def bench_batch(args, gc, sg, torch):
             return times, total, out
 
         t_one, tot_one, ref = run(rt.run_one_per_launch, None, "one pair per launch")
-        t_bat, tot_bat, got = run(rt.run_batched, best, "batched (lanes)")
-        merged_opts = gc.GcSolveOpts(relabel_period=best.relabel_period, tile_w=best.tile_w,
-                                     tile_h=best.tile_h, tile_j=best.tile_j,
-                                     flags=(best.flags & ~gc.GC_OPT_SWEEP_GRAPH) | gc.GC_OPT_BATCH_MERGED)
-        t_mrg, tot_mrg, got_m = run(rt.run_merged, merged_opts, "merged rounds")
+        t_eng, tot_eng, got_e = run(rt.run_merged, best_eng, "batch engine")
+        t_lan, tot_lan, got_l = run(rt.run_batched, best_lanes, "concurrent lanes")
         same = all(a[0] == b[0] == c[0] and a[1] == b[1] == c[1] and bool((a[2] == b[2]).all())
-                   and bool((a[2] == c[2]).all()) for a, b, c in zip(ref, got, got_m))
+                   and bool((a[2] == c[2]).all()) for a, b, c in zip(ref, got_e, got_l))
     n = len(mix)
     nodes = sum(s.w * s.h * (s.m - 1) for s, _ in mix)
 
@@ -221,19 +222,94 @@ def bench_batch(args, gc, sg, torch):
         return {"pairs_per_s": round(n / total, 2), "total_s": round(total, 3),
                 "p50_ms": _pct(times, 50), "p99_ms": _pct(times, 99)}
 
+    def opts_of(o):
+        return {"tile": [o.tile_w, o.tile_h, o.tile_j], "relabel_period": o.relabel_period,
+                "sweep": ("fused" if o.flags & gc.GC_OPT_FUSED_SWEEP else
+                          "split" if o.flags & gc.GC_OPT_SPLIT_SWEEP else "by depth")}
+
     return {"workload": f"{n} seeded pairs uniform over 320x240x16, 384x288x16, 450x375x64, "
                         "640x480x64 (6-10 slanted planes, sigma 3, cap 30, penalty 1, inhibit 1023)",
             "nodes_total": nodes,
-            "batched": dict(block(t_bat, tot_bat), mode=f"maxflow_solve_batch, {gc.GC_BATCH_LANES} concurrent lanes"),
-            "merged_rounds": block(t_mrg, tot_mrg),
+            "batched": dict(block(t_eng, tot_eng),
+                            mode="batch engine: members advance on the device, 32 captured steps "
+                                 "per host read-back, one work queue per unit kind",
+                            options=opts_of(best_eng)),
             "one_per_launch": block(t_one, tot_one),
-            "speedup": round(tot_one / tot_bat, 3),
-            "autotuned": {"tile": [best.tile_w, best.tile_h, best.tile_j],
-                          "relabel_period": best.relabel_period,
-                          "sweep": ("fused" if best.flags & gc.GC_OPT_FUSED_SWEEP else
-                                    "split" if best.flags & gc.GC_OPT_SPLIT_SWEEP else "by depth"),
-                          "tuning_s": round(tune_s, 2), "candidates": len(trials)},
+            "concurrent_lanes": dict(block(t_lan, tot_lan),
+                                     mode=f"{gc.GC_BATCH_LANES} host threads each running single solves",
+                                     options=opts_of(best_lanes)),
+            "speedup_vs_one_per_launch": round(tot_one / tot_eng, 3),
+            "speedup_vs_lanes": round(tot_lan / tot_eng, 3),
+            "autotune": {"tuning_s": round(tune_s, 2), "candidates": len(trials_l) + len(trials_e)},
             "identical_results": same}
+
+
+def bench_approx(gc, sg, torch, spec, pairs, lefts, rights, n_timed, stream, dev, lam):
+    """The exact cut, the exact cut warm-started from the level-1 skin
+    (b = 3), and the approximate cuts of Sec. 4.5 (level 1 b = 2, 3; level 2
+    b = 3 with max(32, labels) wave steps) on the same pairs, each timed from
+    the cost volume to the labels (median over n_timed pairs after a warm-up
+    pass), with its energy gap to the optimum and eq. (2) error."""
+    p = gc.problem(spec.w, spec.h, spec.m, spec.cap, lam, spec.inhibit)
+    ws, ws2 = gc.alloc_workspace(p, dev), gc.alloc_workspace(p, dev)
+    cost = torch.empty((spec.m, spec.h, spec.w), dtype=torch.int32, device=dev)
+    labels = torch.empty((spec.h, spec.w), dtype=torch.int32, device=dev)
+    result = torch.zeros(2, dtype=torch.int64, device=dev)
+
+    def exact(k):
+        g = gc.graph_build(p, cost, ws, stream)
+        gc.maxflow_solve(g, None, stream)
+        gc.extract_labels(g, cost, labels, result, stream)
+        return labels, int(result.cpu()[0])
+
+    def warm(k):
+        lab, e, _, _, _ = gc.solve_warm(p, cost, 3, None, stream, ws=ws, ws_skin=ws2)
+        return lab, e
+
+    def approx(level, b):
+        def run(k):
+            lab, e, _, _, _ = gc.approx_level1(p, cost, b, None, stream, ws=ws, level=level)
+            return lab, e
+        return run
+
+    out, best = {}, {}
+    for name, fn in (("exact", exact), ("warm_start_b3", warm), ("level1_b2", approx(1, 2)),
+                     ("level1_b3", approx(1, 3)), ("level2_b3", approx(2, 3))):
+        lat, gaps, errs, pcts = [], [], [], []
+        for i in range(n_timed + 1):
+            k = i % len(pairs)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            gc.stereo_cost_volume(lefts[k], rights[k], p, cost, stream)
+            lab, e = fn(k)
+            torch.cuda.synchronize()
+            if i == 0 and n_timed >= len(pairs):
+                continue                                   # warm-up pass
+            lat.append(time.perf_counter() - a)
+            if name == "exact":
+                best[k] = e
+            gaps.append(e - best[k])
+            er, pc = sg.eq2_error(pairs[k].gt, lab.cpu().numpy())
+            errs.append(er)
+            pcts.append(pc)
+        out[name] = {"ms_per_pair": round(1e3 * float(np.median(lat)), 3),
+                     "energy_gap_mean": round(float(np.mean(gaps)), 1),
+                     "energy_gap_rel": round(float(np.mean(gaps)) / float(np.mean(list(best.values()))), 6),
+                     "eq2_error_mean": round(float(np.mean(errs)), 1),
+                     "pct_exact_mean": round(float(np.mean(pcts)), 1)}
+        _log(f"approx {spec.w}x{spec.h}x{spec.m} {name}: {out[name]['ms_per_pair']} ms/pair, "
+             f"eq2 error {out[name]['eq2_error_mean']}")
+    for name in ("warm_start_b3", "level1_b2", "level1_b3", "level2_b3"):
+        out[name]["time_over_exact"] = round(out[name]["ms_per_pair"] / out["exact"]["ms_per_pair"], 3)
+    # Table 2 of the paper: eq. (2) error 21294 at level 2 b=3 against 20657
+    # at level 1 b=3 on its own pair (ratio 1.031)
+    out["level2_over_level1_b3_eq2"] = round(out["level2_b3"]["eq2_error_mean"] /
+                                             out["level1_b3"]["eq2_error_mean"], 4)
+    out["paper_table2_level2_over_level1_b3_eq2"] = round(21294 / 20657, 4)
+    out["workload"] = (f"{spec.w}x{spec.h}x{spec.m}, {len(pairs)} seeded pairs, penalty {lam}, "
+                       f"inhibit {spec.inhibit}")
+    del ws, ws2
+    return out
 
 
 def bench_larger(args, gc, torch, sg, lspec, seed0, stream, dev):
@@ -289,7 +365,7 @@ def bench_serving(args, gc, sg, torch, rate, n_req):
     pools = {s: [(sg.spec_like(sg.MID, *s), sg.make_pair(sg.spec_like(sg.MID, *s), (5, k, i)))
                  for i in range(2)] for k, s in enumerate(sg.SERVE_SHAPES)}
     reqs = rt.poisson_requests(n_req, rate, sg.SERVE_SHAPES, 2, seed=5)
-    opts = gc.GcSolveOpts(flags=gc.GC_OPT_SWEEP_GRAPH)
+    opts = gc.GcSolveOpts(relabel_period=32)
     _log(f"serving: {len(reqs)} requests at {rate:g}/s")
     done, wall, srv = rt.serve(reqs, pools, int(args.serve_budget_gb * 1e9), opts)
     _log(f"serving: done in {wall:.1f} s")
@@ -444,48 +520,17 @@ def main():
                         "pct_exact_mean": round(float(np.mean(pcts)), 1)}
             _log(f"rgb {key}: {rgb[key]['ms_per_pair']} ms/pair, eq2 error {rgb[key]['eq2_error_mean']}")
 
-    # the paper's approximate cuts (Sec. 4.5) on the same pairs, timed the same way
-    approx = {}
+    # the paper's approximate cuts (Sec. 4.5) and the warm-started exact cut,
+    # beside the exact cut, on the headline pairs and on 450x375x64 pairs
+    approx = approx_large = None
     if "approx" in args.sec:
-        best_e = {}
-        for variant, level, b in (("level1_b2", 1, 2), ("level1_b3", 1, 3), ("level2_b3", 2, 3)):
-            c = gc.coarse_problem(p, b)
-            ws_c = gc.alloc_workspace(c, dev)
-            lat_a, gaps, errs, pcts = [], [], [], []
-            n_a = max(4, args.steps // 4)
-            for i in range(n_a + 2):
-                k = i % len(pairs)
-                torch.cuda.synchronize()
-                a = time.perf_counter()
-                gc.stereo_cost_volume(lefts[k], rights[k], p, cost, stream)
-                lab_a, e_a, _, _, _ = gc.approx_level1(p, cost, b, None, stream, ws=ws, ws_coarse=ws_c,
-                                                       level=level)
-                torch.cuda.synchronize()
-                if i >= 2:
-                    lat_a.append(time.perf_counter() - a)
-                    if k not in best_e:
-                        gc.stereo_cost_volume(lefts[k], rights[k], p, cost, stream)
-                        g = gc.graph_build(p, cost, ws, stream)
-                        gc.maxflow_solve(g, None, stream)
-                        gc.extract_labels(g, cost, labels, result, stream)
-                        best_e[k] = int(result.cpu()[0])
-                    gaps.append(e_a - best_e[k])
-                    er, pc = sg.eq2_error(pairs[k].gt, lab_a.cpu().numpy())
-                    errs.append(er)
-                    pcts.append(pc)
-            _log(f"approx {variant}: {1e3 * float(np.median(lat_a)):.3f} ms/pair")
-            approx[variant] = {"ms_per_pair": round(1e3 * float(np.median(lat_a)), 3),
-                               "energy_gap_mean": round(float(np.mean(gaps)), 1),
-                               "energy_gap_rel": round(float(np.mean(gaps)) / float(np.mean(
-                                   [best_e[k] for k in best_e])), 6),
-                               "eq2_error_mean": round(float(np.mean(errs)), 1),
-                               "pct_exact_mean": round(float(np.mean(pcts)), 1)}
-        if "level2_b3" in approx and "level1_b3" in approx:
-            # Table 2 of the paper: eq. (2) error 21294 at level 2 b=3 against
-            # 20657 at level 1 b=3 on its own pair (ratio 1.031)
-            approx["level2_over_level1_b3_eq2"] = round(
-                approx["level2_b3"]["eq2_error_mean"] / approx["level1_b3"]["eq2_error_mean"], 4)
-            approx["paper_table2_level2_over_level1_b3_eq2"] = round(21294 / 20657, 4)
+        approx = bench_approx(gc, sg, torch, spec, pairs, lefts, rights, max(4, args.steps // 4),
+                              stream, dev, args.lam)
+        lspec = sg.LARGE
+        lp = [sg.make_pair(lspec, (3, i)) for i in range(2)]
+        approx_large = bench_approx(gc, sg, torch, lspec, lp, [torch.from_numpy(q.left).to(dev) for q in lp],
+                                    [torch.from_numpy(q.right).to(dev) for q in lp], 2, stream, dev, 1)
+        torch.cuda.empty_cache()
 
     # the larger configurations, whose state does not fit the Infinity Cache:
     # 450x375 pairs with 64 depth numbers (12 slanted planes, 10 % textureless)
@@ -582,7 +627,8 @@ def main():
         "bfs_passes_per_pair": round(sum(s["bfs_passes"] for s in stats) / args.steps, 2),
         "energy_last": int(r[0]), "flow_last": int(r[1]),
         "eq2_error_last": err, "pct_exact_last": pct,
-        "approx": approx or None,
+        "approx": approx,
+        "approx_450x375x64": approx_large,
         "pairwise_variants": variants or None,
         "larger_pair": larger.get("450x375x64"),
         "larger_640x480x64": larger.get("640x480x64"),

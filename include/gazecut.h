@@ -353,7 +353,9 @@ int graph_warm_start(gc_graph *g, const gc_graph *skin, const int32_t *cost, voi
  * cost:          DEVICE int32 [labels][height][width], the full data term.
  * coarse_labels: DEVICE int32 [ceil(h/b)][ceil(w/b)], the delegate labels
  *                the skin was built from.
- * wave_steps:    A-1 >= 0 (64 recommended; see the benchmark record).
+ * wave_steps:    A-1 >= 0; max(32, labels) recommended (fewer steps can leave
+ *                regions whose flow has not reached the cut at the top of
+ *                their windows).
  * labels:        DEVICE int32 [height][width], written.
  * result:        DEVICE int64[2], written: result[0] = E(labels) from its
  *                definition, result[1] = -1 (no global cut value exists).
@@ -366,12 +368,16 @@ int approx_level2_cut(gc_graph *skin, const int32_t *cost, const int32_t *coarse
 
 /* ------------------------------------------------------------------------
  * Batched solve.  Many graphs of any sizes (full or thin-skin) are solved
- * together: every kernel launch of a phase covers all member graphs, its
- * blocks finding their graph in a device table.  A round runs, for every
- * member, exactly the single-graph sequence: exact global relabel, then the
- * termination test (finished members leave the batch), then
- * `relabel_period` push-relabel sweeps.  Results are identical to
- * maxflow_solve on each graph (the cut is canonical).  Graphs may join
+ * together, each advancing through the single-graph sequence (exact global
+ * relabel by relaxation passes, termination test, a period of push-relabel
+ * sweeps) on the device.  A step moves every member by one phase of that
+ * sequence in four launches shared by all members: one workgroup per member
+ * picks its next phase from what its last step left, the members' work lists
+ * are compacted (active blocks of a sweep, changed tiles of a relaxation
+ * pass), their offsets are summed, and a fixed grid of workgroups takes the
+ * units of all members in turn (the work queue).  A round replays a captured
+ * run of steps and reads the members' records once.  Results are identical
+ * to maxflow_solve on each graph (the cut is canonical).  Graphs may join
  * between rounds, which is how a serving loop admits new work while others
  * are on the GPU.
  * ---------------------------------------------------------------------- */
@@ -383,8 +389,9 @@ typedef struct gc_batch gc_batch;
 size_t gc_batch_footprint_bytes(void);
 
 /* Creates a batch over the caller's DEVICE table buffer; `o` fixes the
- * relabel period, relaxation tile and GC_OPT_SWEEP_GRAPH for all members.
- * Errors: GC_E_ARG, GC_E_WORKSPACE. */
+ * relabel period, relaxation tile (8x8x16, 16x8x16, 8x8x32 or 16x16x8),
+ * sweep kind and max_sweeps for all members; GC_OPT_WAVE_FIRST is not used.
+ * Errors: GC_E_ARG (also for another tile shape), GC_E_WORKSPACE. */
 int gc_batch_create(void *dev_table, size_t dev_bytes, const gc_solve_opts *o, gc_batch **out);
 
 /* Frees the host object (not the caller's memory). */
@@ -398,12 +405,14 @@ int gc_batch_members(const gc_batch *b);
  * Errors: GC_E_ARG (batch full), errors of an invalid graph. */
 int gc_batch_add(gc_batch *b, const gc_graph *g, int64_t tag);
 
-/* One round for every member on `stream`.  Members that finished leave the
- * batch; their tags (and stats, if done_stats is not NULL) are written to
- * done_tags[0 .. *n_done-1] (at most max_done of them; others stay for the
- * next round).  A member leaves unfinished after max_sweeps sweeps, with
- * stats.active_last > 0.  Blocks the host for the relabel read-backs; the
- * sweeps are left running on the stream.  Errors: GC_E_ARG, GC_E_HIP. */
+/* One round on `stream`: 32 steps of every member (captured once per
+ * membership and replayed when `stream` is not null), then one read-back of
+ * the members' records.  Members that finished leave the batch; their tags
+ * (and stats, if done_stats is not NULL) are written to done_tags[0 ..
+ * *n_done-1] (at most max_done of them; others are reported by the next
+ * call).  A member stops unfinished after max_sweeps sweeps, with
+ * stats.active_last > 0.  Returns with the stream synchronised.
+ * Errors: GC_E_ARG, GC_E_HIP. */
 int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solve_stats *done_stats,
                    int32_t max_done, int32_t *n_done);
 
@@ -411,8 +420,9 @@ int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solve_stats
 #define GC_BATCH_LANES 4
 
 /* gc_solve_opts.flags, maxflow_solve_batch: run the graphs in rounds of the
- * merged batch engine (gc_batch_*, one launch per phase over all members, on
- * `stream`, using dev_table) instead of concurrent lanes. */
+ * batch engine (gc_batch_*: every member advances on the device, each step's
+ * launches shared by all members; on `stream`, using dev_table) instead of
+ * concurrent lanes. */
 #define GC_OPT_BATCH_MERGED 128
 
 /* Solves n built graphs and returns when all are solved; extract_labels then

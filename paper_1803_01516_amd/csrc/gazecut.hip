@@ -46,6 +46,7 @@
 #include <new>
 #include <numeric>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "gazecut.h"
@@ -114,16 +115,28 @@ struct Slot {
 static_assert(sizeof(Slot) == 64, "one slot per cache line");
 constexpr int kSlots = 256;
 
+// Device memory of a graph.  The pointers carry the global address space, so
+// kernels that read a graph from a table (the batch engine) access its arrays
+// with global instructions, as kernels whose graph is an argument do; a
+// pointer of unknown space compiles to flat instructions, whose waits also
+// wait for scalar loads.
+// (The host pass sees plain pointers of the same size and value.)
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GDEV __attribute__((address_space(1)))
+#else
+#define GDEV
+#endif
+
 struct Graph {
-    int32_t *ex, *ht, *rd, *re, *rs, *rem, *rep, *rsm, *rsp, *ein, *aux;
-    uint16_t *mask;
-    int32_t *stamps;          // per relaxation tile: last pass that changed it
-    int32_t *blist, *tlist;   // work lists: 256-node blocks of a sweep, tiles of a relaxation pass
-    int32_t *wlo, *whi;       // per-site label window of a thin-skin graph
-    uint8_t *bact;            // per 64-node group: holds an active node
-    uint8_t *binf;            // per 64-node group: received inflow in the last push sweep
-    DevHeader *hdr;
-    Slot *slots;
+    GDEV int32_t *ex, *ht, *rd, *re, *rs, *rem, *rep, *rsm, *rsp, *ein, *aux;
+    GDEV uint16_t *mask;
+    GDEV int32_t *stamps;     // per relaxation tile: last pass that changed it
+    GDEV int32_t *blist, *tlist;   // work lists: 256-node blocks of a sweep, tiles of a relaxation pass
+    GDEV int32_t *wlo, *whi;  // per-site label window of a thin-skin graph
+    GDEV uint8_t *bact;       // per 64-node group: holds an active node
+    GDEV uint8_t *binf;       // per 64-node group: received inflow in the last push sweep
+    GDEV DevHeader *hdr;
+    GDEV Slot *slots;
     int32_t W, H, J;
     int64_t plane, N;
     int32_t te, ts, ie, is;   // pair totals: 2*pen_h, 2*pen_v, inh_h, inh_v
@@ -170,19 +183,19 @@ Graph view(const gc_graph *g)
     s.plane = (int64_t)s.W * s.H;
     s.N = s.plane * s.J;
     char *b = (char *)g->ws;
-    s.hdr = (DevHeader *)b; b += align256(sizeof(DevHeader));
-    s.slots = (Slot *)b; b += align256(kSlots * sizeof(Slot));
+    s.hdr = (GDEV DevHeader *)b; b += align256(sizeof(DevHeader));
+    s.slots = (GDEV Slot *)b; b += align256(kSlots * sizeof(Slot));
     size_t w4 = align256((size_t)s.N * 4);
-    int32_t **arr[] = {&s.ex, &s.ht, &s.rd, &s.re, &s.rs, &s.rem, &s.rep, &s.rsm, &s.rsp, &s.ein, &s.aux};
-    for (int32_t **a : arr) { *a = (int32_t *)b; b += w4; }
-    s.mask = (uint16_t *)b; b += align256((size_t)s.N * 2);
-    s.wlo = (int32_t *)b; b += align256((size_t)s.plane * 4);
-    s.whi = (int32_t *)b; b += align256((size_t)s.plane * 4);
-    s.bact = (uint8_t *)b; b += align256(flag_bytes(s.N));
-    s.binf = (uint8_t *)b; b += align256(flag_bytes(s.N));
-    s.stamps = (int32_t *)b; b += align256(max_tiles(&p) * 4);
-    s.blist = (int32_t *)b; b += align256((size_t)((s.N + kBlock - 1) / kBlock) * 4);
-    s.tlist = (int32_t *)b;
+    GDEV int32_t **arr[] = {&s.ex, &s.ht, &s.rd, &s.re, &s.rs, &s.rem, &s.rep, &s.rsm, &s.rsp, &s.ein, &s.aux};
+    for (GDEV int32_t **a : arr) { *a = (GDEV int32_t *)b; b += w4; }
+    s.mask = (GDEV uint16_t *)b; b += align256((size_t)s.N * 2);
+    s.wlo = (GDEV int32_t *)b; b += align256((size_t)s.plane * 4);
+    s.whi = (GDEV int32_t *)b; b += align256((size_t)s.plane * 4);
+    s.bact = (GDEV uint8_t *)b; b += align256(flag_bytes(s.N));
+    s.binf = (GDEV uint8_t *)b; b += align256(flag_bytes(s.N));
+    s.stamps = (GDEV int32_t *)b; b += align256(max_tiles(&p) * 4);
+    s.blist = (GDEV int32_t *)b; b += align256((size_t)((s.N + kBlock - 1) / kBlock) * 4);
+    s.tlist = (GDEV int32_t *)b;
     s.te = 2 * p.penalty_h; s.ts = 2 * p.penalty_v;
     s.ie = p.inhibit_h; s.is = p.inhibit_v;
     s.win = g->window_block > 0 ? 1 : 0;
@@ -254,9 +267,8 @@ __device__ inline int block_max(int v)
     return t;
 }
 
-// Kernel sources.  A solver kernel runs either on one graph (passed by value,
-// one block per 256 nodes or per tile) or on a batch: a device table of
-// graphs with prefix offsets of their blocks.
+// Kernel sources.  A solver kernel runs on one graph passed by value, one
+// workgroup per 256 nodes or per tile, or over a device list of them.
 constexpr int kMaxBatch = GC_BATCH_MAX_GRAPHS;
 constexpr unsigned kGridX = 65535;      // x extent of a batch launch's 2-D grid
 
@@ -267,50 +279,59 @@ inline dim3 batch_grid(int64_t blocks)
     if (blocks <= kGridX) return dim3((unsigned)blocks, 1, 1);
     return dim3(kGridX, (unsigned)((blocks + kGridX - 1) / kGridX), 1);
 }
-struct BatchDev {
-    int32_t ng;
-    int32_t pad[63];
-    int32_t node_off[kMaxBatch + 1];    // node blocks (256 nodes each)
-    int32_t tile_off[kMaxBatch + 1];    // relaxation tiles
-    int32_t pad2[2];
-    Graph graphs[kMaxBatch];
-    int32_t gathered[kMaxBatch][16];    // per-graph flags / counters read back by the host
-};
-// A launch over the members g0 .. g1-1 of a batch table.
-struct Batch {
-    const BatchDev *T;
-    int g0, g1;
+// Phases of a member of a batch: the step a member takes next.
+enum BatchPhase : int32_t {
+    BP_INIT = 0, BP_SEED, BP_RELAX, BP_COUNT, BP_PUSH, BP_RELABEL, BP_SWEEP, BP_MERGE, BP_DONE
 };
 
-// Runs f(graph, local block) for the block of a launch.  One graph: the
-// grid covers its blocks exactly.  A batch: the 2-D grid (x fastest) covers
-// the total of the launch's member graphs' blocks; a block finds its graph by
-// binary search over the prefix offsets and blocks past the total exit.
+// Kinds of work unit, each run by its own launch so that each kernel keeps
+// the register count of its own code: every block of the member (seeds,
+// count, merge), a listed relaxation tile, a listed block of a sweep.
+enum BatchKind : int32_t { BK_FULL = 0, BK_RELAX = 1, BK_SWEEP = 2 };
+
+__host__ __device__ inline int batch_kind(int phase)
+{
+    return phase == BP_RELAX ? BK_RELAX
+         : (phase == BP_PUSH || phase == BP_RELABEL || phase == BP_SWEEP) ? BK_SWEEP : BK_FULL;
+}
+
+// Device record of one member's progress through its solve.
+struct MemberCtl {
+    int32_t phase;            // phase of the current step
+    int32_t pass;             // relaxation pass of the current global relabel, from 1
+    int32_t sweep;            // sweeps done in the current period
+    int32_t period;           // length of the current period
+    int32_t round;            // global relabels begun
+    int32_t status;           // GC_OK, or GC_E_NOT_CONVERGED when stopped at max_sweeps
+    int32_t units;            // work units of the current step
+    int32_t fused;            // fused sweeps (else push + relabel)
+    int32_t blocks, tiles;    // 256-node blocks, relaxation tiles
+    int32_t active, max_height;
+    int32_t sweeps, passes, relabels;
+    int32_t done_step;        // step in which it finished
+    long long pushes, visits;
+};
+
+// Device table of a batch.
+struct BatchDev {
+    int32_t ng;               // members in the table
+    int32_t total[3];         // work units of the current step, per kind (BatchKind)
+    int32_t live;             // members not finished
+    int32_t step;             // steps run
+    int32_t period, max_sweeps, local_iters, flags;
+    int32_t pad[6];
+    int32_t unit_off[3][kMaxBatch + 1];   // per kind, prefix of the members' units
+    int32_t list_off[kMaxBatch + 1];   // prefix of the members' compaction workgroups
+    MemberCtl ctl[kMaxBatch];
+    Graph graphs[kMaxBatch];
+};
+
+// Runs f(graph, local block) for the block of a launch: one graph, the grid
+// covering its blocks (or tiles) exactly.
 template <class F>
 __device__ inline void for_blocks(const Graph &s, int, F &&f)
 {
     f(s, (int64_t)blockIdx.x);
-}
-
-template <class F>
-__device__ inline void for_blocks(const Batch &b, int which, F &&f)
-{
-    const BatchDev *T = b.T;
-    const int32_t *off = which ? T->tile_off : T->node_off;
-    if (b.g1 <= b.g0) return;
-    const int64_t vb = off[b.g0] + (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
-    if (vb >= off[b.g1]) return;
-    int lo = b.g0, hi = b.g1 - 1;                // largest g with off[g] <= vb
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= vb) lo = mid;
-        else hi = mid - 1;
-    }
-    // a private copy: through a reference into the table every field would be
-    // reloaded after each store the kernel makes (the compiler cannot rule
-    // out that the store aliases the table)
-    const Graph g = T->graphs[lo];
-    f(g, vb - off[lo]);
 }
 
 // A list-driven launch over one graph: the workgroups of a fixed grid take
@@ -327,7 +348,9 @@ template <class F>
 __device__ inline void for_blocks(const Listed &L, int, F &&f)
 {
     const int n = *L.count;
-    for (int i = blockIdx.x; i < n; i += gridDim.x) f(L.s, (int64_t)L.ids[i]);
+    // the id is the same in every lane: read it into a scalar register, so
+    // that the block's index arithmetic and loads stay scalar
+    for (int i = blockIdx.x; i < n; i += gridDim.x) f(L.s, (int64_t)__builtin_amdgcn_readfirstlane(L.ids[i]));
 }
 
 // Workgroup-wide compaction: every thread with `want` gets a distinct slot
@@ -1016,7 +1039,7 @@ k_seed(Src src, int mode)
 // less arithmetic but measured 30 % slower: the rounds are bound by barrier
 // and LDS latency, not by the evaluations.)  flags[p % kMaxFlags] <- 1 if
 // any value changed; pass p returns at once when pass p-1 changed nothing.
-template <int TW, int TH, int TJ>
+template <int TW, int TH, int TJ, bool kLooped = false>
 __device__ inline void relax_blk(const Graph &s, int64_t lb, int mode, int max_rounds, int pass)
 {
     constexpr int HW = TW + 2, HH = TH + 2, HJ = TJ + 2;
@@ -1031,7 +1054,12 @@ __device__ inline void relax_blk(const Graph &s, int64_t lb, int mode, int max_r
     int32_t *flags = s.hdr->flags;
     int32_t *__restrict__ stamps = s.stamps;
     const int ntx = (s.W + TW - 1) / TW, nty = (s.H + TH - 1) / TH, ntz = (s.J + TJ - 1) / TJ;
-    const int tid = threadIdx.x;
+    // In a loop over many tiles (kLooped) the thread index goes through an
+    // empty asm statement: otherwise every per-thread offset of the tile is
+    // hoisted out of the loop and stays live across it (87 registers instead
+    // of 45 for an 8x8x16 tile).
+    int tid = threadIdx.x;
+    if (kLooped) asm volatile("" : "+v"(tid));
     if (pass > 1 && flags[(pass - 1) % kMaxFlags] == 0) return;     // converged already
     const int tile = (int)lb;
     const int bx = tile % ntx, by = (tile / ntx) % nty, bz = tile / (ntx * nty);
@@ -1161,7 +1189,10 @@ template <int TW, int TH, int TJ, class Src>
 __global__ void __launch_bounds__(kBlock)
 k_relax(Src src, int mode, int max_rounds, int pass)
 {
-    for_blocks(src, 1, [&](const Graph &s, int64_t lb) { relax_blk<TW, TH, TJ>(s, lb, mode, max_rounds, pass); });
+    constexpr bool kLooped = std::is_same<Src, Listed>::value;
+    for_blocks(src, 1, [&](const Graph &s, int64_t lb) {
+        relax_blk<TW, TH, TJ, kLooped>(s, lb, mode, max_rounds, pass);
+    });
 }
 
 __device__ inline void count_blk(const Graph &s, int64_t lb)
@@ -1335,50 +1366,6 @@ k_fold_slots(const Slot *slots, DevHeader *hdr, int what, int64_t *result)
     } else {
         long long e0 = block_sum(sl.e0);
         if (threadIdx.x == 0) hdr->seeded = e0;
-    }
-}
-
-// Per-graph bookkeeping of a batch, one block per member graph.
-// what 0: clear change flags of passes first .. first+count-1;
-// what 1: clear the active counters.
-__global__ void __launch_bounds__(kSlots)
-k_batch_zero(const BatchDev *T, int what, int first, int count)
-{
-    const Graph &s = T->graphs[blockIdx.x];
-    const int t = threadIdx.x;
-    if (what == 0) {
-        if (t < count) s.hdr->flags[(first + t) % kMaxFlags] = 0;
-    } else {
-        s.slots[t].active = 0;
-        s.slots[t].max_height = 0;
-    }
-}
-
-// what 0: copy the change flags; what 1: fold active nodes and pushes.
-__global__ void __launch_bounds__(kSlots)
-k_batch_gather(BatchDev *T, int what)
-{
-    const int g = blockIdx.x;
-    const Graph &s = T->graphs[g];
-    const int t = threadIdx.x;
-    if (what == 0) {
-        if (t < kMaxFlags) T->gathered[g][t] = s.hdr->flags[t];
-        return;
-    }
-    const int a = block_sum(s.slots[t].active);
-    __syncthreads();
-    const unsigned long long pu = block_sum(s.slots[t].pushes);
-    __syncthreads();
-    const unsigned long long vi = block_sum(s.slots[t].visits);
-    if (t == 0) {
-        s.hdr->active = a;
-        s.hdr->pushes = pu;
-        s.hdr->visits = vi;
-        T->gathered[g][0] = a;
-        T->gathered[g][1] = (int32_t)(pu & 0x7fffffffULL);
-        T->gathered[g][2] = (int32_t)(pu >> 31);
-        T->gathered[g][3] = (int32_t)(vi & 0x7fffffffULL);
-        T->gathered[g][4] = (int32_t)(vi >> 31);
     }
 }
 
@@ -1719,14 +1706,42 @@ inline bool sweep_fused(const Opts &o, int layers)
 // slower (384x288x16, 450x375x64, 640x480x64), so they are off by default.
 constexpr unsigned kListGrid = 2048;
 
+// Workgroups of `kernel` (kBlock threads) that the GPU holds at once.  A
+// persistent grid larger than this leaves the surplus waiting until a
+// resident workgroup has finished its whole share, which doubles the time
+// of an evenly split launch.
+// Looked up once per (kernel, device) and kept.
+template <class K>
+unsigned resident_grid(K kernel)
+{
+    struct Entry { const void *k; int dev; unsigned grid; };
+    static std::mutex mu;
+    static Entry cache[64];
+    static int used = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return kListGrid;
+    const void *key = reinterpret_cast<const void *>(kernel);
+    std::lock_guard<std::mutex> lock(mu);
+    for (int i = 0; i < used; ++i)
+        if (cache[i].k == key && cache[i].dev == dev) return cache[i].grid;
+    int cus = 0, per_cu = 0;
+    unsigned grid = kListGrid;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) == hipSuccess &&
+        cus > 0 && per_cu > 0)
+        grid = (unsigned)(cus * per_cu);
+    if (used < 64) cache[used++] = Entry{key, dev, grid};
+    return grid;
+}
+
 inline bool use_lists(const Opts &o, int64_t)
 {
     return (o.flags & GC_OPT_LISTS) != 0;
 }
 
-inline unsigned list_grid(int64_t items)
+inline unsigned list_grid(int64_t items, unsigned resident)
 {
-    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, kListGrid));
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, resident));
 }
 
 // Sweeps until the next global relabel.  The first period is the full
@@ -1926,7 +1941,8 @@ int relax_to_fixpoint(const Graph &s, int mode, const Opts &o, Launcher &L, int 
                 hipLaunchKernelGGL(k_list_tiles, dim3(grid_for(tiles)), dim3(kBlock), 0, L.st, s, pass,
                                    pass & 1, o.tw, o.th, o.tj);
                 const Listed ls{s, s.tlist, &s.hdr->lists[2 + (pass & 1)]};
-                L.run(GC_K_RELAX, fnl, dim3(list_grid(tiles)), ls, mode, o.local_iters, pass);
+                L.run(GC_K_RELAX, fnl, dim3(list_grid(tiles, resident_grid(fnl))), ls, mode, o.local_iters,
+                      pass);
             } else {
                 L.run(GC_K_RELAX, fn, dim3((unsigned)tiles), s, mode, o.local_iters, pass);
             }
@@ -1978,7 +1994,7 @@ constexpr int kSweepCaptures = 8;
 void launch_period(const Graph &s, int period, bool fused, bool listed, Launcher &L)
 {
     const unsigned grid = grid_for(s.N);
-    const unsigned lgrid = list_grid(grid), cgrid = grid_for(grid);
+    const unsigned cgrid = grid_for(grid);
     int par = 0;
     auto list = [&](int which) {
         L.run(GC_K_OTHER, k_list_blocks, dim3(cgrid), s, par, which);
@@ -1989,11 +2005,13 @@ void launch_period(const Graph &s, int period, bool fused, bool listed, Launcher
     if (listed) hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, L.st, s.hdr, 3);
     for (int i = 0; i < period; ++i) {
         if (fused) {
-            if (listed) L.run(GC_K_PUSH, k_sweep<Listed>, dim3(lgrid), list(0));
+            if (listed)
+                L.run(GC_K_PUSH, k_sweep<Listed>, dim3(list_grid(grid, resident_grid(k_sweep<Listed>))), list(0));
             else L.run(GC_K_PUSH, k_sweep<Graph>, dim3(grid), s);
         } else if (listed) {
-            L.run(GC_K_PUSH, k_push<Listed>, dim3(lgrid), list(1));
-            L.run(GC_K_RELABEL, k_relabel<Listed>, dim3(lgrid), list(0));
+            L.run(GC_K_PUSH, k_push<Listed>, dim3(list_grid(grid, resident_grid(k_push<Listed>))), list(1));
+            L.run(GC_K_RELABEL, k_relabel<Listed>, dim3(list_grid(grid, resident_grid(k_relabel<Listed>))),
+                  list(0));
         } else {
             L.run(GC_K_PUSH, k_push<Graph>, dim3(grid), s);
             L.run(GC_K_RELABEL, k_relabel<Graph>, dim3(grid), s);
@@ -2435,110 +2453,385 @@ GC_API int approx_level2_cut(gc_graph *skin, const int32_t *cost, const int32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Batched solve: one launch per phase covers every member graph.
+// Batched solve: every member advances on the device.
+//
+// A batch is a device table of member graphs, each with a MemberCtl record
+// of where its solve stands.  One step moves every member by one phase of
+// the single-graph solve (the mask and seeds of a global relabel, one
+// relaxation pass, the termination count, one push / relabel / fused sweep,
+// the inflow merge), all members in the same launches:
+//   k_batch_phase   one workgroup per member: reads what its last step left
+//                   (a relaxation pass's change flag, the folded count) and
+//                   picks the member's next phase, as maxflow_solve's host
+//                   loop does;
+//   k_batch_list    per member, the work list of the step (active blocks of
+//                   a sweep, changed tiles of a relaxation pass);
+//   k_batch_scan    prefix offsets of the members' work units;
+//   k_batch_full, k_batch_relax, k_batch_sweeps
+//                   each a fixed grid of workgroups that takes the units of
+//                   one kind (every block; listed tiles; listed blocks) of all
+//                   members in turn (the tile work queue) and runs the same
+//                   device functions as the single-graph kernels.
+// The host replays a captured sequence of steps and reads the members'
+// records once per replay; nothing in a step waits for the host.
 // ---------------------------------------------------------------------------
+
+namespace {
+
+__device__ inline int batch_period(const BatchDev *T, int round, int max_height)
+{
+    if (round == 0 || (T->flags & GC_OPT_FIXED_PERIOD)) return T->period;
+    const int q = 2 * max_height;
+    const int lo = T->period < kMinPeriod ? T->period : kMinPeriod;
+    return q < lo ? lo : q > T->period ? T->period : q;
+}
+
+__global__ void __launch_bounds__(kSlots)
+k_batch_phase(BatchDev *T)
+{
+    const int g = blockIdx.x;
+    MemberCtl &c = T->ctl[g];
+    const Graph s = T->graphs[g];
+    const int t = threadIdx.x;
+    __shared__ int next;
+    const int last = c.phase;
+    __syncthreads();                         // every wave has read it before it changes
+    if (last == BP_COUNT) {                  // fold the termination count
+        const Slot &sl = s.slots[t];
+        const int a = block_sum(sl.active);
+        const int mh = block_max(sl.max_height);
+        __syncthreads();
+        const unsigned long long pu = block_sum(sl.pushes);
+        __syncthreads();
+        const unsigned long long vi = block_sum(sl.visits);
+        if (t == 0) {
+            c.active = a;
+            c.max_height = mh;
+            c.pushes = (long long)pu;
+            c.visits = (long long)vi;
+            c.relabels++;
+        }
+    }
+    if (t == 0) {
+        int nx = BP_DONE;
+        switch (last) {
+        case BP_INIT:
+            nx = BP_SEED;
+            break;
+        case BP_SEED:
+            nx = BP_RELAX;
+            c.pass = 1;
+            s.hdr->flags[1 % kMaxFlags] = 0;
+            break;
+        case BP_RELAX:
+            c.passes++;
+            if (s.hdr->flags[c.pass % kMaxFlags]) {
+                nx = BP_RELAX;
+                c.pass++;
+                s.hdr->flags[c.pass % kMaxFlags] = 0;
+            } else {
+                nx = BP_COUNT;
+            }
+            break;
+        case BP_COUNT:
+            if (c.active == 0 || c.sweeps >= T->max_sweeps) {
+                nx = BP_DONE;
+                c.status = c.active == 0 ? GC_OK : GC_E_NOT_CONVERGED;
+                c.done_step = T->step;
+            } else {
+                c.period = batch_period(T, c.round, c.max_height);
+                c.sweep = 0;
+                nx = c.fused ? BP_SWEEP : BP_PUSH;
+            }
+            break;
+        case BP_PUSH:
+            nx = BP_RELABEL;
+            break;
+        case BP_RELABEL:
+            c.sweep++;
+            c.sweeps++;
+            if (c.sweep >= c.period) { c.round++; nx = BP_SEED; }
+            else nx = BP_PUSH;
+            break;
+        case BP_SWEEP:
+            c.sweep++;
+            c.sweeps++;
+            nx = c.sweep >= c.period ? BP_MERGE : BP_SWEEP;
+            break;
+        case BP_MERGE:
+            c.round++;
+            nx = BP_SEED;
+            break;
+        default:
+            nx = BP_DONE;
+        }
+        c.phase = nx;
+        s.hdr->lists[0] = 0;                // the step's lists count from zero
+        s.hdr->lists[2] = 0;
+        next = nx;
+    }
+    __syncthreads();
+    if (next == BP_COUNT) {                 // the count accumulates into the slots
+        s.slots[t].active = 0;
+        s.slots[t].max_height = 0;
+    }
+}
+
+// The work lists of the step, one workgroup per 256 candidates of a member.
+__global__ void __launch_bounds__(kBlock)
+k_batch_list(BatchDev *T, int tw, int th, int tj)
+{
+    const int64_t wg = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+    const int ng = T->ng;
+    if (wg >= T->list_off[ng]) return;
+    int lo = 0, hi = ng - 1;                 // largest member with list_off <= wg
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (T->list_off[mid] <= wg) lo = mid;
+        else hi = mid - 1;
+    }
+    const MemberCtl &c = T->ctl[lo];
+    const int phase = c.phase;
+    if (phase != BP_RELAX && phase != BP_PUSH && phase != BP_RELABEL && phase != BP_SWEEP) return;
+    const Graph s = T->graphs[lo];
+    const int64_t id = (wg - T->list_off[lo]) * kBlock + threadIdx.x;
+    bool want = false;
+    if (phase == BP_RELAX) {
+        if (id < c.tiles) {
+            const int pass = c.pass;
+            if (pass == 1) {
+                want = true;
+            } else {
+                const int ntx = (s.W + tw - 1) / tw, nty = (s.H + th - 1) / th, ntz = (s.J + tj - 1) / tj;
+                const int bx = (int)(id % ntx), by = (int)((id / ntx) % nty), bz = (int)(id / ((int64_t)ntx * nty));
+                for (int q = 0; q < 27 && !want; ++q) {
+                    const int tz = bz + q / 9 - 1, ty = by + (q / 3) % 3 - 1, tx = bx + q % 3 - 1;
+                    if (tz >= 0 && tz < ntz && ty >= 0 && ty < nty && tx >= 0 && tx < ntx)
+                        want = (s.stamps[(tz * nty + ty) * ntx + tx] >> 1) == pass - 1;
+                }
+            }
+        }
+        block_append(want, (int32_t)id, s.tlist, &s.hdr->lists[2]);
+    } else {
+        if (id < c.blocks) {
+            const uint32_t a = *(const uint32_t *)(s.bact + 4 * id);
+            const uint32_t f = phase == BP_PUSH ? 0u : *(const uint32_t *)(s.binf + 4 * id);
+            want = (a | f) != 0u;
+        }
+        block_append(want, (int32_t)id, s.blist, &s.hdr->lists[0]);
+    }
+}
+
+// Units of every member in this step and their prefix offsets, per kind.
+__global__ void __launch_bounds__(kMaxBatch)
+k_batch_scan(BatchDev *T)
+{
+    __shared__ int sc[3][kMaxBatch];
+    const int g = threadIdx.x, ng = T->ng;
+    int u = 0, kind = BK_FULL, live = 0;
+    if (g < ng) {
+        MemberCtl &c = T->ctl[g];
+        const Graph &s = T->graphs[g];
+        switch (c.phase) {
+        case BP_SEED: case BP_COUNT: case BP_MERGE: u = c.blocks; break;
+        case BP_RELAX: u = s.hdr->lists[2]; break;
+        case BP_PUSH: case BP_RELABEL: case BP_SWEEP: u = s.hdr->lists[0]; break;
+        default: u = 0;
+        }
+        kind = batch_kind(c.phase);
+        c.units = u;
+        live = c.phase != BP_DONE;
+    }
+    for (int k = 0; k < 3; ++k) sc[k][g] = kind == k ? u : 0;
+    __syncthreads();
+    for (int off = 1; off < kMaxBatch; off <<= 1) {      // inclusive scans
+        int v[3];
+        for (int k = 0; k < 3; ++k) v[k] = g >= off ? sc[k][g - off] : 0;
+        __syncthreads();
+        for (int k = 0; k < 3; ++k) sc[k][g] += v[k];
+        __syncthreads();
+    }
+    for (int k = 0; k < 3; ++k) {
+        if (g < ng) T->unit_off[k][g + 1] = sc[k][g];
+        if (g == 0) {
+            T->unit_off[k][0] = 0;
+            T->total[k] = ng > 0 ? sc[k][ng - 1] : 0;
+        }
+    }
+    const int nlive = block_sum(live);
+    if (g == 0) {
+        T->live = nlive;
+        T->step++;
+    }
+}
+
+// The member a unit of a kind belongs to: the largest g with off[g] <= u
+// (that member has units, since u < off[ng]).
+__device__ inline int batch_member(const int32_t *off, int ng, int u)
+{
+    int lo = 0, hi = ng - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Every block of the members in a seeding, counting or merging step.
+__global__ void __launch_bounds__(kBlock)
+k_batch_full(const BatchDev *__restrict__ T)
+{
+    const int total = T->total[BK_FULL], ng = T->ng;
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int g = __builtin_amdgcn_readfirstlane(batch_member(T->unit_off[BK_FULL], ng, u));
+        const Graph &s = T->graphs[g];          // fields load as needed (a copy held every one)
+        const int k = __builtin_amdgcn_readfirstlane(u - T->unit_off[BK_FULL][g]);
+        switch (T->ctl[g].phase) {
+        case BP_SEED:
+            mask_blk(s, k, 0);
+            seed_blk(s, k, 0);
+            break;
+        case BP_COUNT: count_blk(s, k); break;
+        case BP_MERGE: merge_blk(s, k); break;
+        default: break;
+        }
+        __syncthreads();                     // the count's shared memory is reused by the next unit
+    }
+}
+
+// The listed tiles of the members in a relaxation pass.
+template <int TW, int TH, int TJ>
+__global__ void __launch_bounds__(kBlock)
+k_batch_relax(const BatchDev *__restrict__ T)
+{
+    const int total = T->total[BK_RELAX], ng = T->ng;
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int g = __builtin_amdgcn_readfirstlane(batch_member(T->unit_off[BK_RELAX], ng, u));
+        const Graph &s = T->graphs[g];          // fields load as needed (a copy held every one)
+        const int k = u - T->unit_off[BK_RELAX][g];
+        relax_blk<TW, TH, TJ, true>(s, __builtin_amdgcn_readfirstlane(s.tlist[k]), 0, T->local_iters,
+                              __builtin_amdgcn_readfirstlane(T->ctl[g].pass));
+        __syncthreads();
+    }
+}
+
+// The listed blocks of the members in a push, relabel or fused sweep.
+__global__ void __launch_bounds__(kBlock)
+k_batch_sweeps(const BatchDev *__restrict__ T)
+{
+    const int total = T->total[BK_SWEEP], ng = T->ng;
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int g = __builtin_amdgcn_readfirstlane(batch_member(T->unit_off[BK_SWEEP], ng, u));
+        const Graph &s = T->graphs[g];          // fields load as needed (a copy held every one)
+        const int64_t lb = __builtin_amdgcn_readfirstlane(s.blist[u - T->unit_off[BK_SWEEP][g]]);
+        switch (T->ctl[g].phase) {
+        case BP_PUSH: push_blk(s, lb); break;
+        case BP_RELABEL: relabel_blk(s, lb); break;
+        case BP_SWEEP: sweep_blk(s, lb); break;
+        default: break;
+        }
+    }
+}
+
+using BatchWorkFn = void (*)(const BatchDev *__restrict__);   // the relaxation kernel of a tile shape
+
+// Relaxation tiles the batch engine is compiled for (the autotuner's candidates).
+#define GC_BATCH_SHAPES(X) X(8, 8, 16) X(16, 8, 16) X(8, 8, 32) X(16, 16, 8)
+
+BatchWorkFn batch_work_kernel(int tw, int th, int tj)
+{
+#define GC_BATCH_CASE(a, b, c) \
+    if (tw == a && th == b && tj == c) return k_batch_relax<a, b, c>;
+    GC_BATCH_SHAPES(GC_BATCH_CASE)
+#undef GC_BATCH_CASE
+    return nullptr;
+}
+
+// Steps per replay: the host reads the members' records once per this many
+// steps (a member that finishes early in a replay waits for its end).
+constexpr int kBatchSteps = 32;
+
+}  // namespace
 
 struct gc_batch {
     struct Member {
         gc_graph g;
         Graph s;
         int64_t tag;
-        gc_solve_stats st;
-        int64_t blocks, tiles;
+        bool reported = false;
     };
     BatchDev *dev = nullptr;
     Opts opt{};
+    BatchWorkFn work = nullptr;
     std::vector<Member> mem;
-    std::vector<char> host;            // staging copy of the table prefix
+    std::vector<MemberCtl> ctl;        // host copy of the members' records
+    std::vector<char> host;            // staging copy of the table
     bool dirty = true;
-    hipGraph_t graph = nullptr;
+    int64_t list_wgs = 0;
     hipGraphExec_t exec = nullptr;
-    std::vector<int64_t> exec_key;     // group bounds and grids the graph was captured for
     hipStream_t exec_stream = nullptr;
 };
 
 namespace {
 
-int batch_upload(gc_batch *b, hipStream_t st)
+MemberCtl member_init(const gc_batch *b, const Graph &s)
 {
-    if (!b->dirty) return GC_OK;
-    BatchDev *h = (BatchDev *)b->host.data();
-    const int ng = (int)b->mem.size();
-    h->ng = ng;
-    h->node_off[0] = 0;
-    h->tile_off[0] = 0;
-    for (int g = 0; g < ng; ++g) {
-        h->graphs[g] = b->mem[g].s;
-        h->node_off[g + 1] = h->node_off[g] + (int32_t)b->mem[g].blocks;
-        h->tile_off[g + 1] = h->tile_off[g] + (int32_t)b->mem[g].tiles;
-    }
-    const size_t bytes = offsetof(BatchDev, graphs) + (size_t)ng * sizeof(Graph);
-    if (!hip_ok(hipMemcpyAsync(b->dev, h, bytes, hipMemcpyHostToDevice, st))) return GC_E_HIP;
-    // the staging copy must outlive the transfer
-    if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
-    b->dirty = false;
-    return GC_OK;
+    MemberCtl c;
+    memset(&c, 0, sizeof(c));
+    c.phase = BP_INIT;
+    c.fused = sweep_fused(b->opt, s.J) ? 1 : 0;
+    c.blocks = (int32_t)grid_for(s.N);
+    c.tiles = (int32_t)relax_tiles(s, b->opt);
+    return c;
 }
 
 void batch_drop_graph(gc_batch *b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
-    b->graph = nullptr;
-    b->exec_key.clear();
+    b->exec_stream = nullptr;
 }
 
-// Sweeps touch 40 B per node (excess, height, inflow, seven pair words).  The
-// members are split into consecutive groups whose sweep state fits in this
-// many bytes, and each group runs its whole period of sweeps before the next
-// starts, so a group of small graphs keeps its state in the 256 MB Infinity
-// Cache instead of streaming every member from HBM on every sweep.  A
-// member larger than the budget forms a group of its own.
-constexpr size_t kSweepBytesPerNode = 40;
-constexpr size_t kSweepGroupBytes = size_t(192) << 20;
+// Writes the table: members, their records as last read back, offsets.
+int batch_upload(gc_batch *b, hipStream_t st)
+{
+    BatchDev *h = (BatchDev *)b->host.data();
+    const int ng = (int)b->mem.size();
+    memset(h, 0, sizeof(BatchDev));
+    h->ng = ng;
+    h->live = ng;
+    h->period = b->opt.period;
+    h->max_sweeps = b->opt.max_sweeps;
+    h->local_iters = b->opt.local_iters;
+    h->flags = b->opt.flags;
+    h->list_off[0] = 0;
+    for (int g = 0; g < ng; ++g) {
+        h->graphs[g] = b->mem[g].s;
+        h->ctl[g] = b->ctl[g];
+        const int64_t cand = std::max<int64_t>(b->ctl[g].blocks, b->ctl[g].tiles);
+        h->list_off[g + 1] = h->list_off[g] + (int32_t)((cand + kBlock - 1) / kBlock);
+    }
+    b->list_wgs = h->list_off[ng];
+    if (!hip_ok(hipMemcpyAsync(b->dev, h, sizeof(BatchDev), hipMemcpyHostToDevice, st))) return GC_E_HIP;
+    if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;   // the staging copy is reused
+    b->dirty = false;
+    return GC_OK;
+}
 
-void sweep_groups(const gc_batch *b, std::vector<int> &bounds)
+void launch_batch_steps(gc_batch *b, hipStream_t st, int steps)
 {
     const int ng = (int)b->mem.size();
-    bounds.assign(1, 0);
-    size_t acc = 0;
-    for (int g = 0; g < ng; ++g) {
-        const size_t by = (size_t)b->mem[g].s.N * kSweepBytesPerNode;
-        if (g > bounds.back() && acc + by > kSweepGroupBytes) {
-            bounds.push_back(g);
-            acc = 0;
-        }
-        acc += by;
-    }
-    bounds.push_back(ng);
-}
-
-// Sweep kind of a group: by the flags, else by its shallowest member.
-bool group_fused(const gc_batch *b, int g0, int g1)
-{
-    int layers = 1 << 30;
-    for (int g = g0; g < g1; ++g) layers = b->mem[g].s.J < layers ? b->mem[g].s.J : layers;
-    return sweep_fused(b->opt, layers);
-}
-
-// One period of sweeps, group after group; grids[k] workgroups for group k.
-void launch_sweeps(gc_batch *b, hipStream_t st, const std::vector<int> &bounds,
-                   const std::vector<int64_t> &grids)
-{
-    for (size_t k = 0; k + 1 < bounds.size(); ++k) {
-        const bool fused = group_fused(b, bounds[k], bounds[k + 1]);
-        const Batch B{b->dev, bounds[k], bounds[k + 1]};
-        const dim3 grid = batch_grid(grids[k]);
-        for (int i = 0; i < b->opt.period; ++i) {
-            if (fused) {
-                hipLaunchKernelGGL(k_sweep<Batch>, grid, dim3(kBlock), 0, st, B);
-            } else {
-                hipLaunchKernelGGL(k_push<Batch>, grid, dim3(kBlock), 0, st, B);
-                hipLaunchKernelGGL(k_relabel<Batch>, grid, dim3(kBlock), 0, st, B);
-            }
-        }
-        if (fused) hipLaunchKernelGGL(k_merge<Batch>, grid, dim3(kBlock), 0, st, B);
+    for (int i = 0; i < steps; ++i) {
+        hipLaunchKernelGGL(k_batch_phase, dim3(ng), dim3(kSlots), 0, st, b->dev);
+        hipLaunchKernelGGL(k_batch_list, batch_grid(b->list_wgs), dim3(kBlock), 0, st, b->dev,
+                           b->opt.tw, b->opt.th, b->opt.tj);
+        hipLaunchKernelGGL(k_batch_scan, dim3(1), dim3(kMaxBatch), 0, st, b->dev);
+        hipLaunchKernelGGL(k_batch_full, dim3(resident_grid(k_batch_full)), dim3(kBlock), 0, st,
+                           (const BatchDev *)b->dev);
+        hipLaunchKernelGGL(b->work, dim3(resident_grid(b->work)), dim3(kBlock), 0, st, (const BatchDev *)b->dev);
+        hipLaunchKernelGGL(k_batch_sweeps, dim3(resident_grid(k_batch_sweeps)), dim3(kBlock), 0, st,
+                           (const BatchDev *)b->dev);
     }
 }
 
@@ -2554,10 +2847,13 @@ GC_API int gc_batch_create(void *dev_table, size_t dev_bytes, const gc_solve_opt
     Opts opt = resolve(o);
     int rc = check_opts(opt);
     if (rc != GC_OK) return rc;
+    BatchWorkFn work = batch_work_kernel(opt.tw, opt.th, opt.tj);
+    if (!work) return GC_E_ARG;
     gc_batch *b = new (std::nothrow) gc_batch();
     if (!b) return GC_E_ARG;
     b->dev = (BatchDev *)dev_table;
     b->opt = opt;
+    b->work = work;
     b->host.assign(sizeof(BatchDev), 0);
     *out = b;
     return GC_OK;
@@ -2571,23 +2867,26 @@ GC_API int gc_batch_destroy(gc_batch *b)
     return GC_OK;
 }
 
-GC_API int gc_batch_members(const gc_batch *b) { return b ? (int)b->mem.size() : 0; }
+GC_API int gc_batch_members(const gc_batch *b)
+{
+    if (!b) return 0;
+    int n = 0;
+    for (const auto &m : b->mem) n += m.reported ? 0 : 1;
+    return n;
+}
 
 GC_API int gc_batch_add(gc_batch *b, const gc_graph *g, int64_t tag)
 {
     if (!b) return GC_E_ARG;
     int rc = graph_check(g);
     if (rc != GC_OK) return rc;
-    if ((int)b->mem.size() >= kMaxBatch) return GC_E_ARG;
+    if (gc_batch_members(b) >= kMaxBatch) return GC_E_ARG;
     gc_batch::Member m;
     m.g = *g;
     m.s = view(g);
     m.tag = tag;
-    memset(&m.st, 0, sizeof(m.st));
-    m.blocks = (int64_t)grid_for(m.s.N);
-    m.tiles = relax_tiles(m.s, b->opt);
-    if (m.s.N == 0) m.blocks = m.tiles = 0;
     b->mem.push_back(m);
+    b->ctl.push_back(member_init(b, m.s));
     b->dirty = true;
     return GC_OK;
 }
@@ -2598,134 +2897,67 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
     if (!b || !n_done || (max_done > 0 && !done_tags)) return GC_E_ARG;
     *n_done = 0;
     hipStream_t st = (hipStream_t)stream;
-    int rc;
-    // empty graphs are finished at once
-    for (size_t i = 0; i < b->mem.size();) {
-        if (b->mem[i].s.N == 0 && *n_done < max_done) {
-            done_tags[*n_done] = b->mem[i].tag;
-            if (done_stats) done_stats[*n_done] = b->mem[i].st;
-            ++*n_done;
-            b->mem.erase(b->mem.begin() + i);
-            b->dirty = true;
-        } else {
-            ++i;
+    auto report = [&](size_t i) {
+        gc_batch::Member &m = b->mem[i];
+        const MemberCtl &c = b->ctl[i];
+        done_tags[*n_done] = m.tag;
+        if (done_stats) {
+            gc_solve_stats &o = done_stats[*n_done];
+            memset(&o, 0, sizeof(o));
+            o.sweeps = c.sweeps;
+            o.global_relabels = c.relabels;
+            o.bfs_passes = c.passes;
+            o.active_last = c.active;
+            o.pushes = c.pushes;
+            o.active_visits = c.visits;
         }
+        ++*n_done;
+        m.reported = true;
+    };
+    // finished members not yet reported; empty graphs finish at once
+    for (size_t i = 0; i < b->mem.size() && *n_done < max_done; ++i) {
+        if (b->mem[i].reported) continue;
+        if (b->mem[i].s.N == 0) { b->ctl[i].phase = BP_DONE; b->ctl[i].status = GC_OK; }
+        if (b->ctl[i].phase == BP_DONE) report(i);
     }
-    if (b->mem.empty()) return GC_OK;
-    if ((rc = batch_upload(b, st)) != GC_OK) return rc;
+    int live = 0;
+    for (size_t i = 0; i < b->mem.size(); ++i) live += (!b->mem[i].reported && b->ctl[i].phase != BP_DONE);
+    if (live == 0) return GC_OK;
+    // a member joined (or the table holds reported members and others wait):
+    // drop the reported ones and write the table again
+    if (b->dirty) {
+        size_t k = 0;
+        for (size_t i = 0; i < b->mem.size(); ++i)
+            if (!b->mem[i].reported) { b->mem[k] = b->mem[i]; b->ctl[k] = b->ctl[i]; ++k; }
+        b->mem.resize(k);
+        b->ctl.resize(k);
+        batch_drop_graph(b);
+        int rc = batch_upload(b, st);
+        if (rc != GC_OK) return rc;
+    }
     const int ng = (int)b->mem.size();
-    const BatchDev *h = (const BatchDev *)b->host.data();
-    const int64_t nblk = h->node_off[ng], ntile = h->tile_off[ng];
-    const Batch B{b->dev, 0, ng};
-    const Opts &o = b->opt;
-    const dim3 gnode = batch_grid(nblk), gtile = batch_grid(ntile);
-
-    // wave-front pass for the members in their first round (or for all),
-    // then exact global relabelling of every member
-    for (int g0 = 0; g0 < ng;) {
-        int g1 = g0;
-        while (g1 < ng && wave_in_round(o, b->mem[g1].st.global_relabels)) ++g1;
-        if (g1 > g0) {
-            const Batch W{b->dev, g0, g1};
-            hipLaunchKernelGGL(k_wave<Batch>, batch_grid(h->node_off[g1] - h->node_off[g0]),
-                               dim3(kBlock), 0, st, W);
-            g0 = g1;
-        } else {
-            ++g0;
-        }
+    if (st != nullptr && !b->exec) {
+        hipGraph_t g = nullptr;
+        if (!hip_ok(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal))) return GC_E_HIP;
+        launch_batch_steps(b, st, kBatchSteps);
+        if (!hip_ok(hipStreamEndCapture(st, &g))) return GC_E_HIP;
+        const bool ok = hip_ok(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        if (!ok) { b->exec = nullptr; return GC_E_HIP; }
+        b->exec_stream = st;
     }
-    hipLaunchKernelGGL(k_mask<Batch>, gnode, dim3(kBlock), 0, st, B, 0);
-    hipLaunchKernelGGL(k_seed<Batch>, gnode, dim3(kBlock), 0, st, B, 0);
-    RelaxFn<Batch> fn = relax_kernel<Batch>(o.tw, o.th, o.tj);
-    std::vector<int32_t> gathered((size_t)ng * 16);
-    std::vector<char> conv(ng, 0);
-    int passes = 0, batch = 4, n_conv = 0;
-    while (n_conv < ng) {
-        hipLaunchKernelGGL(k_batch_zero, dim3(ng), dim3(kSlots), 0, st, b->dev, 0, passes + 1, batch);
-        for (int q = 1; q <= batch; ++q)
-            hipLaunchKernelGGL(fn, gtile, dim3(kBlock), 0, st, B, 0, o.local_iters, passes + q);
-        hipLaunchKernelGGL(k_batch_gather, dim3(ng), dim3(kSlots), 0, st, b->dev, 0);
-        if (!hip_ok(hipGetLastError())) return GC_E_HIP;
-        if (!hip_ok(hipMemcpyAsync(gathered.data(), b->dev->gathered, gathered.size() * 4,
-                                   hipMemcpyDeviceToHost, st)))
-            return GC_E_HIP;
-        if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
-        for (int g = 0; g < ng; ++g) {
-            if (conv[g]) continue;
-            for (int q = 1; q <= batch; ++q) {
-                b->mem[g].st.bfs_passes++;
-                if (!gathered[(size_t)g * 16 + (passes + q) % kMaxFlags]) { conv[g] = 1; ++n_conv; break; }
-            }
-        }
-        passes += batch;
-        if (passes >= (1 << 22)) return GC_E_NOT_CONVERGED;
-        batch = batch >= 8 ? kMaxFlags - 1 : batch * 2;      // as in relax_to_fixpoint
+    if (b->exec && b->exec_stream == st) {
+        if (!hip_ok(hipGraphLaunch(b->exec, st))) return GC_E_HIP;
+    } else {
+        launch_batch_steps(b, st, kBatchSteps);
     }
-    // termination test
-    hipLaunchKernelGGL(k_batch_zero, dim3(ng), dim3(kSlots), 0, st, b->dev, 1, 0, 0);
-    hipLaunchKernelGGL(k_count_active<Batch>, gnode, dim3(kBlock), 0, st, B);
-    hipLaunchKernelGGL(k_batch_gather, dim3(ng), dim3(kSlots), 0, st, b->dev, 1);
     if (!hip_ok(hipGetLastError())) return GC_E_HIP;
-    if (!hip_ok(hipMemcpyAsync(gathered.data(), b->dev->gathered, gathered.size() * 4,
+    if (!hip_ok(hipMemcpyAsync(b->ctl.data(), b->dev->ctl, (size_t)ng * sizeof(MemberCtl),
                                hipMemcpyDeviceToHost, st)))
         return GC_E_HIP;
     if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
-    std::vector<gc_batch::Member> keep;
-    keep.reserve(b->mem.size());
-    for (int g = 0; g < ng; ++g) {
-        gc_batch::Member &m = b->mem[g];
-        const int32_t *gv = &gathered[(size_t)g * 16];
-        m.st.global_relabels++;
-        m.st.active_last = gv[0];
-        m.st.pushes = (int64_t)(uint32_t)gv[1] | ((int64_t)(uint32_t)gv[2] << 31);
-        m.st.active_visits = (int64_t)(uint32_t)gv[3] | ((int64_t)(uint32_t)gv[4] << 31);
-        const bool finished = gv[0] == 0 || m.st.sweeps >= o.max_sweeps;
-        if (finished && *n_done < max_done) {
-            done_tags[*n_done] = m.tag;
-            if (done_stats) done_stats[*n_done] = m.st;
-            ++*n_done;
-            b->dirty = true;
-        } else {
-            keep.push_back(m);
-        }
-    }
-    b->mem.swap(keep);
-    if (b->mem.empty()) return GC_OK;
-    // push-relabel sweeps of the members still running, group by group
-    if ((rc = batch_upload(b, st)) != GC_OK) return rc;
-    const BatchDev *hk = (const BatchDev *)b->host.data();
-    std::vector<int> bounds;
-    sweep_groups(b, bounds);
-    std::vector<int64_t> grids(bounds.size() - 1);
-    for (size_t k = 0; k + 1 < bounds.size(); ++k)
-        grids[k] = hk->node_off[bounds[k + 1]] - hk->node_off[bounds[k]];
-    const bool use_graph = st != nullptr && (o.flags & GC_OPT_SWEEP_GRAPH) != 0;
-    if (use_graph) {
-        std::vector<int64_t> key;
-        for (size_t k = 0; k + 1 < bounds.size(); ++k) {
-            int64_t cap = 1;
-            while (cap < grids[k]) cap <<= 1;         // upper-bound grids: fewer captures
-            grids[k] = cap;
-            key.push_back(bounds[k]);
-            key.push_back(cap);
-            key.push_back(group_fused(b, bounds[k], bounds[k + 1]));
-        }
-        key.push_back(bounds.back());
-        if (b->exec_key != key || b->exec_stream != st) {
-            batch_drop_graph(b);
-            if (!hip_ok(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal))) return GC_E_HIP;
-            launch_sweeps(b, st, bounds, grids);
-            if (!hip_ok(hipStreamEndCapture(st, &b->graph))) return GC_E_HIP;
-            if (!hip_ok(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0))) return GC_E_HIP;
-            b->exec_key = key;
-            b->exec_stream = st;
-        }
-        if (!hip_ok(hipGraphLaunch(b->exec, st))) return GC_E_HIP;
-    } else {
-        launch_sweeps(b, st, bounds, grids);
-    }
-    if (!hip_ok(hipGetLastError())) return GC_E_HIP;
-    for (auto &m : b->mem) m.st.sweeps += o.period;
+    for (int i = 0; i < ng && *n_done < max_done; ++i)
+        if (!b->mem[i].reported && b->ctl[i].phase == BP_DONE) report(i);
     return GC_OK;
 }
 

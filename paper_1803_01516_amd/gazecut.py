@@ -323,16 +323,21 @@ def graph_build_window(p: GcProblem, cost, coarse_labels, block: int, ws, stream
     return Graph(g, ws)
 
 
-# Wave steps (A - 1) of the level-2 cut when the caller gives none: on the
-# 384x288x16 pairs 24-32 steps already reach the level-1 labels' quality, the
-# 64-label pairs with textureless regions need about 64 (measured on the
-# oracle: fewer steps leave whole regions whose flow has not yet reached the
-# cut, and the read-out then places them at the window's top).
-LEVEL2_WAVE_STEPS = 64
+# Wave steps (A - 1) of the level-2 cut when the caller gives none:
+# max(32, labels).  Measured on MI355X: on the 384x288x16 pairs 32 steps
+# reach the level-1 labels' quality (eq. (2) error 1195 against 1161 for
+# level 1 b=3; 16 steps leave it at 137000) in 2.1 ms against 3.0 ms for 64;
+# the 450x375x64 pairs with textureless regions need 64 (at 32 steps whole
+# regions whose flow has not yet reached the cut are read out at the top of
+# their windows: error 503000 against 49900).
+def level2_wave_steps(labels: int) -> int:
+    return max(32, int(labels))
 
 
 def approx_level2_cut(skin: Graph, cost, coarse_labels, labels, result, stream=None,
-                      wave_steps: int = LEVEL2_WAVE_STEPS):
+                      wave_steps: int | None = None):
+    if wave_steps is None:
+        wave_steps = level2_wave_steps(skin.handle.p.labels)
     _check(load().approx_level2_cut(ctypes.byref(skin.handle), ctypes.c_void_p(cost.data_ptr()),
                                     ctypes.c_void_p(coarse_labels.data_ptr()), int(wave_steps),
                                     ctypes.c_void_p(labels.data_ptr()),
@@ -349,7 +354,7 @@ APPROX_RELABEL_PERIOD = 32
 
 
 def approx_level1(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, stream=None,
-                  ws=None, ws_coarse=None, level: int = 1, wave_steps: int = LEVEL2_WAVE_STEPS):
+                  ws=None, ws_coarse=None, level: int = 1, wave_steps: int | None = None):
     """Delegate-point cut, then the cut inside the thin skin: exact (level 1)
     or block by block after a wave-front pass (level 2).  Returns (labels,
     energy, flow, coarse labels, (coarse stats, fine stats)); level 2 has
@@ -426,7 +431,7 @@ def solve_warm(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, 
 
 
 def approx_level2(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, stream=None,
-                  ws=None, ws_coarse=None, wave_steps: int = LEVEL2_WAVE_STEPS):
+                  ws=None, ws_coarse=None, wave_steps: int | None = None):
     return approx_level1(p, cost, block, opts, stream, ws, ws_coarse, level=2,
                          wave_steps=wave_steps)
 

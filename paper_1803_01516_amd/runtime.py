@@ -93,13 +93,14 @@ SWEEP_CANDIDATES = (0, gc.GC_OPT_FUSED_SWEEP, gc.GC_OPT_SPLIT_SWEEP)   # by dept
 
 
 def autotune(items, tiles=TILE_CANDIDATES, periods=PERIOD_CANDIDATES, sweeps=SWEEP_CANDIDATES,
-             stream=None, use_graph=False):
+             stream=None, use_graph=False, extra_flags=0):
     """Times one batched solve of `items` per (tile, period, sweep kind)
     candidate and returns (best options, [(tile, period, sweep flags,
     seconds)]).  The items' graphs are rebuilt in place before every trial,
-    so the trials solve the same graphs."""
+    so the trials solve the same graphs.  extra_flags selects the engine
+    (GC_OPT_BATCH_MERGED: the batch engine; none: concurrent lanes)."""
     import torch
-    base = gc.GC_OPT_SWEEP_GRAPH if use_graph else 0
+    base = (gc.GC_OPT_SWEEP_GRAPH if use_graph else 0) | extra_flags
     table = torch.empty(gc.batch_footprint_bytes(), dtype=torch.uint8, device="cuda")
     trials = []
     for tile in tiles:
@@ -477,4 +478,8 @@ def latency_summary(done):
     return {"p50_ms": round(float(np.percentile(lat, 50)), 2),
             "p99_ms": round(float(np.percentile(lat, 99)), 2),
             "mean_ms": round(float(lat.mean()), 2),
-            "admission_wait_p99_ms": round(float(np.percentile(wait, 99)), 2)}
+            "admission_wait_p50_ms": round(float(np.percentile(wait, 50)), 2),
+            "admission_wait_p99_ms": round(float(np.percentile(wait, 99)), 2),
+            # share of the mean latency spent waiting for admission (memory
+            # budget or a full lane) rather than on the GPU
+            "queue_share": round(float(wait.mean() / lat.mean()), 4) if lat.mean() > 0 else 0.0}

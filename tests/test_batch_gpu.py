@@ -1,6 +1,7 @@
 """GPU tests of the batched solve: graphs of mixed sizes and kinds solved in
-one batch (one launch per phase over all members) give the same canonical
-cut, energy and flow as one solve per graph and as the oracle."""
+one batch (every member advancing on the device, each step's launches shared
+by all members) give the same canonical cut, energy and flow as one solve per
+graph and as the oracle."""
 import numpy as np
 import pytest
 
@@ -112,10 +113,9 @@ def test_batch_rounds_with_members_joining(torch_cuda, orc):
 
 
 def test_batch_larger_than_one_launch_grid(torch_cuda):
-    """Two 450x375x64 graphs hold more node blocks than one grid row has
-    workgroups (65535), so the launch grid gets a second dimension, and each
-    graph's sweep state exceeds the cache-sized group budget, so the sweeps
-    run in two groups; the cuts equal the single-graph solves."""
+    """Two 450x375x64 graphs (more node blocks than one grid row has
+    workgroups, 65535) in one batch: their lists fill the shared work queue
+    together; the cuts equal the single-graph solves."""
     torch = torch_cuda
     items = []
     for seed in [(3, 0), (3, 1)]:
@@ -142,9 +142,10 @@ def test_batch_larger_than_one_launch_grid(torch_cuda):
                                    gc.GC_OPT_WAVE_FIRST | gc.GC_OPT_SWEEP_GRAPH],
                          ids=["plain", "fused", "fused-graph", "wave-graph"])
 def test_batch_groups_and_variants(torch_cuda, orc, flags):
-    """Four 384x288x16 graphs (66 MB of sweep state each) split into two
-    sweep groups, mixed with small graphs; every solver variant gives the
-    single-graph cut (itself checked against the oracle for the small ones)."""
+    """Four 384x288x16 graphs mixed with small graphs; every solver variant
+    (split or fused sweeps, direct launches or a captured round; the batch
+    engine ignores the wave-front option) gives the single-graph cut (itself
+    checked against the oracle for the small ones)."""
     torch = torch_cuda
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
