@@ -211,7 +211,7 @@ def bench_batch(args, gc, sg, torch):
             return times, total, out
 
         t_one, tot_one, ref = run(rt.run_one_per_launch, None, "one pair per launch")
-        t_eng, tot_eng, got_e = run(rt.run_merged, best_eng, "batch engine")
+        t_eng, tot_eng, got_e = run(rt.run_batched, best_eng, "batch engines")
         t_lan, tot_lan, got_l = run(rt.run_batched, best_lanes, "concurrent lanes")
         same = all(a[0] == b[0] == c[0] and a[1] == b[1] == c[1] and bool((a[2] == b[2]).all())
                    and bool((a[2] == c[2]).all()) for a, b, c in zip(ref, got_e, got_l))
@@ -231,8 +231,9 @@ def bench_batch(args, gc, sg, torch):
                         "640x480x64 (6-10 slanted planes, sigma 3, cap 30, penalty 1, inhibit 1023)",
             "nodes_total": nodes,
             "batched": dict(block(t_eng, tot_eng),
-                            mode="batch engine: members advance on the device, 32 captured steps "
-                                 "per host read-back, one work queue per unit kind",
+                            mode=f"{gc.GC_BATCH_ENGINES} batch engines on their own streams, driven "
+                                 "from one host thread: members advance on the device, 32 captured "
+                                 "steps per read-back, one work queue per unit kind",
                             options=opts_of(best_eng)),
             "one_per_launch": block(t_one, tot_one),
             "concurrent_lanes": dict(block(t_lan, tot_lan),

@@ -419,6 +419,9 @@ int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solve_stats
 /* Concurrent lanes of maxflow_solve_batch (host threads, one HIP stream each). */
 #define GC_BATCH_LANES 4
 
+/* Batch engines of maxflow_solve_batch with GC_OPT_BATCH_MERGED. */
+#define GC_BATCH_ENGINES 2
+
 /* gc_solve_opts.flags, maxflow_solve_batch: run the graphs in rounds of the
  * batch engine (gc_batch_*: every member advances on the device, each step's
  * launches shared by all members; on `stream`, using dev_table) instead of
@@ -431,8 +434,12 @@ int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solve_stats
  * priority) and solve one graph at a time exactly as maxflow_solve does, so
  * one graph's latency-bound phases (relaxation passes, read-backs) overlap
  * other graphs' sweeps; dev_table may then be NULL.  With
- * GC_OPT_BATCH_MERGED the graphs run in rounds of the merged engine on
- * `stream`, refilled as members finish (dev_table: see gc_batch_create).
+ * GC_OPT_BATCH_MERGED the graphs, largest first, are dealt to up to
+ * GC_BATCH_ENGINES batch engines (gc_batch_*), the first on `stream`, the
+ * others on streams of their own, all driven from the calling thread (every
+ * engine's round is queued before any is waited for) and refilled as members
+ * finish; dev_table holds one table of gc_batch_footprint_bytes() per engine
+ * (dev_bytes decides how many run, at least one).
  * Either way the work starts after what is queued on `stream` so far.  stats
  * (optional) receives n entries in input order.  Returns GC_E_NOT_CONVERGED
  * if any graph hit max_sweeps, else the first error of any graph. */

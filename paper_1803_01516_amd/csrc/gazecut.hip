@@ -309,6 +309,8 @@ struct MemberCtl {
     int32_t active, max_height;
     int32_t sweeps, passes, relabels;
     int32_t done_step;        // step in which it finished
+    int32_t dense;            // this step's sweep takes every block in order (list too long)
+    int32_t pad;
     long long pushes, visits;
 };
 
@@ -1067,13 +1069,18 @@ __device__ inline void relax_blk(const Graph &s, int64_t lb, int mode, int max_r
     // round trip instead of 27 in a row); neighbouring tiles may rewrite
     // their stamps during this pass, so the block-wide OR of what was read
     // decides for the whole block.
-    int changed = pass == 1;
-    if (pass > 1 && tid < 27) {
-        const int tz = bz + tid / 9 - 1, ty = by + (tid / 3) % 3 - 1, tx = bx + tid % 3 - 1;
-        if (tz >= 0 && tz < ntz && ty >= 0 && ty < nty && tx >= 0 && tx < ntx)
-            changed = (stamps[(tz * nty + ty) * ntx + tx] >> 1) == pass - 1;
+    // (a listed tile passed this test when the list was made)
+    if (!kLooped) {
+        int changed = pass == 1;
+        if (pass > 1 && tid < 27) {
+            const int tz = bz + tid / 9 - 1, ty = by + (tid / 3) % 3 - 1, tx = bx + tid % 3 - 1;
+            if (tz >= 0 && tz < ntz && ty >= 0 && ty < nty && tx >= 0 && tx < ntx)
+                changed = (stamps[(tz * nty + ty) * ntx + tx] >> 1) == pass - 1;
+        }
+        if (!__syncthreads_or(changed)) return;
+    } else {
+        __syncthreads();                     // the tile before may still read the shared arrays
     }
-    if (!__syncthreads_or(changed)) return;
     const int x0 = bx * TW, y0 = by * TH, j0 = bz * TJ;
 
     // Halo values and masks: all of a thread's loads are issued before the
@@ -2639,6 +2646,13 @@ k_batch_scan(BatchDev *T)
         default: u = 0;
         }
         kind = batch_kind(c.phase);
+        // A sweep whose list holds more than half of the member's blocks
+        // runs over every block in index order instead: a block then tests
+        // its flags when it runs and takes flow pushed into it earlier in the
+        // same sweep, as one workgroup per block does, where a list fixed
+        // before the sweep leaves it for the next one.
+        c.dense = kind == BK_SWEEP && 2 * u > c.blocks;
+        if (c.dense) u = c.blocks;
         c.units = u;
         live = c.phase != BP_DONE;
     }
@@ -2724,7 +2738,8 @@ k_batch_sweeps(const BatchDev *__restrict__ T)
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         const int g = __builtin_amdgcn_readfirstlane(batch_member(T->unit_off[BK_SWEEP], ng, u));
         const Graph &s = T->graphs[g];          // fields load as needed (a copy held every one)
-        const int64_t lb = __builtin_amdgcn_readfirstlane(s.blist[u - T->unit_off[BK_SWEEP][g]]);
+        const int k = u - T->unit_off[BK_SWEEP][g];
+        const int64_t lb = T->ctl[g].dense ? k : __builtin_amdgcn_readfirstlane(s.blist[k]);
         switch (T->ctl[g].phase) {
         case BP_PUSH: push_blk(s, lb); break;
         case BP_RELABEL: relabel_blk(s, lb); break;
@@ -2771,6 +2786,8 @@ struct gc_batch {
     int64_t list_wgs = 0;
     hipGraphExec_t exec = nullptr;
     hipStream_t exec_stream = nullptr;
+    MemberCtl *pinned = nullptr;       // landing buffer of the records' read-back
+    int launched = 0;                  // members whose records the read-back in flight covers
 };
 
 namespace {
@@ -2855,6 +2872,10 @@ GC_API int gc_batch_create(void *dev_table, size_t dev_bytes, const gc_solve_opt
     b->opt = opt;
     b->work = work;
     b->host.assign(sizeof(BatchDev), 0);
+    // pinned, so that the read-back does not block the host thread (a
+    // pageable destination is copied synchronously)
+    if (hipHostMalloc((void **)&b->pinned, kMaxBatch * sizeof(MemberCtl), hipHostMallocDefault) != hipSuccess)
+        b->pinned = nullptr;
     *out = b;
     return GC_OK;
 }
@@ -2863,6 +2884,7 @@ GC_API int gc_batch_destroy(gc_batch *b)
 {
     if (!b) return GC_E_ARG;
     batch_drop_graph(b);
+    if (b->pinned) (void)hipHostFree(b->pinned);
     delete b;
     return GC_OK;
 }
@@ -2891,14 +2913,17 @@ GC_API int gc_batch_add(gc_batch *b, const gc_graph *g, int64_t tag)
     return GC_OK;
 }
 
-GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solve_stats *done_stats,
-                          int32_t max_done, int32_t *n_done)
+namespace {
+
+// Reports finished members not yet reported (at most max_done in total).
+void batch_report(gc_batch *b, int64_t *done_tags, gc_solve_stats *done_stats, int32_t max_done,
+                  int32_t *n_done)
 {
-    if (!b || !n_done || (max_done > 0 && !done_tags)) return GC_E_ARG;
-    *n_done = 0;
-    hipStream_t st = (hipStream_t)stream;
-    auto report = [&](size_t i) {
+    for (size_t i = 0; i < b->mem.size() && *n_done < max_done; ++i) {
         gc_batch::Member &m = b->mem[i];
+        if (m.reported) continue;
+        if (m.s.N == 0) { b->ctl[i].phase = BP_DONE; b->ctl[i].status = GC_OK; }   // empty: done at once
+        if (b->ctl[i].phase != BP_DONE) continue;
         const MemberCtl &c = b->ctl[i];
         done_tags[*n_done] = m.tag;
         if (done_stats) {
@@ -2913,18 +2938,21 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
         }
         ++*n_done;
         m.reported = true;
-    };
-    // finished members not yet reported; empty graphs finish at once
-    for (size_t i = 0; i < b->mem.size() && *n_done < max_done; ++i) {
-        if (b->mem[i].reported) continue;
-        if (b->mem[i].s.N == 0) { b->ctl[i].phase = BP_DONE; b->ctl[i].status = GC_OK; }
-        if (b->ctl[i].phase == BP_DONE) report(i);
     }
+}
+
+// First half of a round: reports what already finished, writes the table
+// again if members joined, queues the steps and the records' read-back on
+// `st`, and returns without waiting (b->launched = 0 when nothing runs).
+int batch_round_launch(gc_batch *b, hipStream_t st, int64_t *done_tags, gc_solve_stats *done_stats,
+                       int32_t max_done, int32_t *n_done)
+{
+    b->launched = 0;
+    batch_report(b, done_tags, done_stats, max_done, n_done);
     int live = 0;
     for (size_t i = 0; i < b->mem.size(); ++i) live += (!b->mem[i].reported && b->ctl[i].phase != BP_DONE);
     if (live == 0) return GC_OK;
-    // a member joined (or the table holds reported members and others wait):
-    // drop the reported ones and write the table again
+    // a member joined: drop the reported ones and write the table again
     if (b->dirty) {
         size_t k = 0;
         for (size_t i = 0; i < b->mem.size(); ++i)
@@ -2952,50 +2980,140 @@ GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solv
         launch_batch_steps(b, st, kBatchSteps);
     }
     if (!hip_ok(hipGetLastError())) return GC_E_HIP;
-    if (!hip_ok(hipMemcpyAsync(b->ctl.data(), b->dev->ctl, (size_t)ng * sizeof(MemberCtl),
-                               hipMemcpyDeviceToHost, st)))
+    void *dst = b->pinned ? (void *)b->pinned : (void *)b->ctl.data();
+    if (!hip_ok(hipMemcpyAsync(dst, b->dev->ctl, (size_t)ng * sizeof(MemberCtl), hipMemcpyDeviceToHost, st)))
         return GC_E_HIP;
-    if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
-    for (int i = 0; i < ng && *n_done < max_done; ++i)
-        if (!b->mem[i].reported && b->ctl[i].phase == BP_DONE) report(i);
+    b->launched = ng;
     return GC_OK;
+}
+
+// Second half: waits for the read-back and reports the members it shows finished.
+int batch_round_collect(gc_batch *b, hipStream_t st, int64_t *done_tags, gc_solve_stats *done_stats,
+                        int32_t max_done, int32_t *n_done)
+{
+    if (b->launched == 0) return GC_OK;
+    if (!hip_ok(hipStreamSynchronize(st))) return GC_E_HIP;
+    if (b->pinned) memcpy(b->ctl.data(), b->pinned, (size_t)b->launched * sizeof(MemberCtl));
+    b->launched = 0;
+    batch_report(b, done_tags, done_stats, max_done, n_done);
+    return GC_OK;
+}
+
+}  // namespace
+
+GC_API int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solve_stats *done_stats,
+                          int32_t max_done, int32_t *n_done)
+{
+    if (!b || !n_done || (max_done > 0 && !done_tags)) return GC_E_ARG;
+    *n_done = 0;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = batch_round_launch(b, st, done_tags, done_stats, max_done, n_done);
+    if (rc != GC_OK) return rc;
+    return batch_round_collect(b, st, done_tags, done_stats, max_done, n_done);
 }
 
 namespace {
 
-// Merged rounds: the graphs share launches, refilled as members finish.
+// Batch engines driven from this thread: the graphs, largest first, are
+// dealt to up to kBatchEngines engines, each on its own stream (the first on
+// the caller's), refilled as members finish.  Every round of every engine is
+// queued before any is waited for, so one engine's steps run while another
+// is between rounds and each engine's step boundaries are filled by the
+// other's launches.  dev_bytes holds one table per engine.
+constexpr int kBatchEngines = GC_BATCH_ENGINES;
+
 int solve_batch_merged(gc_graph *const *gs, int32_t n, void *dev_table, size_t dev_bytes,
                        const gc_solve_opts *o, gc_solve_stats *stats, void *stream)
 {
-    gc_batch *b = nullptr;
-    int rc = gc_batch_create(dev_table, dev_bytes, o, &b);
-    if (rc != GC_OK) return rc;
+    const size_t table = gc_batch_footprint_bytes();
+    const int ne = (int)std::max<size_t>(1, std::min<size_t>({(size_t)kBatchEngines, (size_t)n,
+                                                              dev_bytes / table}));
+    hipStream_t st0 = (hipStream_t)stream;
+    std::vector<gc_batch *> eng(ne, nullptr);
+    std::vector<hipStream_t> sts(ne, st0);
+    hipEvent_t start = nullptr, fin = nullptr;
+    int rc = GC_OK;
+    auto cleanup = [&]() {
+        for (int e = 0; e < ne; ++e) {
+            if (eng[e]) gc_batch_destroy(eng[e]);
+            if (e > 0 && sts[e]) (void)hipStreamDestroy(sts[e]);
+        }
+        if (start) (void)hipEventDestroy(start);
+        if (fin) (void)hipEventDestroy(fin);
+    };
+    for (int e = 0; e < ne && rc == GC_OK; ++e)
+        rc = gc_batch_create((char *)dev_table + e * table, table, o, &eng[e]);
+    if (rc == GC_OK && ne > 1) {
+        // the other engines start after what the caller queued on its stream
+        if (!hip_ok(hipEventCreateWithFlags(&start, hipEventDisableTiming)) ||
+            !hip_ok(hipEventRecord(start, st0)))
+            rc = GC_E_HIP;
+        for (int e = 1; e < ne && rc == GC_OK; ++e) {
+            sts[e] = nullptr;
+            if (!hip_ok(hipStreamCreateWithFlags(&sts[e], hipStreamNonBlocking)) ||
+                !hip_ok(hipStreamWaitEvent(sts[e], start, 0)))
+                rc = GC_E_HIP;
+        }
+    }
+    if (rc != GC_OK) { cleanup(); return rc; }
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return node_count(&gs[a]->p) > node_count(&gs[b]->p);
+    });
     const auto t0 = std::chrono::steady_clock::now();
-    int next = 0, done = 0;
+    int next = 0, done = 0, status = GC_OK;
     std::vector<int64_t> tags(kMaxBatch);
-    std::vector<gc_solve_stats> sts(kMaxBatch);
-    int status = GC_OK;
-    while (done < n) {
-        while (next < n && gc_batch_members(b) < kMaxBatch) {
-            if ((rc = gc_batch_add(b, gs[next], next)) != GC_OK) { gc_batch_destroy(b); return rc; }
-            ++next;
-        }
-        int32_t nd = 0;
-        if ((rc = gc_batch_round(b, stream, tags.data(), sts.data(), kMaxBatch, &nd)) != GC_OK) {
-            gc_batch_destroy(b);
-            return rc;
-        }
-        if (nd > 0 && !hip_ok(hipStreamSynchronize((hipStream_t)stream))) { gc_batch_destroy(b); return GC_E_HIP; }
+    std::vector<gc_solve_stats> st_out(kMaxBatch);
+    auto take = [&](int e, int32_t nd) {
         const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         for (int i = 0; i < nd; ++i) {
-            sts[i].done_ms = ms;
-            if (stats) stats[tags[i]] = sts[i];
-            if (sts[i].active_last != 0) status = GC_E_NOT_CONVERGED;
+            st_out[i].done_ms = ms;
+            if (stats) stats[tags[i]] = st_out[i];
+            if (st_out[i].active_last != 0) status = GC_E_NOT_CONVERGED;
         }
         done += nd;
+    };
+    // deal the graphs to the engines in turn (largest first), as far as they hold
+    for (int e = 0; next < n && rc == GC_OK; e = (e + 1) % ne) {
+        bool room = false;
+        for (int f = 0; f < ne; ++f) room = room || gc_batch_members(eng[f]) < kMaxBatch;
+        if (!room) break;
+        if (gc_batch_members(eng[e]) >= kMaxBatch) continue;
+        if ((rc = gc_batch_add(eng[e], gs[order[next]], order[next])) == GC_OK) ++next;
     }
-    gc_batch_destroy(b);
-    return status;
+    for (int e = 0; e < ne && rc == GC_OK; ++e) {
+        int32_t nd = 0;
+        rc = batch_round_launch(eng[e], sts[e], tags.data(), st_out.data(), kMaxBatch, &nd);
+        if (rc == GC_OK) take(e, nd);
+    }
+    // each engine is collected and relaunched in turn, so its next round is
+    // queued as soon as its last one ends while the others keep running
+    while (done < n && rc == GC_OK) {
+        for (int e = 0; e < ne && rc == GC_OK; ++e) {
+            int32_t nd = 0;
+            rc = batch_round_collect(eng[e], sts[e], tags.data(), st_out.data(), kMaxBatch, &nd);
+            if (rc != GC_OK) break;
+            take(e, nd);
+            while (next < n && gc_batch_members(eng[e]) < kMaxBatch) {   // refill
+                if ((rc = gc_batch_add(eng[e], gs[order[next]], order[next])) != GC_OK) break;
+                ++next;
+            }
+            if (rc != GC_OK) break;
+            nd = 0;
+            rc = batch_round_launch(eng[e], sts[e], tags.data(), st_out.data(), kMaxBatch, &nd);
+            if (rc == GC_OK) take(e, nd);
+        }
+    }
+    if (rc == GC_OK && ne > 1) {
+        // the caller's stream sees the other engines' work as done
+        if (!hip_ok(hipEventCreateWithFlags(&fin, hipEventDisableTiming))) rc = GC_E_HIP;
+        for (int e = 1; e < ne && rc == GC_OK; ++e)
+            if (!hip_ok(hipEventRecord(fin, sts[e])) || !hip_ok(hipStreamWaitEvent(st0, fin, 0))) rc = GC_E_HIP;
+        if (rc == GC_OK && !hip_ok(hipStreamSynchronize(st0))) rc = GC_E_HIP;
+    }
+    cleanup();
+    return rc != GC_OK ? rc : status;
 }
 
 // Concurrent lanes: worker threads with their own streams take the graphs,

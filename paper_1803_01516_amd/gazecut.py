@@ -44,6 +44,7 @@ GC_OPT_FIXED_PERIOD = 32
 GC_OPT_BATCH_MERGED = 128
 GC_OPT_LISTS = 256
 GC_BATCH_LANES = 4
+GC_BATCH_ENGINES = 2
 GC_BATCH_MAX_GRAPHS = 256
 GC_STATIC_SCRATCH_BYTES = 96 << 20
 KERNEL_CLASSES = ("push", "relabel", "relax", "other")
@@ -502,8 +503,8 @@ def maxflow_solve_batch(graphs, opts: GcSolveOpts | None = None, stream=None, ta
     n = len(graphs)
     arr = (ctypes.POINTER(GcGraph) * max(1, n))(*[ctypes.pointer(g.handle) for g in graphs])
     merged = opts is not None and bool(opts.flags & GC_OPT_BATCH_MERGED)
-    if table is None and merged:
-        table = torch.empty(batch_footprint_bytes(), dtype=torch.uint8, device="cuda")
+    if table is None and merged:                     # one table per engine
+        table = torch.empty(GC_BATCH_ENGINES * batch_footprint_bytes(), dtype=torch.uint8, device="cuda")
     ptr, size = (table.data_ptr(), table.numel()) if table is not None else (None, 0)
     sts = (GcSolveStats * max(1, n))()
     _check(load().maxflow_solve_batch(arr, n, ctypes.c_void_p(ptr), ctypes.c_size_t(size),

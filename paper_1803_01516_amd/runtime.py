@@ -101,7 +101,7 @@ def autotune(items, tiles=TILE_CANDIDATES, periods=PERIOD_CANDIDATES, sweeps=SWE
     (GC_OPT_BATCH_MERGED: the batch engine; none: concurrent lanes)."""
     import torch
     base = (gc.GC_OPT_SWEEP_GRAPH if use_graph else 0) | extra_flags
-    table = torch.empty(gc.batch_footprint_bytes(), dtype=torch.uint8, device="cuda")
+    table = torch.empty(gc.GC_BATCH_ENGINES * gc.batch_footprint_bytes(), dtype=torch.uint8, device="cuda")
     trials = []
     for tile in tiles:
         for period in periods:
