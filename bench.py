@@ -191,9 +191,8 @@ def bench_batch(args, gc, sg, torch):
                 tune.append(rt.make_item(i, spec, pair))
         t = time.perf_counter()
         best_lanes, trials_l = rt.autotune(tune, stream=stream, use_graph=True)
-        best_eng, trials_e = rt.autotune(tune, tiles=rt.TILE_CANDIDATES, periods=(16, 24, 32, 48),
-                                         sweeps=(0, gc.GC_OPT_SPLIT_SWEEP), stream=stream,
-                                         extra_flags=gc.GC_OPT_BATCH_MERGED)
+        best_eng, trials_e = rt.autotune(tune, tiles=((8, 8, 16), (16, 16, 8)), periods=(24, 32, 48),
+                                         sweeps=(0,), stream=stream, extra_flags=gc.GC_OPT_BATCH_MERGED)
         tune_s = time.perf_counter() - t
         _log(f"batch: autotuned over {len(trials_l) + len(trials_e)} candidates in {tune_s:.1f} s")
         for it in tune:

@@ -420,7 +420,7 @@ int gc_batch_round(gc_batch *b, void *stream, int64_t *done_tags, gc_solve_stats
 #define GC_BATCH_LANES 4
 
 /* Batch engines of maxflow_solve_batch with GC_OPT_BATCH_MERGED. */
-#define GC_BATCH_ENGINES 2
+#define GC_BATCH_ENGINES 3
 
 /* gc_solve_opts.flags, maxflow_solve_batch: run the graphs in rounds of the
  * batch engine (gc_batch_*: every member advances on the device, each step's

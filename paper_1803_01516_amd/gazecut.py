@@ -44,7 +44,7 @@ GC_OPT_FIXED_PERIOD = 32
 GC_OPT_BATCH_MERGED = 128
 GC_OPT_LISTS = 256
 GC_BATCH_LANES = 4
-GC_BATCH_ENGINES = 2
+GC_BATCH_ENGINES = 3
 GC_BATCH_MAX_GRAPHS = 256
 GC_STATIC_SCRATCH_BYTES = 96 << 20
 KERNEL_CLASSES = ("push", "relabel", "relax", "other")
