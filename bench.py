@@ -367,7 +367,8 @@ def bench_serving(args, gc, sg, torch, rate, n_req):
     reqs = rt.poisson_requests(n_req, rate, sg.SERVE_SHAPES, 2, seed=5)
     opts = gc.GcSolveOpts(relabel_period=32)
     _log(f"serving: {len(reqs)} requests at {rate:g}/s")
-    done, wall, srv = rt.serve(reqs, pools, int(args.serve_budget_gb * 1e9), opts)
+    done, wall, srv = rt.serve(reqs, pools, int(args.serve_budget_gb * 1e9), opts,
+                               progress=lambda k, t: _log(f"serving: {k} done at {t:.1f} s"))
     _log(f"serving: done in {wall:.1f} s")
     torch.cuda.empty_cache()
     out = {"workload": f"{len(reqs)} Poisson requests at {rate:g}/s, uniform over "

@@ -1832,7 +1832,10 @@ struct Launcher {
     {
         while (t_events.size() <= i) {
             hipEvent_t e = nullptr;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            // no system-scope fence when the event is recorded: a fenced stop
+            // event writes back and invalidates the L2 at the end of the timed
+            // dispatch, which lengthened it (and slowed the launches after it)
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
             t_events.push_back(e);
         }
         return t_events[i];

@@ -417,21 +417,27 @@ class Server:
 
 
 def serve(requests, pools, budget_bytes, opts=None, lanes=DEFAULT_LANES, lam=1, keep_labels=False,
-          max_wall_s=None):
+          max_wall_s=None, progress=None, progress_every=100):
     """Runs the request stream in real time.  `pools[shape][i]` is the
     (spec, pair) a request names.  Returns (completed requests, wall seconds,
-    server).  With keep_labels the labels are kept as host arrays."""
+    server).  With keep_labels the labels are kept as host arrays.
+    `progress(n_done, seconds)` is called each time another
+    `progress_every` requests have completed."""
     import torch
     srv = Server(budget_bytes, opts, lanes, keep_labels=keep_labels)
     queue = list(requests)
     qi = 0
     waiting = []                                        # arrived, not admitted, in arrival order
     srv.t0 = time.perf_counter()
+    reported = 0
     try:
         while True:
             srv.check()
             with srv.lock:
                 n_done = len(srv.done)
+            if progress is not None and n_done >= reported + progress_every:
+                reported = n_done - n_done % progress_every
+                progress(n_done, srv.clock())
             if n_done == len(queue):
                 break
             now = srv.clock()
