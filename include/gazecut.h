@@ -86,7 +86,8 @@ typedef struct {
     size_t ws_bytes;
     gc_problem p;
     int32_t window_block;     /* 0: full graph; b > 0: thin-skin graph of block size b */
-    int32_t reserved;
+    int32_t compact;          /* thin skin storing only each site's window of levels
+                                 (graph_build_skin); 0 otherwise */
 } gc_graph;
 
 /* Solver options; a zero-filled struct selects the defaults. */
@@ -307,6 +308,25 @@ int coarse_cost_volume(const gc_problem *p, const int32_t *cost, int32_t block,
 int graph_build_window(const gc_problem *p, const int32_t *cost, const int32_t *coarse_labels,
                        int32_t block, void *ws, size_t ws_bytes, gc_graph *g_out, void *stream);
 
+/* The same thin skin, stored compactly: only the window's levels of each
+ * site, min(3b - 1, m - 1) per site (level t of site (x, y) is level
+ * wlo + t of the full graph, wlo the bottom of its window above; stored
+ * levels beyond a clamped window are inert padding), so the second cut's
+ * sweeps, masks and relaxation passes cover the free nodes only.  The arcs
+ * between forced nodes, which every labelling cuts, are summed at the build.
+ * maxflow_solve, extract_labels, approx_level2_cut and graph_warm_start
+ * (as `skin`) accept it, with the same results as for graph_build_window;
+ * gc_graph_state and the batch (gc_batch_add, maxflow_solve_batch with
+ * GC_OPT_BATCH_MERGED) do not (GC_E_ARG).
+ * ws: >= gc_skin_footprint_bytes(p, block), 256-B aligned.
+ * Errors: as graph_build_window; GC_E_ARG also when min(3b - 1, m - 1) > 16. */
+int graph_build_skin(const gc_problem *p, const int32_t *cost, const int32_t *coarse_labels,
+                     int32_t block, void *ws, size_t ws_bytes, gc_graph *g_out, void *stream);
+
+/* Bytes of DEVICE workspace graph_build_skin needs (0 for block < 1 or an
+ * invalid problem). */
+size_t gc_skin_footprint_bytes(const gc_problem *p, int32_t block);
+
 /* Coarse-to-fine warm start of the exact solve (our design next to the
  * hierarchy of Sec. 4.5): seeds a freshly built full graph `g` with the
  * state of a thin-skin graph `skin` of the same problem and data term that
@@ -321,7 +341,7 @@ int graph_build_window(const gc_problem *p, const int32_t *cost, const int32_t *
  * ends in the same maximum flow value and extract_labels in the same minimal
  * minimum cut as from the cold build (the minimal source side is unique).
  * g:    built by graph_build (not a skin) on the same gc_problem;
- * skin: built by graph_build_window and solved; read only;
+ * skin: built by graph_build_window or graph_build_skin and solved; read only;
  * cost: DEVICE int32 [labels][height][width], the data term of both.
  * Waits for the device (one 8-byte read-back).
  * Errors: GC_E_ARG (wrong graph kinds or problems), GC_E_CAP_OVERFLOW (the
@@ -330,7 +350,8 @@ int graph_build_window(const gc_problem *p, const int32_t *cost, const int32_t *
 int graph_warm_start(gc_graph *g, const gc_graph *skin, const int32_t *cost, void *stream);
 
 /* Level-2 approximation (Sec. 4.5) on a thin-skin graph from
- * graph_build_window (block size b = skin->window_block, 1 <= b <= 4): the
+ * graph_build_window or graph_build_skin (block size b = skin->window_block,
+ * 1 <= b <= 4): the
  * wave-front pre-phase covers the whole skin and the push-relabel loop cuts
  * every block separately.  Readings (the paper omits the details):
  *   - the wave front is an initialisation (exact residual distances to the

@@ -57,6 +57,7 @@ namespace {
 
 constexpr int32_t kInf = 1 << 30;
 constexpr int kBlock = 256;
+constexpr int kSkinMaxLevels = 16;      // levels per site of a compact thin skin (3b - 1, b <= 5)
 constexpr int kMaxFlags = 16;
 
 // Arc directions (bit index in the residual masks) and their offsets
@@ -141,9 +142,21 @@ struct Graph {
     int64_t plane, N;
     int32_t te, ts, ie, is;   // pair totals: 2*pen_h, 2*pen_v, inh_h, inh_v
     int32_t win;              // thin-skin graph (levels outside per-site windows are inert)
+    int32_t cw;               // compact thin skin: level t of site (x, y) is level wlo + t, and
+                              // only the window's levels are stored (J of them per site)
+    int32_t Jf;               // levels of the full graph (m - 1)
 };
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Levels stored per site: m - 1 for a full graph (or a thin skin in the full
+// layout), the window's 3b - 1 (at most m - 1) for a compact thin skin of
+// block size b.
+int64_t stored_levels(const gc_problem *p, int compact_block)
+{
+    const int64_t J = p->labels > 0 ? p->labels - 1 : 0;
+    return compact_block > 0 ? std::min<int64_t>(J, 3 * (int64_t)compact_block - 1) : J;
+}
 
 // Activity flags cover 64-node groups, the nodes of one wavefront of a
 // block, so that each wavefront decides, clears and sets its own flags with
@@ -159,16 +172,16 @@ bool hip_ok(hipError_t e)
     return true;
 }
 
-int64_t node_count(const gc_problem *p)
+int64_t node_count(const gc_problem *p, int compact_block = 0)
 {
-    return (int64_t)p->width * p->height * (p->labels > 0 ? p->labels - 1 : 0);
+    return (int64_t)p->width * p->height * stored_levels(p, compact_block);
 }
 
 // Relaxation tiles are at least 8 x 4 x 4 nodes, which bounds the tile count.
 constexpr int kMinTileW = 8, kMinTileH = 4, kMinTileJ = 4;
-size_t max_tiles(const gc_problem *p)
+size_t max_tiles(const gc_problem *p, int compact_block = 0)
 {
-    const int64_t J = p->labels > 0 ? p->labels - 1 : 0;
+    const int64_t J = stored_levels(p, compact_block);
     return (size_t)(((int64_t)p->width + kMinTileW - 1) / kMinTileW) *
            (size_t)(((int64_t)p->height + kMinTileH - 1) / kMinTileH) *
            (size_t)((J + kMinTileJ - 1) / kMinTileJ);
@@ -179,7 +192,8 @@ Graph view(const gc_graph *g)
     const gc_problem &p = g->p;
     Graph s;
     memset(&s, 0, sizeof(s));                  // padding too: views are compared bytewise
-    s.W = p.width; s.H = p.height; s.J = p.labels - 1;
+    const int cb = g->compact ? g->window_block : 0;
+    s.W = p.width; s.H = p.height; s.J = (int32_t)stored_levels(&p, cb); s.Jf = p.labels - 1;
     s.plane = (int64_t)s.W * s.H;
     s.N = s.plane * s.J;
     char *b = (char *)g->ws;
@@ -193,12 +207,13 @@ Graph view(const gc_graph *g)
     s.whi = (GDEV int32_t *)b; b += align256((size_t)s.plane * 4);
     s.bact = (GDEV uint8_t *)b; b += align256(flag_bytes(s.N));
     s.binf = (GDEV uint8_t *)b; b += align256(flag_bytes(s.N));
-    s.stamps = (GDEV int32_t *)b; b += align256(max_tiles(&p) * 4);
+    s.stamps = (GDEV int32_t *)b; b += align256(max_tiles(&p, cb) * 4);
     s.blist = (GDEV int32_t *)b; b += align256((size_t)((s.N + kBlock - 1) / kBlock) * 4);
     s.tlist = (GDEV int32_t *)b;
     s.te = 2 * p.penalty_h; s.ts = 2 * p.penalty_v;
     s.ie = p.inhibit_h; s.is = p.inhibit_v;
     s.win = g->window_block > 0 ? 1 : 0;
+    s.cw = cb > 0 ? 1 : 0;
     return s;
 }
 
@@ -453,7 +468,7 @@ __device__ inline int node_class(int k, int lo, int hi) { return k <= lo ? FSRC 
 __device__ inline unsigned arc_exists(const Graph &s, int j, int y, int x)
 {
     const bool hE = x + 1 < s.W, hW = x > 0, hS = y + 1 < s.H, hN = y > 0;
-    const bool hU = j > 0, hD = j + 1 < s.J;
+    const bool hU = j > 0, hD = j + 1 < s.Jf;
     return (unsigned)hD << D_DOWN | (unsigned)hU << D_UP | (unsigned)hE << D_E |
            (unsigned)hW << D_W | (unsigned)hS << D_S | (unsigned)hN << D_N |
            (unsigned)(hE && hU) << D_EM | (unsigned)(hE && hD) << D_EP |
@@ -531,6 +546,90 @@ __device__ inline int32_t load_word(const Graph &s, int64_t n, int d, bool ok)
 __device__ inline int32_t load_height(const Graph &s, int64_t n, int d, bool ok)
 {
     return s.ht[ok ? nbr(s, n, d) : n];
+}
+
+// The array holding the pair word of arc direction d: the node's own entry
+// for the forward directions, the neighbour's for the others.
+__device__ inline int32_t *word_array(const Graph &s, int d)
+{
+    switch (d) {
+    case D_DOWN: case D_UP: return s.rd;
+    case D_E: case D_W:     return s.re;
+    case D_S: case D_N:     return s.rs;
+    case D_EM: case D_WP:   return s.rem;
+    case D_EP: case D_WM:   return s.rep;
+    case D_SM: case D_NP:   return s.rsm;
+    default:                return s.rsp;          // D_SP, D_NM
+    }
+}
+
+// Arc topology of a node, for the kernels shared by full graphs and compact
+// thin skins.  ex: the node's existing arcs; nb: the neighbour's index;
+// wp: the arc's pair word.
+//
+// Full graph (or a skin in the full layout): the 14 lattice arcs.
+struct FullTopo {
+    unsigned ex;
+    __device__ FullTopo(const Graph &s, int64_t, int j, int y, int x) : ex(arc_exists(s, j, y, x)) {}
+    __device__ int64_t nb(const Graph &s, int64_t n, int d) const { return nbr(s, n, d); }
+    __device__ int32_t *wp(const Graph &s, int64_t n, int d) const { return word_ptr(s, n, d); }
+};
+
+// Compact thin skin: stored level t of site (x, y) is level wlo + t, for
+// t < whi - wlo (higher stored levels are padding, with no arcs).  A
+// neighbour across a site boundary at level offset dj therefore sits
+// dj + wlo(own) - wlo(other) stored levels away, and the arc exists only when
+// that level is inside the other site's window; arcs to levels outside it
+// (forced nodes) were folded into the node's excess when the skin was built.
+struct SkinTopo {
+    unsigned ex;
+    int dl[4];                  // wlo(own) - wlo(E, W, S, N)
+    __device__ SkinTopo(const Graph &s, int64_t, int t, int y, int x)
+    {
+        const int64_t site = (int64_t)y * s.W + x;
+        const int lo = s.wlo[site], len = s.whi[site] - lo;
+        ex = 0;
+        dl[0] = dl[1] = dl[2] = dl[3] = 0;
+        if (t >= len) return;                              // padding level
+        unsigned m = (t + 1 < len ? 1u << D_DOWN : 0u) | (t > 0 ? 1u << D_UP : 0u);
+        auto side = [&](bool in, int64_t other, int i, int d0, int dm, int dp) {
+            if (!in) return;
+            const int lo2 = s.wlo[other], len2 = s.whi[other] - lo2;
+            const int tt = t + lo - lo2;                    // same level at the other site
+            dl[i] = lo - lo2;
+            m |= (tt >= 0 && tt < len2 ? 1u << d0 : 0u) | (tt >= 1 && tt - 1 < len2 ? 1u << dm : 0u) |
+                 (tt + 1 >= 0 && tt + 1 < len2 ? 1u << dp : 0u);
+        };
+        side(x + 1 < s.W, site + 1, 0, D_E, D_EM, D_EP);
+        side(x > 0, site - 1, 1, D_W, D_WM, D_WP);
+        side(y + 1 < s.H, site + s.W, 2, D_S, D_SM, D_SP);
+        side(y > 0, site - s.W, 3, D_N, D_NM, D_NP);
+        ex = m;
+    }
+    __device__ int shift(int d) const
+    {
+        return dir_dx(d) > 0 ? dl[0] : dir_dx(d) < 0 ? dl[1] : dir_dy(d) > 0 ? dl[2] : dir_dy(d) < 0 ? dl[3] : 0;
+    }
+    __device__ int64_t nb(const Graph &s, int64_t n, int d) const
+    {
+        return n + (dir_dj(d) + shift(d)) * s.plane + dir_dy(d) * (int64_t)s.W + dir_dx(d);
+    }
+    __device__ int32_t *wp(const Graph &s, int64_t n, int d) const
+    {
+        return word_array(s, d) + (word_is_forward(d) ? n : nb(s, n, d));
+    }
+};
+
+template <class T>
+__device__ inline int32_t load_word(const Graph &s, const T &tp, int64_t n, int d, bool ok)
+{
+    return *(ok ? tp.wp(s, n, d) : s.ht + n);
+}
+
+template <class T>
+__device__ inline int32_t load_height(const Graph &s, const T &tp, int64_t n, int d, bool ok)
+{
+    return s.ht[ok ? tp.nb(s, n, d) : n];
 }
 
 // Capacities of the arc from node (j, site) to its neighbour in direction d
@@ -656,6 +755,103 @@ k_build(Graph s, const int32_t *__restrict__ cost, int m, int cap)
     }
 }
 
+// Compact thin-skin initialisation: one thread per stored node.  A free
+// level gets what k_build<true> gives it (terminal arcs and arcs to forced
+// nodes folded into its overflow, forced neighbours absent); a padding level
+// is inert.  The data terms the skin reads (layers j and j + 1 of each free
+// level j) are checked against [0, cap].
+__global__ void __launch_bounds__(kBlock)
+k_build_skin(Graph s, const int32_t *__restrict__ cost, int m, int cap)
+{
+    const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    long long tsum = 0;
+    if (n < s.N) {
+        int t, y, x;
+        decode(s, n, t, y, x);
+        const int64_t site = (int64_t)y * s.W + x;
+        const int lo = s.wlo[site], hi = s.whi[site];
+        int32_t *const words[7] = {s.rd, s.re, s.rs, s.rem, s.rep, s.rsm, s.rsp};
+        if (t >= hi - lo) {
+            s.ex[n] = 0;
+            s.ht[n] = kInf;
+            s.ein[n] = 0;
+#pragma unroll
+            for (int i = 0; i < 7; ++i) words[i][n] = 0;
+        } else {
+            const int j = lo + t, k = j + 1;
+            const int32_t ca = cost[(int64_t)j * s.plane + site], cb = cost[(int64_t)k * s.plane + site];
+            if (ca < 0 || ca > cap || cb < 0 || cb > cap) atomicOr(&s.hdr->prefix_err, kCostErr);
+            const unsigned ex_mask = arc_exists(s, j, y, x);
+            const int ph = s.te / 2, pv = s.ts / 2;
+            int32_t e = 0;
+#pragma unroll
+            for (int i = 0; i < 7; ++i) words[i][n] = 0;
+#pragma unroll
+            for (int d = 0; d < 14; ++d) {
+                if (!((ex_mask >> d) & 1u)) continue;
+                const int dx = dir_dx(d), dy = dir_dy(d);
+                const int64_t psite = site + dy * (int64_t)s.W + dx;
+                const int cp = (dx == 0 && dy == 0) ? node_class(k + dir_dj(d), lo, hi)
+                                                    : node_class(k + dir_dj(d), s.wlo[psite], s.whi[psite]);
+                int32_t cout, cin;
+                arc_caps(s, cost, d, site, j, ph, pv, cout, cin);
+                if (cp == FSRC) e += cin;
+                else if (cp == FSNK) { e -= cout; tsum += cout; }
+                if (word_is_forward(d))
+                    word_array(s, d)[n] = cp == FREE ? cout : cp == FSRC ? cout + cin : 0;
+            }
+            if (j == 0) e += cost[site];                                      // from s
+            if (j + 1 == s.Jf) {                                              // into t
+                const int32_t gt = cost[(int64_t)(m - 1) * s.plane + site];
+                e -= gt;
+                tsum += gt;
+            }
+            s.ex[n] = e;
+            s.ht[n] = 0;
+            s.ein[n] = 0;
+        }
+    }
+    tsum = block_sum(tsum);
+    if (threadIdx.x == 0 && tsum)
+        atomicAdd((unsigned long long *)&my_slot(s.slots, blockIdx.x).tcap, (unsigned long long)tsum);
+}
+
+// Capacity of the arcs from forced-source to forced-sink nodes of a compact
+// skin, which stores neither: one thread per site sums, for each arc
+// direction to a neighbouring site, the levels k <= wlo(own) whose partner
+// level k + dj lies above the neighbour's window (k + dj > whi), times the
+// arc's capacity (constant along the column for lateral arcs; within a
+// column no such arc exists, the window holding at least one level).
+__global__ void __launch_bounds__(kBlock)
+k_skin_c0(Graph s, int m)
+{
+    const int64_t site = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    long long c0 = 0;
+    if (site < s.plane) {
+        const int y = (int)(site / s.W), x = (int)(site - (int64_t)y * s.W);
+        const int lo = s.wlo[site];
+        const int ph = s.te / 2, pv = s.ts / 2;
+#pragma unroll
+        for (int d = D_E; d < 14; ++d) {
+            const int dx = dir_dx(d), dy = dir_dy(d), dj = dir_dj(d);
+            const int nx = x + dx, ny = y + dy;
+            if (nx < 0 || nx >= s.W || ny < 0 || ny >= s.H) continue;
+            int32_t cout, cin;
+            arc_caps(s, nullptr, d, site, 0, ph, pv, cout, cin);
+            if (cout == 0) continue;
+            const int hi2 = s.whi[(int64_t)ny * s.W + nx];
+            int a = 1 > 1 - dj ? 1 : 1 - dj;                 // k and k + dj are levels 1 .. m-1
+            a = a > hi2 + 1 - dj ? a : hi2 + 1 - dj;         // k + dj > whi(other)
+            int z = lo < m - 1 ? lo : m - 1;                 // k <= wlo(own)
+            z = z < m - 1 - dj ? z : m - 1 - dj;
+            if (z >= a) c0 += (long long)cout * (z - a + 1);
+        }
+    }
+    c0 = block_sum(c0);
+    if (threadIdx.x == 0 && c0)
+        atomicAdd((unsigned long long *)&my_slot(s.slots, blockIdx.x).c0, (unsigned long long)c0);
+}
+
 // Thin-skin windows from the delegate-point labels (Sec. 4.5): the labels of
 // the coarse group and of the groups directly above and below.
 __global__ void __launch_bounds__(kBlock)
@@ -700,6 +896,7 @@ k_coarse_cost(const int32_t *__restrict__ cost, int W, int H, int m, int b,
 // words are loaded next (a second round of memory latency that saves most
 // word loads).  Pushes then run in registers and write the new words
 // directly.
+template <class T = FullTopo>
 __device__ inline void push_blk(const Graph &s, int64_t lb)
 {
     const int64_t g = group_of(lb);
@@ -713,26 +910,27 @@ __device__ inline void push_blk(const Graph &s, int64_t lb)
             vis = 1;
             int j, y, x;
             decode(s, n, j, y, x);
-            const unsigned ex_mask = arc_exists(s, j, y, x);
+            const T tp(s, n, j, y, x);
+            const unsigned ex_mask = tp.ex;
             unsigned cand = 0;                // existing arcs to height h - 1
 #pragma unroll
             for (int d = 0; d < 14; ++d) {
                 const bool ok = (ex_mask >> d) & 1u;
-                const int32_t hv = ok ? s.ht[nbr(s, n, d)] : kInf;
+                const int32_t hv = ok ? s.ht[tp.nb(s, n, d)] : kInf;
                 cand |= (hv == h - 1 ? 1u : 0u) << d;
             }
             int32_t w[14];
 #pragma unroll
             for (int d = 0; d < 14; ++d)
-                w[d] = ((cand >> d) & 1u) ? *word_ptr(s, n, d) : 0;
+                w[d] = ((cand >> d) & 1u) ? *tp.wp(s, n, d) : 0;
 #pragma unroll
             for (int d = 0; d < 14; ++d) {
                 if (!((cand >> d) & 1u)) continue;
                 const int32_t r = res_from_word(s, d, w[d]);
                 if (e > 0 && r > 0) {
                     const int32_t delta = e < r ? e : r;
-                    *word_ptr(s, n, d) = word_is_forward(d) ? w[d] - delta : w[d] + delta;
-                    const int64_t v = nbr(s, n, d);
+                    *tp.wp(s, n, d) = word_is_forward(d) ? w[d] - delta : w[d] + delta;
+                    const int64_t v = tp.nb(s, n, d);
                     atomicAdd(&s.ein[v], delta);
                     s.binf[v / kGroup] = 1;
                     e -= delta;
@@ -748,15 +946,16 @@ __device__ inline void push_blk(const Graph &s, int64_t lb)
     if (lane0() && vis) atomicAdd(&my_slot(s.slots, g).visits, (unsigned long long)vis);
 }
 
-template <class Src>
+template <class Src, class T = FullTopo>
 __global__ void __launch_bounds__(kBlock)
 k_push(Src src)
 {
-    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { push_blk(s, lb); });
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { push_blk<T>(s, lb); });
 }
 
 // Relabel sweep: merges the inflow of the push sweep, then lifts every
 // active node to one above its lowest residual neighbour.
+template <class T = FullTopo>
 __device__ inline void relabel_blk(const Graph &s, int64_t lb)
 {
     // Loads that do not depend on each other are written before the first
@@ -774,13 +973,14 @@ __device__ inline void relabel_blk(const Graph &s, int64_t lb)
         if (e > 0 && h < kInf) {
             int j, y, x;
             decode(s, n, j, y, x);
-            const unsigned ex_mask = arc_exists(s, j, y, x);
+            const T tp(s, n, j, y, x);
+            const unsigned ex_mask = tp.ex;
             int32_t w[14], hv[14];
 #pragma unroll
             for (int d = 0; d < 14; ++d) {
                 const bool ok = (ex_mask >> d) & 1u;
-                w[d] = load_word(s, n, d, ok);
-                hv[d] = load_height(s, n, d, ok);
+                w[d] = load_word(s, tp, n, d, ok);
+                hv[d] = load_height(s, tp, n, d, ok);
             }
             int32_t hmin = kInf;
 #pragma unroll
@@ -803,11 +1003,11 @@ __device__ inline void relabel_blk(const Graph &s, int64_t lb)
     }
 }
 
-template <class Src>
+template <class Src, class T = FullTopo>
 __global__ void __launch_bounds__(kBlock)
 k_relabel(Src src)
 {
-    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { relabel_blk(s, lb); });
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { relabel_blk<T>(s, lb); });
 }
 
 // Fused sweep: one kernel per push-relabel step.  Every node of a 64-node
@@ -820,6 +1020,7 @@ k_relabel(Src src)
 // word every residual stays within [0, pair total] whatever the order.  The
 // labelling may lose validity between global relabels; only the exact global
 // relabel decides termination, so the final state is the same max preflow.
+template <class T = FullTopo>
 __device__ inline void sweep_blk(const Graph &s, int64_t lb)
 {
     const int64_t g = group_of(lb);
@@ -843,13 +1044,14 @@ __device__ inline void sweep_blk(const Graph &s, int64_t lb)
             vis = 1;
             int j, y, x;
             decode(s, n, j, y, x);
-            const unsigned ex_mask = arc_exists(s, j, y, x);
+            const T tp(s, n, j, y, x);
+            const unsigned ex_mask = tp.ex;
             int32_t r[14], hv[14];
 #pragma unroll
             for (int d = 0; d < 14; ++d) {
                 const bool ok = (ex_mask >> d) & 1u;
-                r[d] = load_word(s, n, d, ok);
-                hv[d] = load_height(s, n, d, ok);
+                r[d] = load_word(s, tp, n, d, ok);
+                hv[d] = load_height(s, tp, n, d, ok);
             }
 #pragma unroll
             for (int d = 0; d < 14; ++d) {       // after all loads are issued
@@ -869,8 +1071,8 @@ __device__ inline void sweep_blk(const Graph &s, int64_t lb)
             for (int d = 0; d < 14; ++d) {
                 if (e > 0 && r[d] > 0 && hv[d] < h) {
                     const int32_t delta = e < r[d] ? e : r[d];
-                    atomicAdd(word_ptr(s, n, d), word_is_forward(d) ? -delta : delta);
-                    const int64_t v = nbr(s, n, d);
+                    atomicAdd(tp.wp(s, n, d), word_is_forward(d) ? -delta : delta);
+                    const int64_t v = tp.nb(s, n, d);
                     atomicAdd(&s.ein[v], delta);
                     s.binf[v / kGroup] = 1;
                     e -= delta;
@@ -891,11 +1093,11 @@ __device__ inline void sweep_blk(const Graph &s, int64_t lb)
     }
 }
 
-template <class Src>
+template <class Src, class T = FullTopo>
 __global__ void __launch_bounds__(kBlock)
 k_sweep(Src src)
 {
-    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { sweep_blk(s, lb); });
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { sweep_blk<T>(s, lb); });
 }
 
 // Merges the inflow left by the last fused sweep into the excess.  Every
@@ -975,17 +1177,19 @@ __device__ inline bool is_frozen(const Graph &s, int j, int y, int x)
 // mode 0: out-arc mask (distance to deficits); mode 1: in-arc mask
 // (reachability from excess).  Forced nodes of a thin-skin graph get no
 // arcs, so relaxation never gives them a finite value.
+template <class T = FullTopo>
 __device__ inline void mask_blk(const Graph &s, int64_t lb, int mode)
 {
     int64_t n = lb * kBlock + threadIdx.x;
     if (n >= s.N) return;
     int j, y, x;
     decode(s, n, j, y, x);
-    if (s.win && is_frozen(s, j, y, x)) { s.mask[n] = 0; return; }
-    const unsigned ex_mask = arc_exists(s, j, y, x);
+    if (s.win && !s.cw && is_frozen(s, j, y, x)) { s.mask[n] = 0; return; }
+    const T tp(s, n, j, y, x);
+    const unsigned ex_mask = tp.ex;
     int32_t w[14];
 #pragma unroll
-    for (int d = 0; d < 14; ++d) w[d] = load_word(s, n, d, (ex_mask >> d) & 1u);
+    for (int d = 0; d < 14; ++d) w[d] = load_word(s, tp, n, d, (ex_mask >> d) & 1u);
     unsigned mk = 0;
 #pragma unroll
     for (int d = 0; d < 14; ++d) {
@@ -995,11 +1199,11 @@ __device__ inline void mask_blk(const Graph &s, int64_t lb, int mode)
     s.mask[n] = (uint16_t)mk;
 }
 
-template <class Src>
+template <class Src, class T = FullTopo>
 __global__ void __launch_bounds__(kBlock)
 k_mask(Src src, int mode)
 {
-    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { mask_blk(s, lb, mode); });
+    for_blocks(src, 0, [&](const Graph &s, int64_t lb) { mask_blk<T>(s, lb, mode); });
 }
 
 // Seeds: mode 0 -> ht = 1 at deficit nodes, INF elsewhere;
@@ -1009,7 +1213,7 @@ __device__ inline void seed_blk(const Graph &s, int64_t lb, int mode)
     int64_t n = lb * kBlock + threadIdx.x;
     if (n >= s.N) return;
     int32_t e = s.ex[n];
-    if (s.win) {
+    if (s.win && !s.cw) {                     // (a compact skin stores free levels only)
         int j, y, x;
         decode(s, n, j, y, x);
         if (is_frozen(s, j, y, x)) e = 0;          // inert: never a seed
@@ -1192,6 +1396,127 @@ __device__ inline void relax_blk(const Graph &s, int64_t lb, int mode, int max_r
     }
 }
 
+// The relaxation pass of a compact thin skin: a tile holds 16 x 16 sites
+// with all their stored levels (at most TJ), so every arc between two of its
+// sites stays inside the tile whatever the windows' offsets; the LDS
+// neighbour of a node across a site boundary is dj + wlo(own) - wlo(other)
+// levels away.  Thread t owns the column of site t, whose levels it takes in
+// the order values travel.  Change stamps, flags and rounds as relax_blk.
+constexpr int kSkinTile = 16;
+
+template <int TJ>
+__global__ void __launch_bounds__(kBlock)
+k_relax_skin(Graph s, int mode, int max_rounds, int pass)
+{
+    static_assert(kSkinTile * kSkinTile == kBlock, "one column per thread");
+    constexpr int HW = kSkinTile + 2, HS = HW * HW, NH = HS * TJ;
+    __shared__ int32_t sv[NH];
+    __shared__ uint16_t smk[kBlock * TJ];
+    __shared__ int32_t slo[HS];
+    int32_t *__restrict__ val = mode == 0 ? s.ht : s.aux;
+    const int step = mode == 0 ? 1 : 0;
+    int32_t *flags = s.hdr->flags;
+    int32_t *__restrict__ stamps = s.stamps;
+    const int ntx = (s.W + kSkinTile - 1) / kSkinTile, nty = (s.H + kSkinTile - 1) / kSkinTile;
+    const int tid = threadIdx.x;
+    if (pass > 1 && flags[(pass - 1) % kMaxFlags] == 0) return;     // converged already
+    const int tile = blockIdx.x;
+    const int bx = tile % ntx, by = tile / ntx;
+    int changed = pass == 1;
+    if (pass > 1 && tid < 9) {
+        const int ty = by + tid / 3 - 1, tx = bx + tid % 3 - 1;
+        if (ty >= 0 && ty < nty && tx >= 0 && tx < ntx) changed = (stamps[ty * ntx + tx] >> 1) == pass - 1;
+    }
+    if (!__syncthreads_or(changed)) return;
+    const int x0 = bx * kSkinTile, y0 = by * kSkinTile;
+
+    constexpr int NHT = (NH + kBlock - 1) / kBlock;
+    int32_t hv[NHT];
+    bool hin[NHT];
+#pragma unroll
+    for (int k = 0; k < NHT; ++k) {
+        const int i = tid + k * kBlock;
+        const int lx = i % HW, ly = (i / HW) % HW, t = i / HS;
+        const int gx = x0 + lx - 1, gy = y0 + ly - 1;
+        hin[k] = i < NH && gx >= 0 && gx < s.W && gy >= 0 && gy < s.H && t < s.J;
+        hv[k] = val[hin[k] ? (int64_t)t * s.plane + (int64_t)gy * s.W + gx : 0];
+    }
+    for (int i = tid; i < HS; i += kBlock) {
+        const int gx = x0 + i % HW - 1, gy = y0 + i / HW - 1;
+        slo[i] = (gx >= 0 && gx < s.W && gy >= 0 && gy < s.H) ? s.wlo[(int64_t)gy * s.W + gx] : 0;
+    }
+    const int cx = tid % kSkinTile, cy = tid / kSkinTile;       // this thread's site
+    const int gx = x0 + cx, gy = y0 + cy;
+    const bool site_in = gx < s.W && gy < s.H;
+    uint16_t mv[TJ];
+#pragma unroll
+    for (int t = 0; t < TJ; ++t)
+        mv[t] = s.mask[(site_in && t < s.J) ? (int64_t)t * s.plane + (int64_t)gy * s.W + gx : 0];
+#pragma unroll
+    for (int k = 0; k < NHT; ++k) {
+        const int i = tid + k * kBlock;
+        if (i < NH) sv[i] = hin[k] ? hv[k] : kInf;
+    }
+#pragma unroll
+    for (int t = 0; t < TJ; ++t) smk[t * kBlock + tid] = (site_in && t < s.J) ? mv[t] : (uint16_t)0;
+    __syncthreads();
+    // LDS offsets of the 14 neighbours of this thread's nodes
+    const int own = (cy + 1) * HW + (cx + 1);
+    int off[14];
+#pragma unroll
+    for (int d = 0; d < 14; ++d) {
+        const int other = own + dir_dy(d) * HW + dir_dx(d);
+        off[d] = (dir_dj(d) + slo[own] - slo[other]) * HS + dir_dy(d) * HW + dir_dx(d);
+    }
+    int32_t orig[TJ];
+#pragma unroll
+    for (int t = 0; t < TJ; ++t) orig[t] = sv[t * HS + own];
+
+    bool capped = true;
+    for (int round = 0; round < max_rounds; ++round) {
+        bool ch = false;
+        const bool upward = ((round & 1) == 0) == (mode == 0);
+#pragma unroll
+        for (int k = 0; k < TJ; ++k) {
+            const int t = upward ? TJ - 1 - k : k;
+            const unsigned m = smk[t * kBlock + tid];
+            if (!m) continue;
+            const int hi = t * HS + own;
+            const int32_t c = sv[hi];
+            int32_t best = c;
+#pragma unroll
+            for (int d = 0; d < 14; ++d)
+                if ((m >> d) & 1u) {
+                    const int32_t nv = sv[hi + off[d]] + step;
+                    best = nv < best ? nv : best;
+                }
+            if (best < c) {
+                sv[hi] = best;
+                ch = true;
+            }
+        }
+        if (!__syncthreads_or(ch)) { capped = false; break; }
+    }
+    bool wrote = false;
+#pragma unroll
+    for (int t = 0; t < TJ; ++t) {
+        const int32_t v = sv[t * HS + own];
+        if (v != orig[t]) {
+            val[(int64_t)t * s.plane + (int64_t)gy * s.W + gx] = v;
+            wrote = true;
+        }
+    }
+    const bool any_wrote = __syncthreads_or(wrote);
+    if (tid == 0) {
+        if (any_wrote || capped) {
+            stamps[tile] = (pass << 1) | (capped ? 1 : 0);
+            flags[pass % kMaxFlags] = 1;
+        } else if (pass == 1) {
+            stamps[tile] = 0;
+        }
+    }
+}
+
 template <int TW, int TH, int TJ, class Src>
 __global__ void __launch_bounds__(kBlock)
 k_relax(Src src, int mode, int max_rounds, int pass)
@@ -1277,7 +1602,7 @@ k_labels(Graph s, int32_t *__restrict__ labels, int from_aux)
     int X = lo;
     bool gap = false, bad = false;
     for (int j = lo; j < hi; ++j) {
-        const int64_t n = (int64_t)j * s.plane + site;
+        const int64_t n = (int64_t)(s.cw ? j - lo : j) * s.plane + site;
         bool in = from_aux ? s.aux[n] == 0 : s.ht[n] >= kInf;
         if (in) { if (gap) bad = true; ++X; }
         else gap = true;
@@ -1400,7 +1725,7 @@ k_wave(Src src)
         const int lo = s.win ? s.wlo[site] : 0, hi = s.win ? s.whi[site] : s.J;
         int32_t carry = 0;
         for (int k = lo + 1; k <= hi; ++k) {
-            const int64_t n = (int64_t)(k - 1) * s.plane + site;
+            const int64_t n = (int64_t)(s.cw ? k - 1 - lo : k - 1) * s.plane + site;
             const int32_t e0 = s.ex[n];
             int32_t e = e0 + carry;
             carry = 0;
@@ -1429,6 +1754,7 @@ k_wave(Src src)
 // pair word has one writer; inflow is summed into ein (integer atomics,
 // order-free), so the step's result does not depend on the schedule.
 // Forced levels of the skin have infinite height and are never admissible.
+template <class T>
 __global__ void __launch_bounds__(kBlock)
 k_wave_push(Graph s, const int32_t *__restrict__ hc)
 {
@@ -1439,22 +1765,23 @@ k_wave_push(Graph s, const int32_t *__restrict__ hc)
     if (e <= 0 || h >= kInf) return;
     int j, y, x;
     decode(s, n, j, y, x);
-    const unsigned ex_mask = arc_exists(s, j, y, x);
+    const T tp(s, n, j, y, x);
+    const unsigned ex_mask = tp.ex;
     int32_t hv[14];
 #pragma unroll
     for (int d = 0; d < 14; ++d) {
         const bool ok = (ex_mask >> d) & 1u;
-        hv[d] = ok ? hc[nbr(s, n, d)] : kInf;
+        hv[d] = ok ? hc[tp.nb(s, n, d)] : kInf;
     }
 #pragma unroll
     for (int d = 0; d < 14; ++d) {
         if (e <= 0 || hv[d] != h - 1) continue;
-        const int32_t w = *word_ptr(s, n, d);
+        const int32_t w = *tp.wp(s, n, d);
         const int32_t r = res_from_word(s, d, w);
         if (r <= 0) continue;
         const int32_t delta = e < r ? e : r;
-        *word_ptr(s, n, d) = word_is_forward(d) ? w - delta : w + delta;
-        atomicAdd(&s.ein[nbr(s, n, d)], delta);
+        *tp.wp(s, n, d) = word_is_forward(d) ? w - delta : w + delta;
+        atomicAdd(&s.ein[tp.nb(s, n, d)], delta);
         e -= delta;
     }
     s.ex[n] = e;
@@ -1464,6 +1791,7 @@ k_wave_push(Graph s, const int32_t *__restrict__ hc)
 // holding excess to one above its lowest residual neighbour when that is
 // higher.  Neighbour heights are read from `hc` and the new ones written to
 // `hn` (every node, so `hn` is the whole next height field): a Jacobi step.
+template <class T>
 __global__ void __launch_bounds__(kBlock)
 k_wave_relabel(Graph s, const int32_t *__restrict__ hc, int32_t *__restrict__ hn)
 {
@@ -1479,13 +1807,14 @@ k_wave_relabel(Graph s, const int32_t *__restrict__ hc, int32_t *__restrict__ hn
     if (e > 0 && h < kInf) {
         int j, y, x;
         decode(s, n, j, y, x);
-        const unsigned ex_mask = arc_exists(s, j, y, x);
+        const T tp(s, n, j, y, x);
+        const unsigned ex_mask = tp.ex;
         int32_t w[14], hv[14];
 #pragma unroll
         for (int d = 0; d < 14; ++d) {
             const bool ok = (ex_mask >> d) & 1u;
-            w[d] = load_word(s, n, d, ok);
-            hv[d] = ok ? hc[nbr(s, n, d)] : kInf;
+            w[d] = load_word(s, tp, n, d, ok);
+            hv[d] = ok ? hc[tp.nb(s, n, d)] : kInf;
         }
         int32_t hmin = kInf;
 #pragma unroll
@@ -1518,6 +1847,7 @@ constexpr int kCutMaxRounds = 4096;
 // inflow, Jacobi relabel), n the block's node count.  The block's final
 // excess and the pair words of its inner arcs are written back.
 // Grid: (delegate x, delegate y, group offset 0..2 from the delegate label - 1).
+template <class T>
 __global__ void __launch_bounds__(kCutLanes)
 k_block_cut(Graph s, const int32_t *__restrict__ coarse_labels, int b)
 {
@@ -1533,10 +1863,11 @@ k_block_cut(Graph s, const int32_t *__restrict__ coarse_labels, int b)
     const int x = blockIdx.x * b + lx, y = blockIdx.y * b + ly, k = G * b + lk;
     bool mem = false;
     int64_t n = 0;
-    if (lk < b && x < s.W && y < s.H && k >= 1 && k <= s.J) {
+    if (lk < b && x < s.W && y < s.H && k >= 1 && k <= s.Jf) {
         const int64_t site = (int64_t)y * s.W + x;
-        mem = k > s.wlo[site] && k <= s.whi[site];
-        n = (int64_t)(k - 1) * s.plane + site;
+        const int lo = s.wlo[site];
+        mem = k > lo && k <= s.whi[site];
+        n = (int64_t)(s.cw ? k - 1 - lo : k - 1) * s.plane + site;
     }
     member[l] = mem ? 1 : 0;
     __syncthreads();
@@ -1554,12 +1885,13 @@ k_block_cut(Graph s, const int32_t *__restrict__ coarse_labels, int b)
     if (mem) {
         int j_, y_, x_;
         decode(s, n, j_, y_, x_);
-        const unsigned ex_mask = arc_exists(s, j_, y_, x_);
+        const T tp(s, n, j_, y_, x_);
+        const unsigned ex_mask = tp.ex;
         e[l] = s.ex[n];
 #pragma unroll
         for (int d = 0; d < 14; ++d)
             if (((ex_mask >> d) & 1u) && lnb(d) >= 0)
-                res[l][d] = res_from_word(s, d, *word_ptr(s, n, d));
+                res[l][d] = res_from_word(s, d, *tp.wp(s, n, d));
     }
     __syncthreads();
     int round = 0;
@@ -1632,11 +1964,12 @@ k_block_cut(Graph s, const int32_t *__restrict__ coarse_labels, int b)
         s.ex[n] = e[l];
         int j_, y_, x_;
         decode(s, n, j_, y_, x_);
-        const unsigned ex_mask = arc_exists(s, j_, y_, x_);
+        const T tp(s, n, j_, y_, x_);
+        const unsigned ex_mask = tp.ex;
 #pragma unroll
         for (int d = 0; d < 14; ++d)
             if (word_is_forward(d) && ((ex_mask >> d) & 1u) && lnb(d) >= 0)
-                *word_ptr(s, n, d) = res[l][d];
+                *tp.wp(s, n, d) = res[l][d];
     }
 }
 
@@ -1683,8 +2016,22 @@ RelaxFn<Src> relax_kernel(int tw, int th, int tj)
     return nullptr;
 }
 
+// Kernels by topology: a compact thin skin takes the SkinTopo variants and
+// its own relaxation tiles (16 x 16 sites with all their stored levels).
+inline void (*mask_kernel(const Graph &s))(Graph, int)
+{
+    return s.cw ? k_mask<Graph, SkinTopo> : k_mask<Graph, FullTopo>;
+}
+
+inline RelaxFn<Graph> relax_skin_kernel(int levels)
+{
+    return levels <= 2 ? k_relax_skin<2> : levels <= 5 ? k_relax_skin<5> : levels <= 8 ? k_relax_skin<8>
+         : levels <= 11 ? k_relax_skin<11> : levels <= kSkinMaxLevels ? k_relax_skin<kSkinMaxLevels> : nullptr;
+}
+
 int64_t relax_tiles(const Graph &s, const Opts &o)
 {
+    if (s.cw) return (int64_t)((s.W + kSkinTile - 1) / kSkinTile) * ((s.H + kSkinTile - 1) / kSkinTile);
     return (int64_t)((s.W + o.tw - 1) / o.tw) * ((s.H + o.th - 1) / o.th) * ((s.J + o.tj - 1) / o.tj);
 }
 
@@ -1932,10 +2279,10 @@ int relax_to_fixpoint(const Graph &s, int mode, const Opts &o, Launcher &L, int 
                       bool count_active = false, HeaderRead *out = nullptr, int first_batch = 4)
 {
     const int64_t tiles = relax_tiles(s, o);
-    RelaxFn<Graph> fn = relax_kernel<Graph>(o.tw, o.th, o.tj);
+    RelaxFn<Graph> fn = s.cw ? relax_skin_kernel(s.J) : relax_kernel<Graph>(o.tw, o.th, o.tj);
     RelaxFn<Listed> fnl = relax_kernel<Listed>(o.tw, o.th, o.tj);
     if (!fn || !fnl) return GC_E_ARG;
-    const bool listed = use_lists(o, s.N);
+    const bool listed = use_lists(o, s.N) && !s.cw;
     if (listed) hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, L.st, s.hdr, 3);
     if (tiles <= 0 && !count_active) return GC_OK;
     const int max_passes = 1 << 22;
@@ -2017,14 +2364,14 @@ void launch_period(const Graph &s, int period, bool fused, bool listed, Launcher
         if (fused) {
             if (listed)
                 L.run(GC_K_PUSH, k_sweep<Listed>, dim3(list_grid(grid, resident_grid(k_sweep<Listed>))), list(0));
-            else L.run(GC_K_PUSH, k_sweep<Graph>, dim3(grid), s);
+            else L.run(GC_K_PUSH, s.cw ? k_sweep<Graph, SkinTopo> : k_sweep<Graph, FullTopo>, dim3(grid), s);
         } else if (listed) {
             L.run(GC_K_PUSH, k_push<Listed>, dim3(list_grid(grid, resident_grid(k_push<Listed>))), list(1));
             L.run(GC_K_RELABEL, k_relabel<Listed>, dim3(list_grid(grid, resident_grid(k_relabel<Listed>))),
                   list(0));
         } else {
-            L.run(GC_K_PUSH, k_push<Graph>, dim3(grid), s);
-            L.run(GC_K_RELABEL, k_relabel<Graph>, dim3(grid), s);
+            L.run(GC_K_PUSH, s.cw ? k_push<Graph, SkinTopo> : k_push<Graph, FullTopo>, dim3(grid), s);
+            L.run(GC_K_RELABEL, s.cw ? k_relabel<Graph, SkinTopo> : k_relabel<Graph, FullTopo>, dim3(grid), s);
         }
     }
     if (fused) L.run(GC_K_OTHER, k_merge<Graph>, dim3(grid), s);
@@ -2110,14 +2457,24 @@ GC_API int gc_problem_check(const gc_problem *p)
     return GC_OK;
 }
 
-GC_API size_t gc_graph_footprint_bytes(const gc_problem *p)
+static size_t footprint(const gc_problem *p, int compact_block)
 {
     if (gc_problem_check(p) != GC_OK) return 0;
-    size_t n = (size_t)node_count(p);
+    size_t n = (size_t)node_count(p, compact_block);
     const size_t sites = (size_t)p->width * p->height;
     return align256(sizeof(DevHeader)) + align256(kSlots * sizeof(Slot)) + 11 * align256(n * 4) +
            align256(n * 2) + 2 * align256(sites * 4) + 2 * align256(flag_bytes((int64_t)n)) +
-           2 * align256(max_tiles(p) * 4) + align256((n + kBlock - 1) / kBlock * 4);
+           2 * align256(max_tiles(p, compact_block) * 4) + align256((n + kBlock - 1) / kBlock * 4);
+}
+
+GC_API size_t gc_graph_footprint_bytes(const gc_problem *p)
+{
+    return footprint(p, 0);
+}
+
+GC_API size_t gc_skin_footprint_bytes(const gc_problem *p, int32_t block)
+{
+    return block >= 1 ? footprint(p, block) : 0;
 }
 
 GC_API int stereo_cost_volume(const uint8_t *left, const uint8_t *right, const gc_problem *p,
@@ -2153,17 +2510,17 @@ GC_API int stereo_cost_volume_rgb(const uint8_t *left, const uint8_t *right, con
 }
 
 static int build_common(const gc_problem *p, const int32_t *cost, void *ws, size_t ws_bytes,
-                        gc_graph *g_out, int32_t block)
+                        gc_graph *g_out, int32_t block, bool compact = false)
 {
     int rc = gc_problem_check(p);
     if (rc != GC_OK) return rc;
     if (!cost || !ws || !g_out) return GC_E_ARG;
-    if (((uintptr_t)ws & 255) != 0 || ws_bytes < gc_graph_footprint_bytes(p)) return GC_E_WORKSPACE;
+    if (((uintptr_t)ws & 255) != 0 || ws_bytes < footprint(p, compact ? block : 0)) return GC_E_WORKSPACE;
     g_out->ws = ws;
     g_out->ws_bytes = ws_bytes;
     g_out->p = *p;
     g_out->window_block = block;
-    g_out->reserved = 0;
+    g_out->compact = compact ? 1 : 0;
     return GC_OK;
 }
 
@@ -2243,12 +2600,39 @@ GC_API int graph_build_window(const gc_problem *p, const int32_t *cost,
     return hip_ok(hipGetLastError()) ? GC_OK : GC_E_HIP;
 }
 
+GC_API int graph_build_skin(const gc_problem *p, const int32_t *cost, const int32_t *coarse_labels,
+                            int32_t block, void *ws, size_t ws_bytes, gc_graph *g_out, void *stream)
+{
+    if (block < 1 || !coarse_labels) return GC_E_ARG;
+    gc_problem c;
+    int rc = gc_coarse_problem(p, block, &c);
+    if (rc != GC_OK) return rc;
+    if (stored_levels(p, block) > kSkinMaxLevels) return GC_E_ARG;
+    if ((rc = build_common(p, cost, ws, ws_bytes, g_out, block, true)) != GC_OK) return rc;
+    Graph s = view(g_out);
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, st, s.hdr, 0);
+    hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 0);
+    if (s.plane > 0) {
+        hipLaunchKernelGGL(k_windows, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, coarse_labels,
+                           block, p->labels);
+        hipLaunchKernelGGL(k_skin_c0, dim3(grid_for(s.plane)), dim3(kBlock), 0, st, s, p->labels);
+    }
+    if (s.N > 0)
+        hipLaunchKernelGGL(k_build_skin, dim3(grid_for(s.N)), dim3(kBlock), 0, st, s, cost, p->labels,
+                           p->cap);
+    hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, s.slots, s.hdr, 3, nullptr);
+    return hip_ok(hipGetLastError()) ? GC_OK : GC_E_HIP;
+}
+
 static int graph_check(const gc_graph *g)
 {
     if (!g || !g->ws || g->window_block < 0) return GC_E_ARG;
+    if (g->compact != 0 && (g->compact != 1 || g->window_block < 1)) return GC_E_ARG;
     int rc = gc_problem_check(&g->p);
     if (rc != GC_OK) return rc;
-    if (g->ws_bytes < gc_graph_footprint_bytes(&g->p)) return GC_E_WORKSPACE;
+    if (g->compact && stored_levels(&g->p, g->window_block) > kSkinMaxLevels) return GC_E_ARG;
+    if (g->ws_bytes < footprint(&g->p, g->compact ? g->window_block : 0)) return GC_E_WORKSPACE;
     return GC_OK;
 }
 
@@ -2269,7 +2653,7 @@ static int solve_graph(gc_graph *g, const Opts &opt, gc_solve_stats *stats, hipS
     L.rb = rb;
     const unsigned grid = grid_for(s.N);
     const bool fused = sweep_fused(opt, s.J);
-    const bool listed = use_lists(opt, s.N);
+    const bool listed = use_lists(opt, s.N) && !s.cw;
     const bool use_graph = st != nullptr && (opt.flags & GC_OPT_SWEEP_GRAPH) != 0 && !L.timing;
     int status = GC_OK;
     int batch_hint = 4;
@@ -2278,7 +2662,7 @@ static int solve_graph(gc_graph *g, const Opts &opt, gc_solve_stats *stats, hipS
         // BFS distance to the deficit nodes
         if (wave_in_round(opt, round))
             L.run(GC_K_OTHER, k_wave<Graph>, dim3(grid_for(s.plane)), s);
-        L.run(GC_K_OTHER, k_mask<Graph>, dim3(grid), s, 0);
+        L.run(GC_K_OTHER, mask_kernel(s), dim3(grid), s, 0);
         L.run(GC_K_OTHER, k_seed<Graph>, dim3(grid), s, 0);
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
         // termination count and push total come back with the last flags;
@@ -2344,6 +2728,7 @@ __global__ void k_set_i64(int64_t *p, long long v)
 // forced-sink node gains what it received).  Heights restart at 0: the
 // solve begins with an exact global relabel.  Slots' e0 collects the total
 // positive excess, which bounds every node's excess from then on.
+template <bool kCompact>
 __global__ void __launch_bounds__(kBlock)
 k_warm_start(Graph f, Graph k, const int32_t *__restrict__ cost)
 {
@@ -2354,7 +2739,10 @@ k_warm_start(Graph f, Graph k, const int32_t *__restrict__ cost)
         decode(f, n, j, y, x);
         const int64_t site = (int64_t)y * f.W + x;
         const int kk = j + 1;
-        const int cn = node_class(kk, k.wlo[site], k.whi[site]);
+        const int lo = k.wlo[site];
+        const int cn = node_class(kk, lo, k.whi[site]);
+        // the skin's copy of this node (a compact skin stores free levels only)
+        const int64_t nk = kCompact ? (int64_t)(j - lo) * k.plane + site : n;
         const unsigned ex_mask = arc_exists(f, j, y, x);
         const int ph = f.te / 2, pv = f.ts / 2;
         int32_t e = 0;
@@ -2363,15 +2751,17 @@ k_warm_start(Graph f, Graph k, const int32_t *__restrict__ cost)
             if (!((ex_mask >> d) & 1u)) continue;
             const int64_t psite = site + dir_dy(d) * (int64_t)f.W + dir_dx(d);
             const int cp = node_class(kk + dir_dj(d), k.wlo[psite], k.whi[psite]);
-            if (word_is_forward(d) && (cn == FREE || cp == FREE))
-                *word_ptr(f, n, d) = *word_ptr(k, n, d);
-            if (cn != FREE && cp == FREE) {
-                int32_t cout, cin;
-                arc_caps(f, cost, d, site, j, ph, pv, cout, cin);
-                e += cn == FSRC ? -cout : cin;
+            int32_t cout = 0, cin = 0;
+            if (cn != FREE && cp == FREE) arc_caps(f, cost, d, site, j, ph, pv, cout, cin);
+            if (word_is_forward(d) && (cn == FREE || cp == FREE)) {
+                // a forced node's word towards a free one never changes in the
+                // skin (nothing is pushed into a forced node): its build value
+                *word_ptr(f, n, d) = cn == FREE ? word_array(k, d)[nk]
+                                   : !kCompact ? *word_ptr(k, n, d) : cn == FSNK ? cout + cin : 0;
             }
+            if (cn != FREE && cp == FREE) e += cn == FSRC ? -cout : cin;
         }
-        const int32_t ex = cn == FREE ? k.ex[n] : f.ex[n] + e;
+        const int32_t ex = cn == FREE ? k.ex[nk] : f.ex[n] + e;
         f.ex[n] = ex;
         f.ht[n] = 0;
         f.ein[n] = 0;
@@ -2393,7 +2783,8 @@ GC_API int graph_warm_start(gc_graph *g, const gc_graph *skin, const int32_t *co
     hipStream_t st = (hipStream_t)stream;
     if (f.N == 0) return GC_OK;
     hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, f.slots, 2);
-    hipLaunchKernelGGL(k_warm_start, dim3(grid_for(f.N)), dim3(kBlock), 0, st, f, k, cost);
+    if (k.cw) hipLaunchKernelGGL(k_warm_start<true>, dim3(grid_for(f.N)), dim3(kBlock), 0, st, f, k, cost);
+    else hipLaunchKernelGGL(k_warm_start<false>, dim3(grid_for(f.N)), dim3(kBlock), 0, st, f, k, cost);
     hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, st, f.slots, f.hdr, 4, nullptr);
     // the relaxation flags and activity flags of the fresh build stay valid:
     // the solve's first global relabel recomputes every height, and every
@@ -2425,7 +2816,7 @@ GC_API int approx_level2_cut(gc_graph *skin, const int32_t *cost, const int32_t 
     if (s.N > 0) {
         const unsigned grid = grid_for(s.N);
         // initialisation: exact residual distances to the deficits
-        hipLaunchKernelGGL(k_mask<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 0);
+        hipLaunchKernelGGL(mask_kernel(s), dim3(grid), dim3(kBlock), 0, st, s, 0);
         hipLaunchKernelGGL(k_seed<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 0);
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
         if ((rc = relax_to_fixpoint(s, 0, opt, L, &passes)) != GC_OK) return rc;
@@ -2433,15 +2824,21 @@ GC_API int approx_level2_cut(gc_graph *skin, const int32_t *cost, const int32_t 
         hipLaunchKernelGGL(k_zero_i32, dim3(grid), dim3(kBlock), 0, st, s.ein, s.N);
         int32_t *hc = s.ht, *hn = s.aux;
         for (int t = 0; t < wave_steps; ++t) {
-            hipLaunchKernelGGL(k_wave_push, dim3(grid), dim3(kBlock), 0, st, s, hc);
-            hipLaunchKernelGGL(k_wave_relabel, dim3(grid), dim3(kBlock), 0, st, s, hc, hn);
+            if (s.cw) {
+                hipLaunchKernelGGL(k_wave_push<SkinTopo>, dim3(grid), dim3(kBlock), 0, st, s, hc);
+                hipLaunchKernelGGL(k_wave_relabel<SkinTopo>, dim3(grid), dim3(kBlock), 0, st, s, hc, hn);
+            } else {
+                hipLaunchKernelGGL(k_wave_push<FullTopo>, dim3(grid), dim3(kBlock), 0, st, s, hc);
+                hipLaunchKernelGGL(k_wave_relabel<FullTopo>, dim3(grid), dim3(kBlock), 0, st, s, hc, hn);
+            }
             std::swap(hc, hn);
         }
         // every block's push-relabel loop on its own
         const dim3 bgrid((unsigned)((s.W + b - 1) / b), (unsigned)((s.H + b - 1) / b), 3);
-        hipLaunchKernelGGL(k_block_cut, bgrid, dim3(kCutLanes), 0, st, s, coarse_labels, b);
+        if (s.cw) hipLaunchKernelGGL(k_block_cut<SkinTopo>, bgrid, dim3(kCutLanes), 0, st, s, coarse_labels, b);
+        else hipLaunchKernelGGL(k_block_cut<FullTopo>, bgrid, dim3(kCutLanes), 0, st, s, coarse_labels, b);
         // read-out: distances to the unfilled deficits; unreachable = source side
-        hipLaunchKernelGGL(k_mask<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 0);
+        hipLaunchKernelGGL(mask_kernel(s), dim3(grid), dim3(kBlock), 0, st, s, 0);
         hipLaunchKernelGGL(k_seed<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 0);
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
         if ((rc = relax_to_fixpoint(s, 0, opt, L, &passes)) != GC_OK) return rc;
@@ -2905,6 +3302,7 @@ GC_API int gc_batch_add(gc_batch *b, const gc_graph *g, int64_t tag)
     if (!b) return GC_E_ARG;
     int rc = graph_check(g);
     if (rc != GC_OK) return rc;
+    if (g->compact) return GC_E_ARG;           // the batch kernels take the lattice topology
     if (gc_batch_members(b) >= kMaxBatch) return GC_E_ARG;
     gc_batch::Member m;
     m.g = *g;
@@ -3194,7 +3592,7 @@ GC_API int gc_graph_state(const gc_graph *g, int32_t *excess, int32_t *words, vo
 {
     int rc = graph_check(g);
     if (rc != GC_OK) return rc;
-    if (!excess || !words) return GC_E_ARG;
+    if (!excess || !words || g->compact) return GC_E_ARG;
     const Graph s = view(g);
     if (s.N == 0) return GC_OK;
     hipStream_t st = (hipStream_t)stream;
@@ -3220,7 +3618,7 @@ static int extract_graph(const gc_graph *g, const int32_t *cost, int32_t *labels
     int passes = 0;
     if (s.N > 0) {
         const unsigned grid = grid_for(s.N);
-        hipLaunchKernelGGL(k_mask<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 1);
+        hipLaunchKernelGGL(mask_kernel(s), dim3(grid), dim3(kBlock), 0, st, s, 1);
         hipLaunchKernelGGL(k_seed<Graph>, dim3(grid), dim3(kBlock), 0, st, s, 1);
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
         if ((rc = relax_to_fixpoint(s, 1, opt, L, &passes)) != GC_OK) return rc;

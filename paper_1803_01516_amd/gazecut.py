@@ -25,7 +25,7 @@ class GcProblem(ctypes.Structure):
 
 class GcGraph(ctypes.Structure):
     _fields_ = [("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t), ("p", GcProblem),
-                ("window_block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("window_block", ctypes.c_int32), ("compact", ctypes.c_int32)]
 
 
 class GcSolveOpts(ctypes.Structure):
@@ -74,7 +74,8 @@ EXPORTS = ("gc_status_str", "gc_last_hip_error", "gc_problem_check", "gc_graph_f
            "gc_coarse_problem", "coarse_cost_volume", "graph_build_window", "approx_level2_cut",
            "gc_batch_footprint_bytes", "gc_batch_create", "gc_batch_destroy", "gc_batch_members",
            "gc_batch_add", "gc_batch_round", "maxflow_solve_batch",
-           "gc_solve_pair_static_bytes", "gc_solve_pair_static", "graph_warm_start")
+           "gc_solve_pair_static_bytes", "gc_solve_pair_static", "graph_warm_start",
+           "graph_build_skin", "gc_skin_footprint_bytes")
 
 _lib = None
 
@@ -129,6 +130,11 @@ def load(path: str = LIB_PATH):
     lib.graph_build_window.argtypes = [ctypes.POINTER(GcProblem), P, P, ctypes.c_int32, P,
                                        ctypes.c_size_t, ctypes.POINTER(GcGraph), P]
     lib.graph_build_window.restype = ctypes.c_int
+    lib.graph_build_skin.argtypes = [ctypes.POINTER(GcProblem), P, P, ctypes.c_int32, P,
+                                     ctypes.c_size_t, ctypes.POINTER(GcGraph), P]
+    lib.graph_build_skin.restype = ctypes.c_int
+    lib.gc_skin_footprint_bytes.argtypes = [ctypes.POINTER(GcProblem), ctypes.c_int32]
+    lib.gc_skin_footprint_bytes.restype = ctypes.c_size_t
     lib.approx_level2_cut.argtypes = [ctypes.POINTER(GcGraph), P, P, ctypes.c_int32, P, P, P]
     lib.approx_level2_cut.restype = ctypes.c_int
     lib.graph_warm_start.argtypes = [ctypes.POINTER(GcGraph), ctypes.POINTER(GcGraph), P, P]
@@ -276,6 +282,19 @@ def alloc_workspace(p: GcProblem, device="cuda"):
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
+def skin_footprint_bytes(p: GcProblem, block: int) -> int:
+    return int(load().gc_skin_footprint_bytes(ctypes.byref(p), int(block)))
+
+
+def alloc_skin_workspace(p: GcProblem, block: int, device="cuda"):
+    """Workspace of a compact thin skin (graph_build_skin)."""
+    import torch
+    nbytes = skin_footprint_bytes(p, block)
+    if nbytes == 0:
+        _check(problem_check(p) or -1, "skin footprint")
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
 def solve_pair(left, right, p: GcProblem, opts: GcSolveOpts | None = None, stream=None,
                ws=None):
     """Runs the whole path on one pair of uint8 CUDA tensors ([h][w] grey or
@@ -324,6 +343,17 @@ def graph_build_window(p: GcProblem, cost, coarse_labels, block: int, ws, stream
     return Graph(g, ws)
 
 
+def graph_build_skin(p: GcProblem, cost, coarse_labels, block: int, ws, stream=None) -> Graph:
+    """The compact thin skin (only the windows' levels stored); ws of at
+    least skin_footprint_bytes(p, block) bytes."""
+    g = GcGraph()
+    _check(load().graph_build_skin(ctypes.byref(p), ctypes.c_void_p(cost.data_ptr()),
+                                   ctypes.c_void_p(coarse_labels.data_ptr()), int(block),
+                                   ctypes.c_void_p(ws.data_ptr()), ctypes.c_size_t(ws.numel()),
+                                   ctypes.byref(g), _stream_ptr(stream)), "graph_build_skin")
+    return Graph(g, ws)
+
+
 # Wave steps (A - 1) of the level-2 cut when the caller gives none:
 # max(32, labels).  Measured on MI355X: on the 384x288x16 pairs 32 steps
 # reach the level-1 labels' quality (eq. (2) error 1195 against 1161 for
@@ -356,8 +386,9 @@ APPROX_RELABEL_PERIOD = 32
 
 def approx_level1(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, stream=None,
                   ws=None, ws_coarse=None, level: int = 1, wave_steps: int | None = None):
-    """Delegate-point cut, then the cut inside the thin skin: exact (level 1)
-    or block by block after a wave-front pass (level 2).  Returns (labels,
+    """Delegate-point cut, then the cut inside the thin skin (built compact,
+    graph_build_skin; ws, if given, holds at least skin_footprint_bytes):
+    exact (level 1) or block by block after a wave-front pass (level 2).  Returns (labels,
     energy, flow, coarse labels, (coarse stats, fine stats)); level 2 has
     flow -1 and no fine stats."""
     import torch
@@ -375,10 +406,10 @@ def approx_level1(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = Non
     st_c = maxflow_solve(gcoarse, opts, stream)
     extract_labels(gcoarse, ccost, clab, cres, stream)
     if ws is None:
-        ws = alloc_workspace(p, dev)
+        ws = alloc_skin_workspace(p, block, dev)
     labels = torch.empty((p.height, p.width), dtype=torch.int32, device=dev)
     res = torch.zeros(2, dtype=torch.int64, device=dev)
-    gfine = graph_build_window(p, cost, clab, block, ws, stream)
+    gfine = graph_build_skin(p, cost, clab, block, ws, stream)
     if level == 1:
         st_f = maxflow_solve(gfine, opts, stream)
         extract_labels(gfine, cost, labels, res, stream)
@@ -396,9 +427,11 @@ def graph_warm_start(graph: Graph, skin: Graph, cost, stream=None):
 
 
 def solve_warm(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, stream=None,
-               ws=None, ws_skin=None, ws_coarse=None, approx_opts: GcSolveOpts | None = None):
+               ws=None, ws_skin=None, ws_coarse=None, approx_opts: GcSolveOpts | None = None,
+               compact: bool = True):
     """Exact cut seeded from the level-1 approximation: delegate-point cut,
-    thin-skin cut, then the full graph warm-started from the skin's state and
+    thin-skin cut (a compact skin, or with compact=False one in the full
+    layout), then the full graph warm-started from the skin's state and
     solved exactly.  Returns (labels, energy, flow, (coarse, skin, full
     stats), the solved full graph)."""
     import torch
@@ -412,14 +445,14 @@ def solve_warm(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, 
     if ws_coarse is None:
         ws_coarse = alloc_workspace(c, dev)
     if ws_skin is None:
-        ws_skin = alloc_workspace(p, dev)
+        ws_skin = alloc_skin_workspace(p, block, dev) if compact else alloc_workspace(p, dev)
     if ws is None:
         ws = alloc_workspace(p, dev)
     coarse_cost_volume(p, cost, block, ccost, stream)
     gcoarse = graph_build(c, ccost, ws_coarse, stream)
     st_c = maxflow_solve(gcoarse, approx_opts, stream)
     extract_labels(gcoarse, ccost, clab, cres, stream)
-    gskin = graph_build_window(p, cost, clab, block, ws_skin, stream)
+    gskin = (graph_build_skin if compact else graph_build_window)(p, cost, clab, block, ws_skin, stream)
     st_s = maxflow_solve(gskin, approx_opts, stream)
     g = graph_build(p, cost, ws, stream)
     graph_warm_start(g, gskin, cost, stream)

@@ -55,6 +55,44 @@ def test_problem_validation_and_footprint():
     assert gc.load().gc_status_str(-5).decode().startswith("iteration cap")
 
 
+def test_skin_footprint():
+    """A compact thin skin stores min(3b - 1, m - 1) levels per site."""
+    gc.load()
+    p = gc.problem(450, 375, 64, 30, 1, 1023)
+    sites = 450 * 375
+    full = gc.footprint_bytes(p)
+    for b, levels in [(1, 2), (2, 5), (3, 8), (5, 14)]:
+        n = sites * levels
+        fp = gc.skin_footprint_bytes(p, b)
+        tiles = -(-450 // 8) * -(-375 // 4) * -(-levels // 4)
+        base = 46 * n + 8 * sites + 8 * tiles + 12 * (n // 256)
+        assert base <= fp < base + 64 * 1024, (b, fp, base)
+        assert fp < full
+    small = gc.problem(40, 30, 4, 30, 1, 1023)                  # m - 1 < 3b - 1: every level
+    assert gc.skin_footprint_bytes(small, 3) == gc.footprint_bytes(small)
+    assert gc.skin_footprint_bytes(p, 0) == 0
+
+
+def test_compact_skin_handles_checked_on_the_host():
+    """Handles are validated before any device work: a compact flag needs a
+    block size, more than 16 stored levels are refused, and the batch does
+    not take compact skins."""
+    fp = gc.batch_footprint_bytes()
+    b = gc.Batch(1 << 20, fp)
+    p = gc.problem(16, 8, 64, 20, 1, 1023)
+    bad = gc.GcGraph(ws=1 << 24, ws_bytes=gc.footprint_bytes(p), p=p, window_block=0, compact=1)
+    with pytest.raises(gc.GazecutError):
+        b.add(gc.Graph(bad, None), 1)
+    skin = gc.GcGraph(ws=1 << 24, ws_bytes=gc.footprint_bytes(p), p=p, window_block=3, compact=1)
+    with pytest.raises(gc.GazecutError):
+        b.add(gc.Graph(skin, None), 2)
+    wide = gc.GcGraph(ws=1 << 24, ws_bytes=gc.footprint_bytes(p), p=p, window_block=6, compact=1)
+    with pytest.raises(gc.GazecutError):                     # 17 levels per site
+        b.add(gc.Graph(wide, None), 3)
+    assert len(b) == 0
+    b.close()
+
+
 def test_coarse_problem_sizes():
     p = gc.problem(384, 288, 16, 30, 1, 1023)
     c = gc.coarse_problem(p, 3)

@@ -390,8 +390,61 @@ def test_approx_level2_parity(torch_cuda, orc, b, steps, spec, seed):
     assert (labels.cpu().numpy() == ref_lab).all()
 
 
+_SKIN_OPTS = {"default": None, "fused": gc.GcSolveOpts(flags=gc.GC_OPT_FUSED_SWEEP),
+              "wave-first-p5": gc.GcSolveOpts(relabel_period=5, flags=gc.GC_OPT_WAVE_FIRST),
+              "captured": gc.GcSolveOpts(flags=gc.GC_OPT_SWEEP_GRAPH)}
+
+
+@pytest.mark.parametrize("opt", list(_SKIN_OPTS))
+@pytest.mark.parametrize("build", ["window", "skin"])
+@pytest.mark.parametrize("b,seed", [(1, 0), (2, 1), (3, 2), (4, 3), (5, 4)])
+def test_skin_exact_arbitrary_windows(torch_cuda, orc, b, seed, build, opt):
+    """The second cut of level 1 inside windows from random delegate labels
+    (large label jumps between neighbouring delegate points, so neighbouring
+    windows are offset by many levels; windows clamped at both ends; ragged
+    edges; soft inhibit), in the full layout and in the compact one, against
+    the oracle's exact cut inside the same windows: labels, energy and the
+    restricted min-cut value."""
+    rng = np.random.default_rng(900 + seed)
+    w, h, m = 23 + 3 * seed, 13 + 2 * seed, 10 + 4 * seed
+    pen_h, inh_h, pen_v, inh_v = [(1, 1023, 1, 1023), (2, 7, 1, 3), (3, 5, 0, 0)][seed % 3]
+    cost_np = rng.integers(0, 30, (m, h, w)).astype(np.int32)
+    cl_np = rng.integers(0, -(-m // b), (-(-h // b), -(-w // b))).astype(np.int32)
+    lo, hi = orc.skin_windows(cl_np, w, h, m, b)
+    ref_lab, ref_flow, ref_e = orc.solve_window(cost_np, lo, hi, pen_h, inh_h, pen_v, inh_v)
+    p = gc.problem(w, h, m, 30, pen_h, inh_h, pen_v, inh_v)
+    cost = torch_cuda.from_numpy(cost_np).cuda()
+    cl = torch_cuda.from_numpy(cl_np).cuda()
+    print(f"skin {build} {w}x{h}x{m} b={b} opts={opt}", flush=True)
+    if build == "skin":
+        ws = gc.alloc_skin_workspace(p, b)
+        assert ws.numel() <= gc.footprint_bytes(p)
+        g = gc.graph_build_skin(p, cost, cl, b, ws)
+    else:
+        g = gc.graph_build_window(p, cost, cl, b, gc.alloc_workspace(p))
+    gc.maxflow_solve(g, _SKIN_OPTS[opt])
+    labels = torch_cuda.empty((h, w), dtype=torch_cuda.int32, device="cuda")
+    res = torch_cuda.zeros(2, dtype=torch_cuda.int64, device="cuda")
+    gc.extract_labels(g, cost, labels, res)
+    e, f = res.cpu().tolist()
+    assert (labels.cpu().numpy() == ref_lab).all()
+    assert e == ref_e and f == ref_flow
+
+
+def test_compact_skin_refuses_state_export(torch_cuda):
+    p = gc.problem(20, 12, 16, 30, 1, 1023)
+    cost = torch_cuda.zeros((16, 12, 20), dtype=torch_cuda.int32, device="cuda")
+    cl = torch_cuda.zeros((4, 7), dtype=torch_cuda.int32, device="cuda")
+    g = gc.graph_build_skin(p, cost, cl, 3, gc.alloc_skin_workspace(p, 3))
+    with pytest.raises(gc.GazecutError):
+        gc.graph_state(g)
+    with pytest.raises(gc.GazecutError):                      # workspace too small
+        gc.graph_build_skin(p, cost, cl, 3, gc.alloc_skin_workspace(p, 2))
+
+
+@pytest.mark.parametrize("build", ["window", "skin"])
 @pytest.mark.parametrize("b,steps,seed", [(2, 0, 0), (2, 3, 1), (3, 0, 2), (3, 7, 3), (3, 64, 4)])
-def test_approx_level2_arbitrary_windows(torch_cuda, orc, b, steps, seed):
+def test_approx_level2_arbitrary_windows(torch_cuda, orc, b, steps, seed, build):
     """The level-2 cut on skins built from random delegate labels (large
     label jumps between neighbouring delegate points, ragged edges, soft
     inhibit) against the oracle's level-2 cut inside the same windows."""
@@ -405,11 +458,13 @@ def test_approx_level2_arbitrary_windows(torch_cuda, orc, b, steps, seed):
     p = gc.problem(w, h, m, 30, pen_h, inh_h, pen_v, inh_v)
     cost = torch_cuda.from_numpy(cost_np).cuda()
     cl = torch_cuda.from_numpy(cl_np).cuda()
-    ws = gc.alloc_workspace(p)
     labels = torch_cuda.empty((h, w), dtype=torch_cuda.int32, device="cuda")
     res = torch_cuda.zeros(2, dtype=torch_cuda.int64, device="cuda")
-    print(f"level2 windows {w}x{h}x{m} b={b} steps={steps}", flush=True)
-    g = gc.graph_build_window(p, cost, cl, b, ws)
+    print(f"level2 windows {build} {w}x{h}x{m} b={b} steps={steps}", flush=True)
+    if build == "skin":
+        g = gc.graph_build_skin(p, cost, cl, b, gc.alloc_skin_workspace(p, b))
+    else:
+        g = gc.graph_build_window(p, cost, cl, b, gc.alloc_workspace(p))
     gc.approx_level2_cut(g, cost, cl, labels, res, wave_steps=steps)
     got = labels.cpu().numpy()
     assert (got == ref_lab).all()
@@ -442,14 +497,16 @@ _WARM_OPTS = {"default": None,
 @pytest.mark.parametrize("spec,seed", [(sg.TINY, (1, 0)), (sg.spec_like(sg.MID, 70, 33, 9), (9, 8)),
                                        (sg.spec_like(sg.LARGE, 61, 47, 21), (3, 7))],
                          ids=["tiny", "ragged-70x33x9", "textureless-61x47x21"])
-def test_warm_start_exact_parity(torch_cuda, orc, opt, b, spec, seed):
-    """The exact solve seeded from the level-1 skin's state ends in the
-    oracle's exact cut: same labels (minimal source side), energy and flow."""
+@pytest.mark.parametrize("layout", ["compact", "full"])
+def test_warm_start_exact_parity(torch_cuda, orc, opt, b, spec, seed, layout):
+    """The exact solve seeded from the level-1 skin's state (a compact skin
+    or one in the full layout) ends in the oracle's exact cut: same labels
+    (minimal source side), energy and flow."""
     pr = sg.make_pair(spec, seed)
     p = gc.problem(spec.w, spec.h, spec.m, spec.cap, spec.lam, spec.inhibit)
     cost = _cost_gpu(torch_cuda, pr.left, pr.right, p)
-    print(f"warm start {spec.w}x{spec.h}x{spec.m} b={b} opts={opt}", flush=True)
-    labels, energy, flow, sts, _ = gc.solve_warm(p, cost, b, _WARM_OPTS[opt])
+    print(f"warm start {spec.w}x{spec.h}x{spec.m} b={b} opts={opt} {layout}", flush=True)
+    labels, energy, flow, sts, _ = gc.solve_warm(p, cost, b, _WARM_OPTS[opt], compact=layout == "compact")
     _check_against_oracle(orc, cost.cpu().numpy(), labels.cpu().numpy(), energy, flow,
                           (spec.lam, spec.inhibit, spec.lam, spec.inhibit))
     assert sts[2].active_last == 0
