@@ -184,12 +184,12 @@ def bench_batch(args, gc, sg, torch):
     stream = torch.cuda.Stream()
     mix = rt.batch_mix(args.batch_pairs, sg.BATCH_SHAPES, seed=4)
     with torch.cuda.stream(stream):
-        # autotune on two pairs of every shape class, for each engine
-        seen, tune = {}, []
+        # autotune on one pair of every shape class, for each engine
+        seen, tune = set(), []
         for i, (spec, pair) in enumerate(mix):
             key = (spec.w, spec.h, spec.m)
-            if seen.get(key, 0) < 2:
-                seen[key] = seen.get(key, 0) + 1
+            if key not in seen:
+                seen.add(key)
                 tune.append(rt.make_item(i, spec, pair))
         t = time.perf_counter()
         best_lanes, trials_l = rt.autotune(tune, stream=stream, use_graph=True)

@@ -21,8 +21,9 @@
  *   extract_labels      minimal source side -> depth numbers, E  (Sec. 3: the cut is the surface)
  *
  * Also: the hierarchical approximations of Sec. 4.5 (coarse_cost_volume,
- * graph_build_window, approx_level2_cut) and batched solves of many graphs
- * (maxflow_solve_batch, gc_batch_*).
+ * graph_build_skin or graph_build_window, approx_level2_cut), the exact solve
+ * warm-started from them (graph_warm_start) and batched solves of many
+ * graphs (maxflow_solve_batch, gc_batch_*).
  *
  * Conventions for every call:
  *   - Buffers marked DEVICE are hipMalloc'd (e.g. torch CUDA tensors) and
