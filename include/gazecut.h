@@ -100,7 +100,14 @@ typedef struct {
     int32_t tile_j;           /* along the depth-number axis (default 16)     */
     int32_t local_iters;      /* max in-tile relaxation rounds per pass (default 8) */
     int32_t flags;            /* GC_OPT_* bits                                */
-    int32_t reserved;
+    int32_t relabel_passes;   /* most relaxation passes of a global relabel that
+                                 does not end the solve (default 16; < 0: none
+                                 stops early).  Stopped early, its heights are
+                                 exact distances where the passes converged and
+                                 INF elsewhere (those nodes wait for the next
+                                 relabel); a relabel that then finds no active
+                                 node is carried on to its exact fixpoint, so the
+                                 solve still ends on an exact one. */
 } gc_solve_opts;
 
 /* gc_solve_opts.flags: bracket one launch in 16 of each kernel class (chosen by a hash

@@ -32,7 +32,7 @@ class GcSolveOpts(ctypes.Structure):
     _fields_ = [("relabel_period", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("tile_j", ctypes.c_int32), ("local_iters", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("relabel_passes", ctypes.c_int32)]
 
 
 GC_OPT_TIME_KERNELS = 1

@@ -88,6 +88,22 @@ def test_batch_matches_oracle(torch_cuda, orc, use_graph, merged):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("passes", [-1, 2])
+@pytest.mark.parametrize("merged", [False, True], ids=["lanes", "merged"])
+def test_batch_relabel_pass_caps(torch_cuda, orc, merged, passes):
+    """Relabels stopped after 2 passes (carried on to the fixpoint when
+    nothing is active) or never stopped, in the batch engine's device phase
+    machine and in the lanes: the oracle's cuts."""
+    torch = torch_cuda
+    built = [_build(torch, orc, *c) for c in _cases(orc)]
+    torch.cuda.synchronize()
+    gc.maxflow_solve_batch([b[2] for b in built],
+                           gc.GcSolveOpts(relabel_period=13, relabel_passes=passes,
+                                          flags=gc.GC_OPT_BATCH_MERGED if merged else 0))
+    for p, cost, g, ref in built:
+        _check(ref, _read(torch, g, cost, p))
+
+
 def test_batch_rounds_with_members_joining(torch_cuda, orc):
     """Graphs join between rounds while others are still being solved."""
     torch = torch_cuda

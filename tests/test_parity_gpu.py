@@ -317,6 +317,37 @@ def test_solver_variants_parity(torch_cuda, orc, variant, name, cost, params):
         assert st.active_last == 0
 
 
+@pytest.mark.parametrize("passes", [-1, 1, 2, 5])
+@pytest.mark.parametrize("flags", [0, gc.GC_OPT_FUSED_SWEEP, gc.GC_OPT_SWEEP_GRAPH],
+                         ids=["split", "fused", "graph"])
+@pytest.mark.parametrize("name,cost,params", list(_variant_cases()), ids=[c[0] for c in _variant_cases()])
+def test_relabel_pass_caps_parity(torch_cuda, orc, passes, flags, name, cost, params):
+    """Global relabels stopped after 1, 2 or 5 passes (or never, -1): the
+    heights are then exact only near the deficits and INF beyond, and a
+    relabel that finds nothing active is carried on to its fixpoint; the
+    cut, energy and flow stay the oracle's."""
+    stream = torch_cuda.cuda.Stream() if flags & gc.GC_OPT_SWEEP_GRAPH else None
+    for period in (1, 13, 64):
+        o = gc.GcSolveOpts(relabel_period=period, flags=flags, relabel_passes=passes)
+        lab, energy, flow, st = _solve_cost_gpu(torch_cuda, cost, *params, opts=o, stream=stream)
+        _check_against_oracle(orc, cost, lab, energy, flow, params)
+        assert st.active_last == 0
+
+
+@pytest.mark.parametrize("passes", [-1, 3])
+def test_relabel_pass_caps_large_full_size(torch_cuda, passes):
+    """450x375x64 with every relabel exact and with relabels stopped after
+    3 passes: the same cut as the default solve (16 passes), energy = flow."""
+    pr = sg.make_pair(sg.LARGE, (3, 1))
+    p = gc.problem(sg.LARGE.w, sg.LARGE.h, sg.LARGE.m, sg.LARGE.cap, 1, 1023)
+    L = torch_cuda.from_numpy(pr.left).cuda()
+    R = torch_cuda.from_numpy(pr.right).cuda()
+    lab0, _, e0, f0, _ = gc.solve_pair(L, R, p)
+    lab, _, e, f, st = gc.solve_pair(L, R, p, gc.GcSolveOpts(relabel_passes=passes))
+    assert e == f == e0 == f0 and st.active_last == 0
+    assert (lab.cpu().numpy() == lab0.cpu().numpy()).all()
+
+
 @pytest.mark.parametrize("variant", ["fused", "fused-wave-first", "lists-split", "lists-fused"])
 def test_solver_variants_mid_full_size(torch_cuda, orc, variant):
     pr = sg.make_pair(sg.MID, (2, 1))
