@@ -102,9 +102,10 @@ typedef struct {
     int32_t flags;            /* GC_OPT_* bits                                */
     int32_t relabel_passes;   /* most relaxation passes of a global relabel that
                                  does not end the solve (default 16; < 0: none
-                                 stops early).  Stopped early, its heights are
-                                 exact distances where the passes converged and
-                                 INF elsewhere (those nodes wait for the next
+                                 stops early; only a solve's first 24 relabels
+                                 may).  Stopped early, its heights bound the
+                                 distances from above near the deficits and are
+                                 INF farther away (those nodes wait for the next
                                  relabel); a relabel that then finds no active
                                  node is carried on to its exact fixpoint, so the
                                  solve still ends on an exact one. */
