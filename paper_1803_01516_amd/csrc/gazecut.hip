@@ -1987,6 +1987,12 @@ k_block_cut(Graph s, const int32_t *__restrict__ coarse_labels, int b)
 // within a few per cent either way.
 constexpr int kRelabelPasses = 16;
 
+// Sweeps between global relabels (the first period; later ones adapt below
+// it).  With relabels stopped early a shorter period pays: 32 against 64
+// was 10-20 % faster on 320x240x16 and 384x288x16 (grey, colour, penalties
+// 1 and 2) and 640x480x64 pairs, within noise on 450x375x64.
+constexpr int kRelabelPeriod = 32;
+
 // Only a solve's first relabels may stop early.  Heights set by an early-
 // stopped relabel need not be a valid labelling, so flow may circulate from
 // one such relabel to the next; from this relabel on every relabel is exact,
@@ -1999,7 +2005,7 @@ struct Opts {
 
 Opts resolve(const gc_solve_opts *o)
 {
-    Opts r{64, 1 << 20, 8, 8, 16, 8, 0, kRelabelPasses};
+    Opts r{kRelabelPeriod, 1 << 20, 8, 8, 16, 8, 0, kRelabelPasses};
     if (o) {
         if (o->relabel_period > 0) r.period = o->relabel_period;
         if (o->max_sweeps > 0) r.max_sweeps = o->max_sweeps;
@@ -2171,14 +2177,19 @@ thread_local std::vector<hipEvent_t> &t_events = t_pool.ev;
 // the interval is the kernel's execution, as a profiler reports it, not the
 // kernel plus the queue's event packets.
 constexpr int kTimeEvery = 16;
+// Graphs of at least this many nodes run few, long launches: one in 4 is
+// timed there (one in 16 left the mean of a 640x480x64 solve's ~800 sweeps
+// 19 % off the profiler's).
+constexpr int64_t kTimeDenseNodes = int64_t(1) << 22;
+constexpr int kTimeEveryLarge = 4;
 
-inline bool timed_launch(int klass, int k)
+inline bool timed_launch(int klass, int k, int every)
 {
     uint32_t h = (uint32_t)k * 0x9E3779B1u + (uint32_t)klass * 0x85EBCA77u;
     h ^= h >> 15;
     h *= 0x2C1B3C6Du;
     h ^= h >> 12;
-    return (h % kTimeEvery) == 0;
+    return (h % (uint32_t)every) == 0;
 }
 
 thread_local uint32_t t_class_launches[GC_K_CLASSES];
@@ -2191,6 +2202,7 @@ struct Launcher {
     std::vector<int> cls;
     int launched[GC_K_CLASSES] = {};
     HeaderRead *rb = nullptr;          // read-back landing buffer; null: the thread's pinned one
+    int every = kTimeEvery;            // one launch in `every` of a class is timed
 
     hipEvent_t event(size_t i)
     {
@@ -2209,7 +2221,7 @@ struct Launcher {
     void run(int klass, K kernel, dim3 grid, Args... args)
     {
         hipEvent_t a = nullptr, b = nullptr;
-        if (timing && (++launched[klass], timed_launch(klass, (int)t_class_launches[klass]++))) {
+        if (timing && (++launched[klass], timed_launch(klass, (int)t_class_launches[klass]++, every))) {
             a = event(2 * cls.size());
             b = event(2 * cls.size() + 1);
         }
@@ -2680,6 +2692,7 @@ static int solve_graph(gc_graph *g, const Opts &opt, gc_solve_stats *stats, hipS
         return GC_OK;
     }
     Launcher L{st, (opt.flags & GC_OPT_TIME_KERNELS) != 0, {}};
+    if (s.N >= kTimeDenseNodes) L.every = kTimeEveryLarge;
     L.rb = rb;
     const unsigned grid = grid_for(s.N);
     const bool fused = sweep_fused(opt, s.J);
