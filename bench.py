@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=60, help="requests of the serving stream (0: skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
-    ap.add_argument("--serve-low-rate", type=float, default=4.0,
+    ap.add_argument("--serve-low-rate", type=float, default=8.0,
                     help="second stream below the GPU's capacity (0: skip)")
     ap.add_argument("--serve-low-requests", type=int, default=1000)
     ap.add_argument("--copy-calibration", action="store_true",
