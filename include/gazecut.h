@@ -98,7 +98,7 @@ typedef struct {
     int32_t tile_w;           /* BFS tile extent along x (default 8)           */
     int32_t tile_h;           /* along y (default 8)                          */
     int32_t tile_j;           /* along the depth-number axis (default 16)     */
-    int32_t local_iters;      /* max in-tile relaxation rounds per pass (default 8) */
+    int32_t local_iters;      /* max in-tile relaxation rounds per pass (default 4 below 32 levels, else 8) */
     int32_t flags;            /* GC_OPT_* bits                                */
     int32_t relabel_passes;   /* most relaxation passes of a global relabel that
                                  does not end the solve (default 16; < 0: none
