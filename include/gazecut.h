@@ -101,9 +101,9 @@ typedef struct {
     int32_t local_iters;      /* max in-tile relaxation rounds per pass (default 4 below 32 levels, else 8) */
     int32_t flags;            /* GC_OPT_* bits                                */
     int32_t relabel_passes;   /* most relaxation passes of a global relabel that
-                                 does not end the solve (default 16; < 0: none
-                                 stops early; only a solve's first 24 relabels
-                                 may).  Stopped early, its heights bound the
+                                 does not end the solve (default 8 below 32
+                                 levels, 16 from there on; < 0: none stops early;
+                                 only a solve's first 24 relabels may).  Stopped early, its heights bound the
                                  distances from above near the deficits and are
                                  INF farther away (those nodes wait for the next
                                  relabel); a relabel that then finds no active

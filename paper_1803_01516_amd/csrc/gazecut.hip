@@ -336,7 +336,7 @@ struct BatchDev {
     int32_t live;             // members not finished
     int32_t step;             // steps run
     int32_t period, max_sweeps, local_iters, flags;
-    int32_t relabel_passes;   // cap of a relabel's passes (0: none)
+    int32_t relabel_passes;   // the option: > 0 a relabel's pass cap, < 0 none, 0 by depth
     int32_t pad[5];
     int32_t unit_off[3][kMaxBatch + 1];   // per kind, prefix of the members' units
     int32_t list_off[kMaxBatch + 1];   // prefix of the members' compaction workgroups
@@ -1978,14 +1978,17 @@ k_block_cut(Graph s, const int32_t *__restrict__ coarse_labels, int b)
 // Host side
 // ---------------------------------------------------------------------------
 
-// Relaxation passes of a global relabel that does not end the solve.  The
-// distances spread from the deficits a tile per pass; most of a relabel's
-// passes carry them laterally over long distances to excess that is far
-// from any deficit, which the sweeps that follow can hardly move anyway.
-// Measured on 450x375x64 and 640x480x64 pairs (seeded sets of 3 and 6), a
-// cap of 12-20 passes took 35-45 % off the solve; at 16 depth numbers it is
-// within a few per cent either way.
-constexpr int kRelabelPasses = 16;
+// Relaxation passes of a global relabel that does not end the solve, when
+// the options leave them at 0.  The distances spread from the deficits a
+// tile per pass; most of a relabel's passes carry them laterally over long
+// distances to excess that is far from any deficit, which the sweeps that
+// follow can hardly move anyway.  Measured on 450x375x64 and 640x480x64
+// pairs (seeded sets of 3 and 6), a cap of 12-20 passes took 35-45 % off
+// the solve (8: slower at 450x375x64); on seven sets of 16-, 24- and
+// 31-level pairs 8 passes were about 10 % faster than 16 (4: outliers of
+// 2-3x, 6: within 3 % of 8).
+constexpr int kRelabelPassesDeep = 16;
+constexpr int kRelabelPassesShallow = 8;
 
 // Sweeps between global relabels (the first period; later ones adapt below
 // it).  With relabels stopped early a shorter period pays: 32 against 64
@@ -2005,7 +2008,7 @@ struct Opts {
 
 Opts resolve(const gc_solve_opts *o)
 {
-    Opts r{kRelabelPeriod, 1 << 20, 8, 8, 16, 0, 0, kRelabelPasses};
+    Opts r{kRelabelPeriod, 1 << 20, 8, 8, 16, 0, 0, 0};
     if (o) {
         if (o->relabel_period > 0) r.period = o->relabel_period;
         if (o->max_sweeps > 0) r.max_sweeps = o->max_sweeps;
@@ -2014,7 +2017,7 @@ Opts resolve(const gc_solve_opts *o)
         if (o->tile_j > 0) r.tj = o->tile_j;
         if (o->local_iters > 0) r.local_iters = o->local_iters;
         r.flags = o->flags;
-        if (o->relabel_passes != 0) r.relabel_passes = o->relabel_passes < 0 ? 0 : o->relabel_passes;
+        r.relabel_passes = o->relabel_passes < 0 ? -1 : o->relabel_passes;
     }
     return r;
 }
@@ -2073,6 +2076,14 @@ constexpr int kFusedMinLayers = 32;
 __host__ __device__ inline int relax_rounds(int opt_rounds, const Graph &s)
 {
     return opt_rounds > 0 ? opt_rounds : (s.J < kFusedMinLayers && !s.cw) ? 4 : 8;
+}
+
+// Pass cap of a relabel that does not end the solve (0: none) from the
+// option (> 0: that many, < 0: none, 0: by depth).
+__host__ __device__ inline int relabel_cap(int opt_passes, const Graph &s)
+{
+    return opt_passes > 0 ? opt_passes : opt_passes < 0 ? 0
+         : s.J < kFusedMinLayers ? kRelabelPassesShallow : kRelabelPassesDeep;
 }
 
 inline bool sweep_fused(const Opts &o, int layers)
@@ -2728,7 +2739,8 @@ static int solve_graph(gc_graph *g, const Opts &opt, gc_solve_stats *stats, hipS
         bool exact = true;
         int last = 0;
         if ((rc = relax_to_fixpoint(s, 0, opt, L, &st_local.bfs_passes, true, &hr, batch_hint,
-                                    round < kCappedRelabels ? opt.relabel_passes : 0, &exact, &last)) != GC_OK)
+                                    round < kCappedRelabels ? relabel_cap(opt.relabel_passes, s) : 0, &exact,
+                                    &last)) != GC_OK)
             return rc;
         if (hr.prefix_err & kCostErr) return GC_E_CAP_OVERFLOW;
         if (hr.active == 0 && !exact &&
@@ -2999,8 +3011,8 @@ k_batch_phase(BatchDev *T)
             if (!s.hdr->flags[c.pass % kMaxFlags]) {
                 nx = BP_COUNT;                   // converged: exact
                 c.cut = 0;
-            } else if (T->relabel_passes > 0 && c.cut != 2 && c.round < kCappedRelabels &&
-                       c.pass >= T->relabel_passes) {
+            } else if (c.cut != 2 && c.round < kCappedRelabels && relabel_cap(T->relabel_passes, s) > 0 &&
+                       c.pass >= relabel_cap(T->relabel_passes, s)) {
                 nx = BP_COUNT;                   // stopped early (as maxflow_solve)
                 c.cut = 1;
             } else {
