@@ -2079,11 +2079,13 @@ __host__ __device__ inline int relax_rounds(int opt_rounds, const Graph &s)
 }
 
 // Pass cap of a relabel that does not end the solve (0: none) from the
-// option (> 0: that many, < 0: none, 0: by depth).
+// option (> 0: that many, < 0: none, 0: by the depth of the full problem,
+// which a thin skin inherits: its windows hold few levels, but its lateral
+// distances are those of the deep problem).
 __host__ __device__ inline int relabel_cap(int opt_passes, const Graph &s)
 {
     return opt_passes > 0 ? opt_passes : opt_passes < 0 ? 0
-         : s.J < kFusedMinLayers ? kRelabelPassesShallow : kRelabelPassesDeep;
+         : s.Jf < kFusedMinLayers ? kRelabelPassesShallow : kRelabelPassesDeep;
 }
 
 inline bool sweep_fused(const Opts &o, int layers)
