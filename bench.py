@@ -260,8 +260,7 @@ def bench_batch(args, gc, sg, torch):
 
     def opts_of(o):
         return {"tile": [o.tile_w, o.tile_h, o.tile_j], "relabel_period": o.relabel_period,
-                "sweep": ("fused" if o.flags & gc.GC_OPT_FUSED_SWEEP else
-                          "split" if o.flags & gc.GC_OPT_SPLIT_SWEEP else "by depth")}
+                "sweep": "split" if o.flags & gc.GC_OPT_SPLIT_SWEEP else "fused"}
 
     return {"workload": f"{n} seeded pairs uniform over 320x240x16, 384x288x16, 450x375x64, "
                         "640x480x64 (6-10 slanted planes, sigma 3, cap 30, penalty 1, inhibit 1023)",
@@ -395,7 +394,7 @@ def bench_larger(args, gc, torch, sg, lspec, seed0, stream, dev):
            "energy_equals_flow": exact}
     if not args.no_timing:
         out["roofline"] = roofline_block(stats, nodes, f"{lspec.w}x{lspec.h}x{lspec.m}",
-                                         lspec.m - 1 >= 32, gc.footprint_bytes(lp), len(stats))
+                                         True, gc.footprint_bytes(lp), len(stats))   # fused sweeps (the default)
     del lws, ll, lr
     return out
 
@@ -499,7 +498,7 @@ def main():
 
     roof = None
     if not args.no_timing:
-        roof = roofline_block(stats, nodes, f"{spec.w}x{spec.h}x{spec.m}", spec.m - 1 >= 32,
+        roof = roofline_block(stats, nodes, f"{spec.w}x{spec.h}x{spec.m}", True,   # fused sweeps (the default)
                               gc.footprint_bytes(p), args.steps)
 
     # pairwise-term variants on the same pairs (Fig. 6 compares inhibit 0 and

@@ -131,11 +131,10 @@ typedef struct {
  * column).  Off by default.  Labels, energy and flow do not depend on it. */
 #define GC_OPT_WAVE_FIRST 4
 
-/* gc_solve_opts.flags: the sweep kernels.  FUSED_SWEEP runs one fused
- * push-relabel kernel per sweep, SPLIT_SWEEP a push kernel and a relabel
- * kernel; by default graphs with at least 32 depth layers (33 labels) get the
- * fused kernel and shallower ones the split pair (a batch decides per sweep
- * group, by its shallowest member).  The final result does not depend on it. */
+/* gc_solve_opts.flags: the sweep kernels.  FUSED_SWEEP (the default) runs
+ * one fused push-relabel kernel per sweep, SPLIT_SWEEP a push kernel and a
+ * relabel kernel (it wins when both are given).  The final result does not
+ * depend on it. */
 #define GC_OPT_FUSED_SWEEP 16
 #define GC_OPT_SPLIT_SWEEP 64
 

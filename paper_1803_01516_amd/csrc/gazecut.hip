@@ -2061,21 +2061,18 @@ int64_t relax_tiles(const Graph &s, const Opts &o)
     return (int64_t)((s.W + o.tw - 1) / o.tw) * ((s.H + o.th - 1) / o.th) * ((s.J + o.tj - 1) / o.tj);
 }
 
-// Sweep kind: forced by the flags, else the fused kernel for graphs with at
-// least kFusedMinLayers depth layers.  Measured on MI355X: with 63 layers
-// (450x375 and 640x480, 64 depth numbers) the fused sweep solves 10-20 %
-// faster; with 15 layers it needs more sweeps and global relabels and is
-// 10-15 % slower.
-constexpr int kFusedMinLayers = 32;
+// Depth (levels of the full graph) from which a graph counts as deep for
+// the relaxation's in-tile rounds and the early-stopped relabels' pass cap.
+constexpr int kDeepLevels = 32;
 
 // In-tile rounds of a relaxation pass when the options leave them at 0:
-// 4 below kFusedMinLayers levels, 8 from there on and in compact skins.
+// 4 below kDeepLevels levels, 8 from there on and in compact skins.
 // Measured with relabels stopped early: 4 rounds were 4-8 % faster than 8 on
 // seven sets of 16-, 24- and 31-level pairs, and 8 were 1.5x faster than 4
 // on 450x375x64.
 __host__ __device__ inline int relax_rounds(int opt_rounds, const Graph &s)
 {
-    return opt_rounds > 0 ? opt_rounds : (s.J < kFusedMinLayers && !s.cw) ? 4 : 8;
+    return opt_rounds > 0 ? opt_rounds : (s.J < kDeepLevels && !s.cw) ? 4 : 8;
 }
 
 // Pass cap of a relabel that does not end the solve (0: none) from the
@@ -2085,14 +2082,19 @@ __host__ __device__ inline int relax_rounds(int opt_rounds, const Graph &s)
 __host__ __device__ inline int relabel_cap(int opt_passes, const Graph &s)
 {
     return opt_passes > 0 ? opt_passes : opt_passes < 0 ? 0
-         : s.Jf < kFusedMinLayers ? kRelabelPassesShallow : kRelabelPassesDeep;
+         : s.Jf < kDeepLevels ? kRelabelPassesShallow : kRelabelPassesDeep;
 }
 
-inline bool sweep_fused(const Opts &o, int layers)
+// Sweep kind: the split pair when the flags ask for it, else the fused
+// kernel.  Measured on MI355X with early-stopped relabels: on 64-level
+// graphs (450x375, 640x480) the fused sweep solves 10-20 % faster; on
+// 384x288x16 it takes about 10 % more sweeps but half the launches and
+// solves 3-4 % faster (mean over four seed sets of 16 pairs; 2.5 % slower on
+// one set of 320x240x16 pairs); on the approximations' coarse graphs and
+// skins of 64-level problems 2-6 % faster.
+inline bool sweep_fused(const Opts &o)
 {
-    if (o.flags & GC_OPT_FUSED_SWEEP) return true;
-    if (o.flags & GC_OPT_SPLIT_SWEEP) return false;
-    return layers >= kFusedMinLayers;
+    return !(o.flags & GC_OPT_SPLIT_SWEEP);
 }
 
 // Work-list launches (sweeps over the listed blocks, relaxation passes over
@@ -2718,7 +2720,7 @@ static int solve_graph(gc_graph *g, const Opts &opt, gc_solve_stats *stats, hipS
     if (s.N >= kTimeDenseNodes) L.every = kTimeEveryLarge;
     L.rb = rb;
     const unsigned grid = grid_for(s.N);
-    const bool fused = sweep_fused(opt, s.J);
+    const bool fused = sweep_fused(opt);
     const bool listed = use_lists(opt, s.N) && !s.cw;
     const bool use_graph = st != nullptr && (opt.flags & GC_OPT_SWEEP_GRAPH) != 0 && !L.timing;
     int status = GC_OK;
@@ -3286,7 +3288,7 @@ MemberCtl member_init(const gc_batch *b, const Graph &s)
     MemberCtl c;
     memset(&c, 0, sizeof(c));
     c.phase = BP_INIT;
-    c.fused = sweep_fused(b->opt, s.J) ? 1 : 0;
+    c.fused = sweep_fused(b->opt) ? 1 : 0;
     c.blocks = (int32_t)grid_for(s.N);
     c.tiles = (int32_t)relax_tiles(s, b->opt);
     return c;

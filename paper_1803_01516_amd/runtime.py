@@ -89,7 +89,7 @@ def release(item: Item):
 
 TILE_CANDIDATES = ((8, 8, 16), (16, 8, 16), (8, 8, 32), (16, 16, 8))
 PERIOD_CANDIDATES = (32, 64, 128)
-SWEEP_CANDIDATES = (0, gc.GC_OPT_FUSED_SWEEP, gc.GC_OPT_SPLIT_SWEEP)   # by depth, fused, split
+SWEEP_CANDIDATES = (0, gc.GC_OPT_SPLIT_SWEEP)   # fused (the default), split
 
 
 def autotune(items, tiles=TILE_CANDIDATES, periods=PERIOD_CANDIDATES, sweeps=SWEEP_CANDIDATES,

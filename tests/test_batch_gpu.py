@@ -154,9 +154,9 @@ def test_batch_larger_than_one_launch_grid(torch_cuda):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("flags", [0, gc.GC_OPT_FUSED_SWEEP, gc.GC_OPT_FUSED_SWEEP | gc.GC_OPT_SWEEP_GRAPH,
+@pytest.mark.parametrize("flags", [0, gc.GC_OPT_SPLIT_SWEEP, gc.GC_OPT_SPLIT_SWEEP | gc.GC_OPT_SWEEP_GRAPH,
                                    gc.GC_OPT_WAVE_FIRST | gc.GC_OPT_SWEEP_GRAPH],
-                         ids=["plain", "fused", "fused-graph", "wave-graph"])
+                         ids=["plain", "split", "split-graph", "wave-graph"])
 def test_batch_groups_and_variants(torch_cuda, orc, flags):
     """Four 384x288x16 graphs mixed with small graphs; every solver variant
     (split or fused sweeps, direct launches or a captured round; the batch

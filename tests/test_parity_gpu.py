@@ -285,7 +285,7 @@ def test_repeat_solves_identical(torch_cuda, orc):
 _VARIANTS = {"wave-first": gc.GC_OPT_WAVE_FIRST, "fused": gc.GC_OPT_FUSED_SWEEP,
              "split": gc.GC_OPT_SPLIT_SWEEP, "graph": gc.GC_OPT_SWEEP_GRAPH,
              "fixed-period": gc.GC_OPT_FIXED_PERIOD,
-             "fused-wave-first": gc.GC_OPT_FUSED_SWEEP | gc.GC_OPT_WAVE_FIRST,
+             "split-wave-first": gc.GC_OPT_SPLIT_SWEEP | gc.GC_OPT_WAVE_FIRST,
              "lists-split": gc.GC_OPT_LISTS | gc.GC_OPT_SPLIT_SWEEP,
              "lists-fused": gc.GC_OPT_LISTS | gc.GC_OPT_FUSED_SWEEP,
              "lists-graph": gc.GC_OPT_LISTS | gc.GC_OPT_SWEEP_GRAPH}
@@ -318,7 +318,7 @@ def test_solver_variants_parity(torch_cuda, orc, variant, name, cost, params):
 
 
 @pytest.mark.parametrize("passes", [-1, 1, 2, 5])
-@pytest.mark.parametrize("flags", [0, gc.GC_OPT_FUSED_SWEEP, gc.GC_OPT_SWEEP_GRAPH],
+@pytest.mark.parametrize("flags", [gc.GC_OPT_SPLIT_SWEEP, 0, gc.GC_OPT_SWEEP_GRAPH],
                          ids=["split", "fused", "graph"])
 @pytest.mark.parametrize("name,cost,params", list(_variant_cases()), ids=[c[0] for c in _variant_cases()])
 def test_relabel_pass_caps_parity(torch_cuda, orc, passes, flags, name, cost, params):
@@ -348,7 +348,7 @@ def test_relabel_pass_caps_large_full_size(torch_cuda, passes):
     assert (lab.cpu().numpy() == lab0.cpu().numpy()).all()
 
 
-@pytest.mark.parametrize("variant", ["fused", "fused-wave-first", "lists-split", "lists-fused"])
+@pytest.mark.parametrize("variant", ["split", "split-wave-first", "lists-split", "lists-fused"])
 def test_solver_variants_mid_full_size(torch_cuda, orc, variant):
     pr = sg.make_pair(sg.MID, (2, 1))
     p = gc.problem(sg.MID.w, sg.MID.h, sg.MID.m, sg.MID.cap, 1, 1023)
@@ -421,7 +421,7 @@ def test_approx_level2_parity(torch_cuda, orc, b, steps, spec, seed):
     assert (labels.cpu().numpy() == ref_lab).all()
 
 
-_SKIN_OPTS = {"default": None, "fused": gc.GcSolveOpts(flags=gc.GC_OPT_FUSED_SWEEP),
+_SKIN_OPTS = {"default": None, "split": gc.GcSolveOpts(flags=gc.GC_OPT_SPLIT_SWEEP),
               "wave-first-p5": gc.GcSolveOpts(relabel_period=5, flags=gc.GC_OPT_WAVE_FIRST),
               "captured": gc.GcSolveOpts(flags=gc.GC_OPT_SWEEP_GRAPH)}
 
@@ -519,7 +519,7 @@ def test_approx_level2_blocks_alone_are_exact(torch_cuda, orc, b):
 
 _WARM_OPTS = {"default": None,
               "wave-first": gc.GcSolveOpts(flags=gc.GC_OPT_WAVE_FIRST),
-              "fused": gc.GcSolveOpts(flags=gc.GC_OPT_FUSED_SWEEP),
+              "captured": gc.GcSolveOpts(flags=gc.GC_OPT_SWEEP_GRAPH),
               "period-13-split": gc.GcSolveOpts(relabel_period=13, flags=gc.GC_OPT_SPLIT_SWEEP)}
 
 
