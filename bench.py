@@ -212,7 +212,7 @@ def bench_batch(args, gc, sg, torch):
                 tune.append(rt.make_item(i, spec, pair))
         t = time.perf_counter()
         best_lanes, trials_l = rt.autotune(tune, stream=stream, use_graph=True)
-        best_eng, trials_e = rt.autotune(tune, tiles=((8, 8, 16), (16, 16, 8)), periods=(24, 32, 48),
+        best_eng, trials_e = rt.autotune(tune, tiles=((8, 8, 16), (16, 16, 8)), periods=(0, 24, 32, 48),
                                          sweeps=(0,), stream=stream, extra_flags=gc.GC_OPT_BATCH_MERGED)
         tune_s = time.perf_counter() - t
         _log(f"batch: autotuned over {len(trials_l) + len(trials_e)} candidates in {tune_s:.1f} s")
@@ -259,7 +259,8 @@ def bench_batch(args, gc, sg, torch):
                 "p50_ms": _pct(times, 50), "p99_ms": _pct(times, 99)}
 
     def opts_of(o):
-        return {"tile": [o.tile_w, o.tile_h, o.tile_j], "relabel_period": o.relabel_period,
+        return {"tile": [o.tile_w, o.tile_h, o.tile_j],
+                "relabel_period": o.relabel_period or "by depth (24 below 32 levels, else 32)",
                 "sweep": "split" if o.flags & gc.GC_OPT_SPLIT_SWEEP else "fused"}
 
     return {"workload": f"{n} seeded pairs uniform over 320x240x16, 384x288x16, 450x375x64, "
@@ -408,7 +409,7 @@ def bench_serving(args, gc, sg, torch, rate, n_req):
     pools = {s: [(sg.spec_like(sg.MID, *s), sg.make_pair(sg.spec_like(sg.MID, *s), (5, k, i)))
                  for i in range(2)] for k, s in enumerate(sg.SERVE_SHAPES)}
     reqs = rt.poisson_requests(n_req, rate, sg.SERVE_SHAPES, 2, seed=5)
-    opts = gc.GcSolveOpts(relabel_period=32)
+    opts = gc.GcSolveOpts()                  # relabel period and pass cap by depth
     _log(f"serving: {len(reqs)} requests at {rate:g}/s")
     done, wall, srv = rt.serve(reqs, pools, int(args.serve_budget_gb * 1e9), opts,
                                progress=lambda k, t: _log(f"serving: {k} done at {t:.1f} s"))

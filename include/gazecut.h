@@ -93,7 +93,8 @@ typedef struct {
 
 /* Solver options; a zero-filled struct selects the defaults. */
 typedef struct {
-    int32_t relabel_period;   /* most push-relabel sweeps between global relabels (default 32) */
+    int32_t relabel_period;   /* most push-relabel sweeps between global relabels (default 24
+                                 when the full problem has fewer than 32 levels, else 32) */
     int32_t max_sweeps;       /* give up with GC_E_NOT_CONVERGED after this many (default 1<<20) */
     int32_t tile_w;           /* BFS tile extent along x (default 8)           */
     int32_t tile_h;           /* along y (default 8)                          */

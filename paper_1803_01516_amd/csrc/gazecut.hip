@@ -1990,11 +1990,21 @@ k_block_cut(Graph s, const int32_t *__restrict__ coarse_labels, int b)
 constexpr int kRelabelPassesDeep = 16;
 constexpr int kRelabelPassesShallow = 8;
 
+// Depth (levels of the full graph) from which a graph counts as deep for
+// the relabel period, the relaxation's in-tile rounds and the early-stopped
+// relabels' pass cap.
+constexpr int kDeepLevels = 32;
+
 // Sweeps between global relabels (the first period; later ones adapt below
-// it).  With relabels stopped early a shorter period pays: 32 against 64
-// was 10-20 % faster on 320x240x16 and 384x288x16 (grey, colour, penalties
-// 1 and 2) and 640x480x64 pairs, within noise on 450x375x64.
-constexpr int kRelabelPeriod = 32;
+// it), 24 below kDeepLevels levels and 32 from there on.  With relabels
+// stopped early a shorter period pays: 32 against 64 was 10-20 % faster on
+// 320x240x16 and 384x288x16 (grey, colour, penalties 1 and 2) and
+// 640x480x64 pairs, within noise on 450x375x64; once shallow relabels
+// stopped after 8 passes, 24 against 32 was 2-5 % faster on five sets of
+// 16-level grey pairs and 12 % on colour pairs, even on 24 and 31 levels,
+// and 6 % slower on 450x375x64 (20 and 16: slower again).
+constexpr int kRelabelPeriodShallow = 24;
+constexpr int kRelabelPeriodDeep = 32;
 
 // Only a solve's first relabels may stop early.  Heights set by an early-
 // stopped relabel need not be a valid labelling, so flow may circulate from
@@ -2008,7 +2018,7 @@ struct Opts {
 
 Opts resolve(const gc_solve_opts *o)
 {
-    Opts r{kRelabelPeriod, 1 << 20, 8, 8, 16, 0, 0, 0};
+    Opts r{0, 1 << 20, 8, 8, 16, 0, 0, 0};  // period 0: by depth (base_period)
     if (o) {
         if (o->relabel_period > 0) r.period = o->relabel_period;
         if (o->max_sweeps > 0) r.max_sweeps = o->max_sweeps;
@@ -2060,10 +2070,6 @@ int64_t relax_tiles(const Graph &s, const Opts &o)
     if (s.cw) return (int64_t)((s.W + kSkinTile - 1) / kSkinTile) * ((s.H + kSkinTile - 1) / kSkinTile);
     return (int64_t)((s.W + o.tw - 1) / o.tw) * ((s.H + o.th - 1) / o.th) * ((s.J + o.tj - 1) / o.tj);
 }
-
-// Depth (levels of the full graph) from which a graph counts as deep for
-// the relaxation's in-tile rounds and the early-stopped relabels' pass cap.
-constexpr int kDeepLevels = 32;
 
 // In-tile rounds of a relaxation pass when the options leave them at 0:
 // 4 below kDeepLevels levels, 8 from there on and in compact skins.
@@ -2155,12 +2161,19 @@ inline unsigned list_grid(int64_t items, unsigned resident)
 // pairs this cut 20 % of the sweeps at the same number of global relabels.
 constexpr int kMinPeriod = 16;
 
-inline int period_for_round(const Opts &o, int round, int max_active_height)
+__host__ __device__ inline int base_period(int opt_period, const Graph &s)
 {
-    if (round == 0 || (o.flags & GC_OPT_FIXED_PERIOD)) return o.period;
+    return opt_period > 0 ? opt_period : s.Jf < kDeepLevels ? kRelabelPeriodShallow : kRelabelPeriodDeep;
+}
+
+__host__ __device__ inline int period_for_round(int opt_period, int flags, const Graph &s, int round,
+                                                int max_active_height)
+{
+    const int base = base_period(opt_period, s);
+    if (round == 0 || (flags & GC_OPT_FIXED_PERIOD)) return base;
     const int q = 2 * max_active_height;
-    const int lo = o.period < kMinPeriod ? o.period : kMinPeriod;
-    return q < lo ? lo : q > o.period ? o.period : q;
+    const int lo = base < kMinPeriod ? base : kMinPeriod;
+    return q < lo ? lo : q > base ? base : q;
 }
 
 // The optional wave-front pass runs once, before the first global relabel
@@ -2757,7 +2770,7 @@ static int solve_graph(gc_graph *g, const Opts &opt, gc_solve_stats *stats, hipS
         st_local.pushes = (int64_t)hr.pushes;
         st_local.active_visits = (int64_t)hr.visits;
         if (hr.active == 0) break;
-        const int period = period_for_round(opt, round, hr.max_height);
+        const int period = period_for_round(opt.period, opt.flags, s, round, hr.max_height);
         if (st_local.sweeps >= opt.max_sweeps) { status = GC_E_NOT_CONVERGED; break; }
         if (use_graph) {
             if ((rc = replay_period(s, period, fused, listed, st)) != GC_OK) return rc;
@@ -2964,13 +2977,6 @@ GC_API int approx_level2_cut(gc_graph *skin, const int32_t *cost, const int32_t 
 
 namespace {
 
-__device__ inline int batch_period(const BatchDev *T, int round, int max_height)
-{
-    if (round == 0 || (T->flags & GC_OPT_FIXED_PERIOD)) return T->period;
-    const int q = 2 * max_height;
-    const int lo = T->period < kMinPeriod ? T->period : kMinPeriod;
-    return q < lo ? lo : q > T->period ? T->period : q;
-}
 
 __global__ void __launch_bounds__(kSlots)
 k_batch_phase(BatchDev *T)
@@ -3037,7 +3043,7 @@ k_batch_phase(BatchDev *T)
                 c.status = c.active == 0 ? GC_OK : GC_E_NOT_CONVERGED;
                 c.done_step = T->step;
             } else {
-                c.period = batch_period(T, c.round, c.max_height);
+                c.period = period_for_round(T->period, T->flags, s, c.round, c.max_height);
                 c.sweep = 0;
                 nx = c.fused ? BP_SWEEP : BP_PUSH;
             }

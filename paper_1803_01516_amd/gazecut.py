@@ -376,22 +376,15 @@ def approx_level2_cut(skin: Graph, cost, coarse_labels, labels, result, stream=N
            "approx_level2_cut")
 
 
-# Relabel period of the two solves of an approximate cut when the caller
-# gives no options: the delegate-point graph and the thin skin are shallow,
-# their flow settles within a few dozen sweeps, and 32 measured 22-28 %
-# faster level-1 cuts on 384x288x16 than the exact solve's default of 64
-# (16 and 24 were slower again).  The cut itself does not depend on it.
-APPROX_RELABEL_PERIOD = 32
-
-
 def approx_solve_opts(p: GcProblem) -> GcSolveOpts:
-    """Options of the coarse and skin solves of the approximations: relabel
-    period APPROX_RELABEL_PERIOD, and relabels that stop early after the
-    pass count of the full problem's depth (16 from 32 levels on), which the
-    coarse graph, with fewer levels but the same lateral structure, needs too
-    (with 8, level 1 b = 2 on 450x375x64 took 27.6 instead of 15.0 ms)."""
-    return GcSolveOpts(relabel_period=APPROX_RELABEL_PERIOD,
-                       relabel_passes=16 if p.labels - 1 >= 32 else 0)
+    """Options of the coarse and skin solves of the approximations when the
+    caller gives none: the relabel period and early-stop pass count of the
+    full problem's depth (32 sweeps and 16 passes from 32 levels on, else 24
+    and 8).  The coarse graph of a deep problem has fewer levels but the same
+    lateral structure and needs them too: with 8 passes, level 1 b = 2 on
+    450x375x64 took 27.6 instead of 15.0 ms.  The cuts do not depend on them."""
+    deep = p.labels - 1 >= 32
+    return GcSolveOpts(relabel_period=32 if deep else 24, relabel_passes=16 if deep else 8)
 
 
 def approx_level1(p: GcProblem, cost, block: int, opts: GcSolveOpts | None = None, stream=None,

@@ -88,7 +88,7 @@ def release(item: Item):
 # ---------------------------------------------------------------------------
 
 TILE_CANDIDATES = ((8, 8, 16), (16, 8, 16), (8, 8, 32), (16, 16, 8))
-PERIOD_CANDIDATES = (32, 64, 128)
+PERIOD_CANDIDATES = (0, 24, 32, 64)   # 0: by depth
 SWEEP_CANDIDATES = (0, gc.GC_OPT_SPLIT_SWEEP)   # fused (the default), split
 
 
