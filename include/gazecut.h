@@ -99,11 +99,14 @@ typedef struct {
     int32_t tile_w;           /* BFS tile extent along x (default 8)           */
     int32_t tile_h;           /* along y (default 8)                          */
     int32_t tile_j;           /* along the depth-number axis (default 16)     */
-    int32_t local_iters;      /* max in-tile relaxation rounds per pass (default 4 below 32 levels, else 8) */
+    int32_t local_iters;      /* max in-tile relaxation rounds per pass (default 4 below 32
+                                 stored levels, else 8; 8 in a compact thin skin) */
     int32_t flags;            /* GC_OPT_* bits                                */
     int32_t relabel_passes;   /* most relaxation passes of a global relabel that
-                                 does not end the solve (default 8 below 32
-                                 levels, 16 from there on; < 0: none stops early;
+                                 does not end the solve (default 8 when the full
+                                 problem has fewer than 32 levels, 16 from there
+                                 on, a thin skin following its full problem;
+                                 < 0: none stops early;
                                  only a solve's first 24 relabels may).  Stopped early, its heights bound the
                                  distances from above near the deficits and are
                                  INF farther away (those nodes wait for the next
@@ -112,7 +115,8 @@ typedef struct {
                                  solve still ends on an exact one. */
 } gc_solve_opts;
 
-/* gc_solve_opts.flags: bracket one launch in 16 of each kernel class (chosen by a hash
+/* gc_solve_opts.flags: bracket one launch in 16 (one in 4 on graphs of 4 M
+ * nodes or more) of each kernel class (chosen by a hash
  * of its number, so the sample does not alias with the sweep periods) with a
  * pair of hipEvents on the solve stream; gc_solve_stats then holds every
  * class's launch count and its device time estimated as the mean of the timed
