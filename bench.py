@@ -433,8 +433,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(pairs shard across GPUs with no exchange; see DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the solver has no multi-GPU path "
+              "(independent pairs would shard across GPUs with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     import torch
