@@ -1670,13 +1670,27 @@ k_zero_slots(Slot *slots, int what)
 
 // Folds the slots: what 0 -> hdr->active, 1 -> hdr->pushes,
 // 2 -> result[0] = energy, result[1] = flow (sink capacity + c0 - deficits),
-// 3 -> hdr->tcap, hdr->c0 after a build.
+// 3 -> hdr->tcap, hdr->c0 after a build, 4 -> hdr->seeded after a warm
+// start, 5 -> 0 and 1 after a termination count, whose slots it then clears
+// for the next count.
 __global__ void __launch_bounds__(kSlots)
-k_fold_slots(const Slot *slots, DevHeader *hdr, int what, int64_t *result)
+k_fold_slots(Slot *slots, DevHeader *hdr, int what, int64_t *result)
 {
     static_assert(kSlots == kBlock, "one thread per slot");
-    const Slot &sl = slots[threadIdx.x];
-    if (what == 0) {
+    Slot &sl = slots[threadIdx.x];
+    if (what == 5) {
+        const int a0 = sl.active, m0 = sl.max_height;
+        const int a = block_sum(a0);
+        __syncthreads();
+        const int m = block_max(m0);
+        __syncthreads();
+        const unsigned long long p = block_sum(sl.pushes);
+        __syncthreads();
+        const unsigned long long v = block_sum(sl.visits);
+        if (threadIdx.x == 0) { hdr->active = a; hdr->max_height = m; hdr->pushes = p; hdr->visits = v; }
+        sl.active = 0;                        // each thread clears the slot it read
+        sl.max_height = 0;
+    } else if (what == 0) {
         int a = block_sum(sl.active);
         __syncthreads();
         int m = block_max(sl.max_height);
@@ -2379,10 +2393,10 @@ int relax_to_fixpoint(const Graph &s, int mode, const Opts &o, Launcher &L, int 
             }
         }
         if (count_active) {
-            hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, L.st, s.slots, 1);
+            // the count's slots are clear: the solve clears them before its
+            // first count and every fold after a count clears them again
             L.run(GC_K_OTHER, k_count_active<Graph>, dim3(grid), s);
-            hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, L.st, s.slots, s.hdr, 0, nullptr);
-            hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, L.st, s.slots, s.hdr, 1, nullptr);
+            hipLaunchKernelGGL(k_fold_slots, dim3(1), dim3(kSlots), 0, L.st, s.slots, s.hdr, 5, nullptr);
         }
         if (!hip_ok(hipGetLastError())) return GC_E_HIP;
         const size_t bytes = count_active ? sizeof(HeaderRead) : sizeof(h->flags);
@@ -2738,6 +2752,7 @@ static int solve_graph(gc_graph *g, const Opts &opt, gc_solve_stats *stats, hipS
     const bool use_graph = st != nullptr && (opt.flags & GC_OPT_SWEEP_GRAPH) != 0 && !L.timing;
     int status = GC_OK;
     int batch_hint = 4;
+    hipLaunchKernelGGL(k_zero_slots, dim3(1), dim3(kSlots), 0, st, s.slots, 1);   // the counts' slots
     for (int round = 0;; ++round) {
         // wave-front pass along the columns, then exact global relabelling:
         // BFS distance to the deficit nodes
