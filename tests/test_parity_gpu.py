@@ -144,6 +144,35 @@ def test_solve_parity_cost_volumes(torch_cuda, orc, name, cost, params):
     _check_against_oracle(orc, cost, lab, energy, flow, params)
 
 
+@pytest.mark.parametrize("spec,seed,flags", [(sg.MID, (2, 3), 0), (sg.MID, (2, 3), gc.GC_OPT_SPLIT_SWEEP),
+                                             (dataclasses.replace(sg.LARGE, w=120, h=90), (3, 4), 0)],
+                         ids=["mid-fused", "mid-split", "deep-120x90x64"])
+def test_second_solve_of_a_solved_graph(torch_cuda, orc, spec, seed, flags):
+    """A solved graph solved again, without a rebuild, holds a maximum
+    preflow already: the second solve ends on its first (exact) relabel with
+    no sweep and the same cut, which also checks that every termination
+    count of the first solve left its reduction slots clear."""
+    torch = torch_cuda
+    pr = sg.make_pair(spec, seed)
+    p = gc.problem(spec.w, spec.h, spec.m, spec.cap, 1, spec.inhibit)
+    L = torch.from_numpy(pr.left).cuda()
+    R = torch.from_numpy(pr.right).cuda()
+    cost = torch.empty((spec.m, spec.h, spec.w), dtype=torch.int32, device="cuda")
+    gc.stereo_cost_volume(L, R, p, cost)
+    g = gc.graph_build(p, cost, gc.alloc_workspace(p))
+    o = gc.GcSolveOpts(flags=flags)
+    st1 = gc.maxflow_solve(g, o)
+    st2 = gc.maxflow_solve(g, o)
+    assert st1.active_last == 0 and st2.active_last == 0
+    assert st2.sweeps == 0 and st2.global_relabels == 1
+    lab = torch.empty((spec.h, spec.w), dtype=torch.int32, device="cuda")
+    res = torch.zeros(2, dtype=torch.int64, device="cuda")
+    gc.extract_labels(g, cost, lab, res)
+    energy, flow = res.cpu().tolist()
+    _check_against_oracle(orc, cost.cpu().numpy(), lab.cpu().numpy(), energy, flow,
+                          (1, spec.inhibit, 1, spec.inhibit))
+
+
 def test_empty_problem(torch_cuda):
     p = gc.problem(0, 0, 8, 20, 1, 1023)
     ws = torch_cuda.empty(max(256, gc.footprint_bytes(p)), dtype=torch_cuda.uint8, device="cuda")
